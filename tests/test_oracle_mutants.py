@@ -1,0 +1,148 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check a pin catches each.
+
+Each mutant patches one oracle function with a small, realistic slip (a dropped
+term, a wrong sign, a wrong index, a transposed operand, an unstable sort, a
+wrong eigenvector, a non-cyclic axis order, grid points on interval edges) and
+runs the pins of tests/test_oracle_pins.py against it: at least one must fail.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import vgpr_oracle as O
+from tests import test_oracle_pins as pins
+
+_orig_posterior = O.gp_posterior
+_orig_kernel = O.se_kernel
+_orig_frame = O.local_frame
+_orig_grid = O.query_grid
+
+
+def _posterior_no_noise(x, f, xq, sf2, ell, sn, full=False):
+    return _orig_posterior(x, f, xq, sf2, ell, 0.0 * np.asarray(sn) + 1e-14, full)
+
+
+def _posterior_no_centering(x, f, xq, sf2, ell, sn, full=False):
+    x = np.asarray(x, float)
+    f = np.asarray(f, float)
+    K = O.se_kernel(x, x, sf2, ell) + np.eye(len(x)) * sn
+    Ks = O.se_kernel(x, xq, sf2, ell)
+    L = scipy.linalg.cholesky(K, lower=True)
+    mean = Ks.T @ scipy.linalg.cho_solve((L, True), f)  # zero prior mean in world coordinates
+    V = scipy.linalg.solve_triangular(L, Ks, lower=True)
+    var = sf2 - (V * V).sum(0)
+    if full:
+        return mean, var, O.se_kernel(xq, xq, sf2, ell) - V.T @ V
+    return mean, var
+
+
+def _posterior_sign_slip(x, f, xq, sf2, ell, sn, full=False):
+    r = _orig_posterior(x, f, xq, sf2, ell, sn, full)
+    mu = np.mean(f)
+    return (2 * mu - r[0],) + tuple(r[1:])
+
+
+def _posterior_var_plus(x, f, xq, sf2, ell, sn, full=False):
+    r = list(_orig_posterior(x, f, xq, sf2, ell, sn, full))
+    r[1] = 2 * sf2 - r[1]  # K** + K*^T K^-1 K*
+    return tuple(r)
+
+
+def _kernel_missing_half(A, B, sf2, ell):
+    return _orig_kernel(A, B, sf2, ell / np.sqrt(2.0))  # exp(-d^2 / l^2)
+
+
+def _kernel_transposed(A, B, sf2, ell):
+    K = _orig_kernel(A, B, sf2, ell)
+    if K.shape[0] == K.shape[1]:
+        return K
+    # a transposed operand reaching the cross-covariance: rows and columns swap roles
+    return _orig_kernel(B[: len(A)] if len(B) >= len(A) else np.resize(B, A.shape), A, sf2, ell).T
+
+
+def _frame_largest_eigvec(P):
+    fr = _orig_frame(P)
+    P = np.asarray(P, float)
+    D = P - P.mean(0)
+    w, V = np.linalg.eigh(D.T @ D / len(P))
+    v = V[:, 2]
+    a = int(np.argmax(np.abs(v)))
+    fr.axis, fr.params, fr.normal = a, O.PARAM_AXES[a], v
+    return fr
+
+
+def _frame_signed_angle(P):
+    fr = _orig_frame(P)
+    a = int(np.argmax(fr.normal))  # forgets |v|: a negative normal component never wins
+    fr.axis, fr.params = a, O.PARAM_AXES[a]
+    return fr
+
+
+def _grid_edges(ku, kw, s, nq):
+    g = _orig_grid(ku, kw, s, nq)
+    S = float(np.float32(s))
+    return g - 0.5 * S / nq
+
+
+def _unstable_voxelize(xyz, s, frame_offsets=None):
+    vox = _orig_voxelize(xyz, s, frame_offsets)
+    perm = vox["perm"].copy()
+    for o, c in zip(vox["offsets"], vox["counts"]):
+        perm[o:o + c] = perm[o:o + c][::-1]
+    vox["perm"] = perm
+    return vox
+
+
+_orig_voxelize = O.voxelize
+_non_cyclic = {0: (1, 2), 1: (0, 2), 2: (0, 1)}
+
+PIN_TESTS = [
+    lambda: pins.test_posterior_n1_closed_form(),
+    lambda: pins.test_posterior_n2_closed_form(),
+    lambda: pins.test_posterior_vs_mpmath_50_digits(),
+    lambda: pins.test_posterior_vs_explicit_inverse(),
+    lambda: pins.test_interpolation_as_noise_vanishes(),
+    lambda: pins.test_variance_bounds_and_monotone_in_data(),
+    lambda: pins.test_far_field_returns_prior(),
+    lambda: pins.test_plane_normal_to_value_axis_is_exact(),
+    lambda: pins.test_voxel_outputs_layout_and_status(),
+    lambda: pins.test_cyclic_relabelling_equivariance(),
+    lambda: pins.test_grid_exact_small_case(),
+    lambda: pins.test_grid_interval_centres(-3, 7, 0.2, 9),
+    lambda: pins.test_keys_match_bruteforce_grouping(),
+    lambda: pins.test_multi_frame_equals_concatenation(),
+    lambda: [pins.test_frame_axis_of_known_planes(n, a) for n, a in
+             [([0, 0, 1], 2), ([1, 0, 0], 0), ([0, 1, 0], 1), ([0.2, -0.3, 1.0], 2), ([1.0, 0.5, -0.4], 0),
+              ([-0.1, 0.9, 0.6], 1)]],
+]
+
+
+def _caught():
+    for t in PIN_TESTS:
+        try:
+            t()
+        except (AssertionError, np.linalg.LinAlgError, ValueError, IndexError):
+            return True
+    return False
+
+
+def test_pins_green_on_unmodified_oracle():
+    assert not _caught()
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("noise term dropped", "gp_posterior", _posterior_no_noise),
+    ("prior mean not subtracted", "gp_posterior", _posterior_no_centering),
+    ("sign slip in the mean", "gp_posterior", _posterior_sign_slip),
+    ("variance term added", "gp_posterior", _posterior_var_plus),
+    ("factor 2 missing in 2 l^2", "se_kernel", _kernel_missing_half),
+    ("transposed cross-covariance", "se_kernel", _kernel_transposed),
+    ("largest eigenvector", "local_frame", _frame_largest_eigvec),
+    ("signed angle", "local_frame", _frame_signed_angle),
+    ("grid on interval edges", "query_grid", _grid_edges),
+    ("unstable point order", "voxelize", _unstable_voxelize),
+    ("non-cyclic parameter axes", "PARAM_AXES", _non_cyclic),
+])
+def test_pins_catch_mutant(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(O, target, mutant)
+    assert _caught(), f"no pin caught the mutant: {name}"
