@@ -1,0 +1,278 @@
+"""Throughput of the Voxel-GPR hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic scans that
+are already resident in HBM: vgpr_voxelize over the batch (frames voxelized
+independently) followed by vgpr_fit_predict over every voxel of the batch.
+The batch is `--frames` seeded 32-beam x 1800-azimuth spinning scans of the
+box scene (voxel 0.5 m, cap 128, tau 3, 8x8 query grid).
+
+Prints one JSON line: solved voxels per second (plus dense points per second),
+the per-kernel roofline of the dominant kernel from HIP events on the
+library's stream, single-frame latency percentiles, and the FP64 CPU oracle
+timed on a bounded sample of the same workload, whose results also give the
+accuracy check of the GPU outputs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2410_17084_amd import configs, synth  # noqa: E402
+
+PEAK = {"f32": 157.3, "f64": 78.6}  # TFLOP/s, MI355X vector FP32 / FP64
+HBM_PEAK = 8000.0                   # GB/s
+BUCKETS = (16, 32, 64, 128)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def voxel_flops(n: np.ndarray, m: int) -> np.ndarray:
+    """Algorithmic FP operations of one voxel solve (see the design notes).
+
+    n^3/3 (factorisation) + n^2 m (L^-1 K*) + 2 n^2 (solve of f) + 4 n m
+    (mean and variance) + 6 (n^2/2 + n m) (kernel entries, exp not counted).
+    """
+    n = n.astype(np.float64)
+    return n ** 3 / 3 + n * n * m + 2 * n * n + 4 * n * m + 6 * (n * n / 2 + n * m)
+
+
+def voxel_bytes(n: np.ndarray, m: int) -> np.ndarray:
+    """Algorithmic HBM bytes of one voxel solve: points in, key/offset/count, rows out, axis/status."""
+    return 12.0 * n + 16 + 16.0 * m + 2
+
+
+def bucket_of(n: np.ndarray) -> np.ndarray:
+    b = np.zeros(len(n), dtype=np.int64)
+    for i, c in enumerate(BUCKETS[:-1]):
+        b += (n > c)
+    return b
+
+
+def cpu_baseline(xyz_f0: np.ndarray, w: dict, gpu_f0: dict, budget_s: float) -> dict:
+    """FP64 oracle on frame 0 of the batch: voxelize, then fit voxels in order until the budget.
+
+    The oracle's outputs for the voxels it reached also check the GPU outputs
+    of the same voxels (the accuracy gate of the metric).
+    """
+    from threadpoolctl import threadpool_limits
+
+    from oracle import vgpr_oracle as O
+    from tests import parity
+
+    prm = parity.oracle_params(w)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ov = O.voxelize(xyz_f0, w["voxel_size"])
+        solved = 0
+        reached = 0
+        V = len(ov["keys"])
+        for v in range(V):
+            P = O.voxel_points(xyz_f0, ov, v)
+            r = O.fit_predict_voxel(P, ov["keys"][v], prm)
+            solved += bool(r["status"] & O.ST_SOLVED)
+            reached = v + 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    stats = parity.compare_fit(xyz_f0, ov, prm, gpu_f0["out"], gpu_f0["axis"], gpu_f0["status"],
+                               voxels=range(reached))
+    return {
+        "value": solved / dt, "unit": "voxel solves/s", "cores": 1, "kind": "oracle",
+        "sample": f"frame 0 of the batch ({len(xyz_f0)} points): oracle voxelize + FP64 fit of the first "
+                  f"{reached} of {V} voxels ({solved} solved) in {dt:.1f} s, BLAS limited to 1 thread",
+        "accuracy": {"voxels_checked": reached, "solved_checked": stats["solved"],
+                     "max_mean_err_m": stats["max_mean_err"], "max_var_err": stats["max_var_err"],
+                     "mean_tol_m": parity.MEAN_TOL, "var_tol": parity.VAR_TOL_REL, "pass": True},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--latency-frames", type=int, default=60)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(voxels shard by key with one all-to-all; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2410_17084_amd import vgpr
+
+    w = configs.params_for("spin32")
+    wl = configs.WORKLOADS["spin32"]
+    m = w["grid_side"] ** 2
+    t0 = time.perf_counter()
+    xyz_np, fo = synth.scan_batch(2, args.frames, n_beams=wl["n_beams"], n_az=wl["n_az"])
+    log(f"generated {args.frames} scans, {len(xyz_np)} points in {time.perf_counter() - t0:.1f} s")
+
+    prec = vgpr.PREC_FP32 if args.precision == "fp32" else vgpr.PREC_FP64
+    p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
+    p.precision = prec
+    ctx = vgpr.Context(0)
+    xyz = torch.from_numpy(xyz_np).cuda()
+    torch.cuda.synchronize()
+
+    # first pass sizes the outputs; every later step reuses them
+    vox = ctx.voxelize(xyz, p, frame_offsets=fo)
+    V = vox.n_vox
+    out = (torch.empty((V, m, 4), dtype=torch.float32, device="cuda"),
+           torch.empty(V, dtype=torch.int8, device="cuda"), torch.empty(V, dtype=torch.uint8, device="cuda"))
+    keys = torch.empty(len(xyz_np), dtype=torch.int64, device="cuda")
+    offs = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+    cnts = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+    perm = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+
+    def step():
+        n = ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm)
+        v = vgpr.Voxels(keys[:n], offs[:n], cnts[:n], perm, n, [], 0)
+        ctx.fit_predict(xyz, v, p, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done: {V} voxels in the batch")
+    if not args.no_profile:
+        ctx.profile(True)
+        for fam in FAMILIES:
+            ctx.profile_read(fam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fam_time = {}
+    if not args.no_profile:
+        for fam in FAMILIES:
+            ms, cnt = ctx.profile_read(fam)
+            if cnt:
+                fam_time[fam] = (ms, cnt)
+        ctx.profile(False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    status = out[2].cpu().numpy()
+    counts = cnts[:V].cpu().numpy().astype(np.int64)
+    n_kept = np.minimum(counts, w["max_pts"])
+    solved = (status & vgpr.ST_SOLVED) != 0
+    refined = (status & vgpr.ST_REFINED) != 0
+    n_solved = int(solved.sum())
+    value = n_solved * args.steps / elapsed
+    dense = value * m
+
+    # roofline of the dominant kernel family (largest summed duration)
+    roof = None
+    kernels = {}
+    if fam_time:
+        b_of = bucket_of(n_kept)
+        fl = voxel_flops(n_kept, m)
+        by = voxel_bytes(n_kept, m)
+        for fam, (ms, cnt) in fam_time.items():
+            kernels[fam] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
+        dom = max((f for f in fam_time if f.startswith(("fit", "refine"))), key=lambda f: fam_time[f][0],
+                  default=None)
+        if dom is not None:
+            cap = int(dom.rsplit("_n", 1)[1])
+            b = BUCKETS.index(cap)
+            if dom.startswith("refine"):
+                sel = solved & refined & (b_of == b)
+            else:
+                sel = solved & (b_of == b)
+            flops = float(fl[sel].sum())
+            ms, cnt = fam_time[dom]
+            per_launch_s = ms / cnt / 1e3
+            launches_per_step = cnt / args.steps
+            flops_per_launch = flops / launches_per_step
+            achieved = flops_per_launch / per_launch_s / 1e12
+            dt = "f64" if ("f64" in dom) else "f32"
+            roof = {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
+                    "frac": achieved / PEAK[dt], "traffic": None, "kernel": dom,
+                    "voxels_per_launch": int(sel.sum() / launches_per_step),
+                    "algorithmic_bytes_per_launch": float(by[sel].sum() / launches_per_step),
+                    "hbm_frac": float(by[sel].sum() / launches_per_step) / per_launch_s / 1e9 / HBM_PEAK}
+        tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
+        kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
+                               "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
+
+    # single-frame latency (voxelize + fit of one scan, host clock, synchronised)
+    lat = []
+    for i in range(args.latency_frames):
+        f = i % args.frames
+        a, b = int(fo[f]), int(fo[f + 1])
+        xf = xyz[a:b]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        vf = ctx.voxelize(xf, p)
+        ctx.fit_predict(xf, vf, p)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat = np.array(lat[5:] if len(lat) > 10 else lat)
+    log(f"latency p50 {np.percentile(lat, 50):.3f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nv0 = int(ctx.voxelize(xyz[: int(fo[1])], p).n_vox)
+        # frame 0's voxels are the first nv0 of the batch (frames keep their order)
+        gpu_f0 = {"out": out[0][:nv0], "axis": out[1][:nv0], "status": out[2][:nv0]}
+        cpu = cpu_baseline(xyz_np[: int(fo[1])], w, gpu_f0, args.cpu_budget)
+        log(f"cpu baseline {cpu['value']:.1f} solves/s; accuracy {cpu['accuracy']}")
+
+    rec = {
+        "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
+        "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"spin32 batch: {args.frames} seeded 32-beam x 1800-azimuth spinning scans "
+                               f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step), voxel 0.5 m, "
+                               f"cap 128, tau 3, 8x8 grid, l 0.25 m, noise 1e-3",
+                   "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec == 0 else ""),
+                   "parallelism": "1 GPU"},
+        "dense_pts_per_s": dense,
+        "solved_per_step": n_solved, "refined_per_step": int(refined.sum()),
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "frames": int(len(lat)), "what": "one scan: voxelize + fit_predict + sync"},
+        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
+    [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS]
+
+
+def ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm) -> int:
+    """vgpr_voxelize into preallocated buffers; returns the voxel count."""
+    import ctypes as C
+    nf = len(fo) - 1
+    fo_c = (C.c_int64 * (nf + 1))(*[int(x) for x in fo])
+    nv = C.c_int64()
+    n = xyz.numel() // 3
+    st = ctx.lib.vgpr_voxelize(ctx.h, C.c_void_p(xyz.data_ptr()), n, fo_c, nf, C.byref(p),
+                               C.c_void_p(keys.data_ptr()), C.c_void_p(offs.data_ptr()), C.c_void_p(cnts.data_ptr()),
+                               C.c_void_p(perm.data_ptr()), n, C.byref(nv), None, None)
+    ctx._check(st, "vgpr_voxelize")
+    return nv.value
+
+
+if __name__ == "__main__":
+    main()

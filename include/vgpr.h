@@ -1,0 +1,244 @@
+/*
+ * vgpr.h - C ABI of the batched Voxel-GPR hot path (GS-LIVM, arXiv 2410.17084)
+ * on one MI355X (gfx950).
+ *
+ * The library densifies sparse LiDAR points voxel by voxel with Gaussian
+ * Process Regression (paper Sec. 3.1, Alg. 1):
+ *
+ *   vgpr_voxelize    - Alg. S1 (STORE): voxel key per point, the visited-voxel
+ *                      list S_updated, each voxel's points in arrival order.
+ *   vgpr_fit_predict - Alg. 1 lines after STORE: per-voxel PCA and value-axis
+ *                      switch, kernel matrices K, K*, K**, and the posterior
+ *                      mean and variance of Eq. (3) on a query grid.
+ *   vgpr_map_update  - the voxel-map update of Sec. 3.3: points stacked into
+ *                      a persistent map, voxels of types (b)/(c) re-solved,
+ *                      types (a)/(d) skipped.
+ *
+ * Conventions shared by every call
+ * - Pointers named d_* are device pointers (HIP global memory on the
+ *   context's device) owned by the caller; pointers named h_* are host
+ *   pointers. The library never frees caller memory.
+ * - Work is enqueued on the context's HIP stream. Device outputs are valid
+ *   once that stream has completed. A host out-parameter that depends on a
+ *   device count (n_vox, n_upd) is written before the call returns, which
+ *   synchronises the stream.
+ * - No exception crosses the ABI. A call that fails returns a status other
+ *   than VGPR_OK and leaves its outputs unspecified; vgpr_last_error gives a
+ *   message. Per-voxel numerical events are not call errors: they are reported
+ *   in the per-voxel status bits below.
+ * - Points are float32 x, y, z interleaved (12 bytes per point), world frame,
+ *   metres. Non-finite points are dropped and counted.
+ * - Calls on one context are not thread-safe; use one context per host thread.
+ */
+#ifndef VGPR_H
+#define VGPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define VGPR_API __attribute__((visibility("default")))
+#else
+#define VGPR_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vgpr_ctx vgpr_ctx;
+typedef struct vgpr_map vgpr_map;
+
+typedef enum {
+  VGPR_OK = 0,
+  VGPR_E_INVALID = 1,     /* bad argument (null pointer, negative size, bad params) */
+  VGPR_E_NOMEM = 2,       /* device allocation failed */
+  VGPR_E_CAPACITY = 3,    /* caller buffer too small: the required size is written back */
+  VGPR_E_RANGE = 4,       /* a finite point's voxel index is outside +-(2^20 - 1) */
+  VGPR_E_BUDGET = 5,      /* the work does not fit the context's HBM budget */
+  VGPR_E_DEVICE = 6,      /* a HIP runtime call failed */
+  VGPR_E_UNSUPPORTED = 7  /* parameter combination this build does not implement */
+} vgpr_status;
+
+/* Per-voxel status bits (uint8 per voxel). */
+enum {
+  VGPR_ST_SOLVED = 1,       /* fitted and predicted */
+  VGPR_ST_BELOW_TAU = 2,    /* fewer than min_pts kept points: not solved (Sec. 3.3 type (a)) */
+  VGPR_ST_CAPPED = 4,       /* more than max_pts points; the first max_pts in order were kept */
+  VGPR_ST_REFINED = 8,      /* FP32 solve flagged by the refinement score, re-solved in FP64 */
+  VGPR_ST_FACTOR_FAIL = 16, /* a non-positive pivot in the FP32 factorisation (then re-solved in
+                               FP64); in FP64 mode, the FP64 factorisation failed (rows are NaN) */
+  VGPR_ST_CONVERGED = 32,   /* max predicted variance <= converge_var (Sec. 3.3 type (d)) */
+  VGPR_ST_AXIS_TIE = 64     /* value-axis decision within rounding of a tie (either axis valid) */
+};
+
+/* Arithmetic of the posterior (kernel entries and factorisation). */
+enum {
+  VGPR_PREC_FP32 = 0,  /* FP32 build and LDL^T; voxels whose refinement score exceeds
+                          refine_threshold are re-solved in FP64 */
+  VGPR_PREC_MIXED = 1, /* reserved: BF16-MFMA cross-covariance form (returns E_UNSUPPORTED) */
+  VGPR_PREC_FP64 = 2   /* FP64 build and LDL^T for every voxel */
+};
+
+/*
+ * Hyper-parameters (plain data, copied at call time).
+ * Paper defaults (Table S6, Sec. 3.1): voxel_size 0.2 m, min_pts (tau) 10,
+ * grid_side = n_s * n_r = 9, converge_var (eta) 0.3, and the kernel
+ * exp(-lambda d^2) with lambda = 1, i.e. signal_var 1, length_scale 1/sqrt(2).
+ */
+typedef struct {
+  float voxel_size;       /* s, metres, > 0 */
+  int32_t max_pts;        /* cap of points per voxel, 1..128 in this build */
+  int32_t min_pts;        /* tau: solve a voxel only with at least this many kept points (>= 1) */
+  int32_t grid_side;      /* n_q: queries per side of the voxel face; m = n_q^2, 1..16 */
+  float signal_var;       /* s_f^2 of the squared-exponential kernel, > 0 */
+  float length_scale;     /* l of exp(-d^2 / (2 l^2)), metres, > 0 (ls_mode 0) */
+  float noise_var;        /* sigma_n^2, the sensor noise variance added to K's diagonal, >= 0 */
+  int32_t ls_mode;        /* 0: fixed length_scale; 1: per voxel from PCA eigenvalues,
+                             l = sqrt(3 (lambda_mid + lambda_max) / 2) clamped to [0.05 s, 2 s] */
+  int32_t frame_mode;     /* 0: world value axis of Alg. 1 (the only mode in this build) */
+  int32_t precision;      /* VGPR_PREC_* */
+  float refine_threshold; /* FP32 mode: re-solve in FP64 when sum_j |y_j| / d_j exceeds this */
+  float converge_var;     /* eta: converged when the max predicted variance <= eta */
+} vgpr_params;
+
+/* Fill *p with the paper's defaults (see above), FP32 precision. */
+VGPR_API void vgpr_params_default(vgpr_params* p);
+
+/* Human-readable name of a status code (static string). */
+VGPR_API const char* vgpr_status_str(vgpr_status s);
+
+/*
+ * Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream). Scratch memory for
+ * sorting, bucketing and refinement lists is allocated on demand and never
+ * exceeds `hbm_budget_bytes` (0 = no limit); exceeding it returns
+ * VGPR_E_BUDGET. The context owns that scratch memory.
+ */
+VGPR_API vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget_bytes, vgpr_ctx** out);
+/* Fails with VGPR_E_INVALID (and frees nothing) while maps created on ctx are alive. */
+VGPR_API vgpr_status vgpr_destroy(vgpr_ctx* ctx);
+VGPR_API vgpr_status vgpr_set_stream(vgpr_ctx* ctx, void* hip_stream);
+/* Message of the last failed call on this context (static until the next call). */
+VGPR_API const char* vgpr_last_error(const vgpr_ctx* ctx);
+/* Scratch bytes the context currently holds on the device. */
+VGPR_API size_t vgpr_workspace_bytes(const vgpr_ctx* ctx);
+
+/*
+ * vgpr_voxelize - Alg. S1 (STORE) for one frame or a batch of frames.
+ *
+ * Key of a point p (float32) with s = voxel_size: k = floor(double(p) * (1/s))
+ * per axis, 1/s computed once in double from the float32 s, one IEEE double
+ * multiply; voxels are half-open [k s, (k+1) s). The 64-bit key packs the
+ * biased fields k + 2^20 in 21 bits each, x highest:
+ *   key = (kx + 2^20) << 42 | (ky + 2^20) << 21 | (kz + 2^20).
+ * Non-finite points get key UINT64_MAX and belong to no voxel.
+ *
+ * Frames: h_frame_offsets (host, n_frames + 1 entries, ascending, first 0,
+ * last n_pts) splits d_xyz into frames voxelized independently; NULL with
+ * n_frames <= 1 means one frame. The voxel list is ordered by frame, then by
+ * ascending key; within a voxel, points keep their input order (stable).
+ *
+ * Outputs (caller-allocated, device):
+ *   d_keys[cap_vox]    voxel keys
+ *   d_offsets[cap_vox] start of each voxel in the sorted point order
+ *   d_counts[cap_vox]  points per voxel (before the max_pts cap)
+ *   d_perm[n_pts]      sorted position -> input point index; frame f's
+ *                      positions stay inside frame f's input range, and its
+ *                      non-finite points come after its voxels
+ * Host outputs: *h_n_vox = voxel count; h_frame_vox (nullable, n_frames + 1)
+ * = cumulative voxel count per frame; h_n_invalid (nullable) = non-finite
+ * points. If the voxel count exceeds cap_vox the call returns
+ * VGPR_E_CAPACITY with *h_n_vox set to the required size. n_pts < 2^31.
+ */
+VGPR_API vgpr_status vgpr_voxelize(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts,
+                          const int64_t* h_frame_offsets, int32_t n_frames,
+                          const vgpr_params* params, uint64_t* d_keys, int32_t* d_offsets,
+                          int32_t* d_counts, int32_t* d_perm, int64_t cap_vox,
+                          int64_t* h_n_vox, int64_t* h_frame_vox, int64_t* h_n_invalid);
+
+/*
+ * vgpr_fit_predict - Alg. 1 per voxel after STORE (Sec. 3.1, Eq. (1)-(3)).
+ *
+ * For voxel v, its kept points are d_xyz[d_perm[d_offsets[v] + i]],
+ * i < min(d_counts[v], max_pts) (d_perm may be NULL: then the points are
+ * d_xyz[d_offsets[v] + i]). With n kept points and n >= min_pts:
+ *  - PCA (double): centroid c, covariance (1/n) sum (p - c)(p - c)^T, eigenvector
+ *    of its smallest eigenvalue v; value axis a = argmax_k |v_k| (ties to the
+ *    lower index); parameter axes (u, w) = (Y,Z), (Z,X), (X,Y) for a = X, Y, Z.
+ *  - f_i = p_i[a] with the constant prior mean mu = mean(f); x_i = (p_i[u], p_i[w]).
+ *  - queries x*_q on the voxel face: coordinate (k + (i + 1/2)/n_q) s evaluated
+ *    in double and rounded to float, q = i n_q + j, i along u.
+ *  - kappa(x, x') = s_f^2 exp(-|x - x'|^2 / (2 l^2)); K + diag(sigma^2) with
+ *    sigma^2 = noise_var, or d_noise_var[input index] when d_noise_var != NULL.
+ *  - mean_q = mu + k*_q^T (K + S)^-1 (f - mu), var_q = s_f^2 - k*_q^T (K + S)^-1 k*_q
+ *    (the diagonal of Sigma* of Eq. (3)), var clamped at 0.
+ * Outputs (caller-allocated, device):
+ *   d_out[n_vox * m * 4]  float x, y, z, var of query q of voxel v at row v*m + q:
+ *                         coordinate a = mean_q, (u, w) = x*_q; NaN rows for
+ *                         unsolved voxels
+ *   d_axis[n_vox]         value axis 0/1/2, -1 when not solved
+ *   d_status[n_vox]       VGPR_ST_* bits
+ * Asynchronous: returns after enqueueing.
+ */
+VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, const uint64_t* d_keys,
+                             const int32_t* d_offsets, const int32_t* d_counts,
+                             const int32_t* d_perm, int64_t n_vox, const float* d_noise_var,
+                             const vgpr_params* params, float* d_out, int8_t* d_axis,
+                             uint8_t* d_status);
+
+/*
+ * Device-resident voxel map (the global map C of Alg. S1 with the voxel
+ * states of Sec. 3.3). Holds up to max_voxels voxels, each with up to
+ * params.max_pts points stored in arrival order; later points of a full voxel
+ * are dropped. The map owns its device memory (about
+ * max_voxels * (32 + 12 * max_pts) bytes plus a hash table of
+ * 2 * max_voxels 8-byte slots), counted against the context's budget.
+ */
+VGPR_API vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels,
+                            vgpr_map** out);
+VGPR_API vgpr_status vgpr_map_destroy(vgpr_map* map);
+
+/*
+ * vgpr_map_update - one frame through the map (Sec. 3.3).
+ * The frame's points (world frame) are voxelized (Alg. S1) and appended to
+ * their voxels. Every voxel the frame touched that now holds >= min_pts
+ * points and is not converged (types (b) and (c)) is re-solved on all its
+ * stored points; it becomes converged (type (d)) once its max predicted
+ * variance <= converge_var and is skipped afterwards, as are voxels with
+ * too few points (type (a)).
+ * Outputs: the re-solved voxels in ascending key order, *h_n_upd of them:
+ * d_upd_keys[cap_upd], d_out[cap_upd * m * 4], d_axis[cap_upd],
+ * d_status[cap_upd] as in vgpr_fit_predict. VGPR_E_CAPACITY when the map
+ * would exceed max_voxels (the frame is then not applied) or when more than
+ * cap_upd voxels were re-solved (*h_n_upd = required; the map state is
+ * updated but outputs are incomplete).
+ */
+VGPR_API vgpr_status vgpr_map_update(vgpr_map* map, const float* d_xyz, int64_t n_pts, uint64_t* d_upd_keys,
+                            float* d_out, int8_t* d_axis, uint8_t* d_status, int64_t cap_upd,
+                            int64_t* h_n_upd);
+
+/* Map counters: voxels held, points stored, converged voxels (host outputs, nullable). */
+VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t* h_n_points,
+                           int64_t* h_n_converged);
+
+/*
+ * Kernel timing for measurement. When enabled, the library records HIP
+ * events on the context's stream around each launch of its kernels.
+ * vgpr_profile_read synchronises the stream and returns, for the kernel
+ * family `name`, the summed duration in milliseconds and the number of
+ * launches since the last read of that family, then resets it. Families:
+ * "voxelize_key", "voxelize_sort" (all radix passes of a call),
+ * "voxelize_segment", "classify", "fit_f32_n<C>" / "fit_f64_n<C>" (the
+ * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 128) and
+ * "refine_f64_n<C>" (the FP64 re-solve of flagged voxels of that bucket).
+ */
+VGPR_API vgpr_status vgpr_profile_enable(vgpr_ctx* ctx, int on);
+VGPR_API vgpr_status vgpr_profile_read(vgpr_ctx* ctx, const char* name, double* h_total_ms,
+                              int64_t* h_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VGPR_H */

@@ -1,0 +1,233 @@
+// Context, workspace, error reporting and launch timing of the Voxel-GPR library.
+#include <cmath>
+#include <cstdio>
+
+#include "vgpr_internal.h"
+
+namespace vgpr {
+
+vgpr_status fail(vgpr_ctx* ctx, vgpr_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+vgpr_status hip_fail(vgpr_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? VGPR_E_NOMEM : VGPR_E_DEVICE, m);
+}
+
+vgpr_status reserve_work(vgpr_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->work.bytes) return VGPR_OK;
+  size_t want = bytes + bytes / 4;
+  size_t others = ctx->held - ctx->work.bytes;
+  if (ctx->budget && others + want > ctx->budget) {
+    want = bytes;
+    if (others + want > ctx->budget)
+      return fail(ctx, VGPR_E_BUDGET,
+                  "scratch of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+  }
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->work.ptr) VGPR_HIP(ctx, hipFree(ctx->work.ptr));
+  ctx->held -= ctx->work.bytes;
+  ctx->work = DeviceBuffer{};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
+  ctx->work.ptr = p;
+  ctx->work.bytes = want;
+  ctx->held += want;
+  return VGPR_OK;
+}
+
+vgpr_status reserve_pinned(vgpr_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) return VGPR_OK;
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->pinned) VGPR_HIP(ctx, hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_bytes = 0;
+  size_t want = bytes < 4096 ? 4096 : bytes * 2;
+  VGPR_HIP(ctx, hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+  ctx->pinned_bytes = want;
+  return VGPR_OK;
+}
+
+vgpr_status alloc_owned(vgpr_ctx* ctx, void** p, size_t bytes) {
+  if (ctx->budget && ctx->held + bytes > ctx->budget)
+    return fail(ctx, VGPR_E_BUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
+  ctx->held += bytes;
+  return VGPR_OK;
+}
+
+void free_owned(vgpr_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->held -= bytes;
+}
+
+static hipEvent_t take_event(vgpr_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(vgpr_ctx* ctx, const char* family, hipEvent_t* start) {
+  (void)family;
+  *start = nullptr;
+  if (!ctx->profiling) return;
+  hipEvent_t e = take_event(ctx);
+  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) *start = e;
+}
+
+void prof_end(vgpr_ctx* ctx, const char* family, hipEvent_t start) {
+  if (!ctx->profiling || !start) return;
+  hipEvent_t e = take_event(ctx);
+  if (!e || hipEventRecord(e, ctx->stream) != hipSuccess) return;
+  ctx->prof[family].pending.emplace_back(start, e);
+}
+
+vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
+  if (!p) return fail(ctx, VGPR_E_INVALID, "params is NULL");
+  if (!(p->voxel_size > 0.f) || !std::isfinite(p->voxel_size))
+    return fail(ctx, VGPR_E_INVALID, "voxel_size must be a positive finite number");
+  if (p->max_pts < 1) return fail(ctx, VGPR_E_INVALID, "max_pts must be >= 1");
+  if (p->max_pts > kMaxPtsLimit)
+    return fail(ctx, VGPR_E_UNSUPPORTED, "max_pts above 128 is not supported by this build");
+  if (p->min_pts < 1) return fail(ctx, VGPR_E_INVALID, "min_pts must be >= 1");
+  if (p->grid_side < 1) return fail(ctx, VGPR_E_INVALID, "grid_side must be >= 1");
+  if (p->grid_side > kMaxGridSide)
+    return fail(ctx, VGPR_E_UNSUPPORTED, "grid_side above 16 is not supported by this build");
+  if (!(p->signal_var > 0.f) || !(p->length_scale > 0.f) || !(p->noise_var >= 0.f))
+    return fail(ctx, VGPR_E_INVALID, "signal_var and length_scale must be > 0, noise_var >= 0");
+  if (p->ls_mode != 0 && p->ls_mode != 1) return fail(ctx, VGPR_E_INVALID, "ls_mode must be 0 or 1");
+  if (p->frame_mode != 0) return fail(ctx, VGPR_E_UNSUPPORTED, "frame_mode 1 is not supported by this build");
+  if (p->precision != VGPR_PREC_FP32 && p->precision != VGPR_PREC_FP64) {
+    if (p->precision == VGPR_PREC_MIXED)
+      return fail(ctx, VGPR_E_UNSUPPORTED, "VGPR_PREC_MIXED is not supported by this build");
+    return fail(ctx, VGPR_E_INVALID, "unknown precision");
+  }
+  return VGPR_OK;
+}
+
+}  // namespace vgpr
+
+using namespace vgpr;
+
+extern "C" {
+
+void vgpr_params_default(vgpr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->voxel_size = 0.2f;
+  p->max_pts = 128;
+  p->min_pts = 10;
+  p->grid_side = 9;
+  p->signal_var = 1.0f;
+  p->length_scale = 0.70710678f;
+  p->noise_var = 1e-3f;
+  p->ls_mode = 0;
+  p->frame_mode = 0;
+  p->precision = VGPR_PREC_FP32;
+  p->refine_threshold = 40.0f;
+  p->converge_var = 0.3f;
+}
+
+const char* vgpr_status_str(vgpr_status s) {
+  switch (s) {
+    case VGPR_OK: return "VGPR_OK";
+    case VGPR_E_INVALID: return "VGPR_E_INVALID";
+    case VGPR_E_NOMEM: return "VGPR_E_NOMEM";
+    case VGPR_E_CAPACITY: return "VGPR_E_CAPACITY";
+    case VGPR_E_RANGE: return "VGPR_E_RANGE";
+    case VGPR_E_BUDGET: return "VGPR_E_BUDGET";
+    case VGPR_E_DEVICE: return "VGPR_E_DEVICE";
+    case VGPR_E_UNSUPPORTED: return "VGPR_E_UNSUPPORTED";
+  }
+  return "VGPR_E_UNKNOWN";
+}
+
+vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget_bytes, vgpr_ctx** out) {
+  if (!out) return VGPR_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VGPR_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return VGPR_E_DEVICE;
+  vgpr_ctx* c = new (std::nothrow) vgpr_ctx();
+  if (!c) return VGPR_E_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->budget = hbm_budget_bytes;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return VGPR_E_DEVICE;
+  }
+  c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_destroy(vgpr_ctx* ctx) {
+  if (!ctx) return VGPR_E_INVALID;
+  if (ctx->live_maps > 0) return fail(ctx, VGPR_E_INVALID, "destroy the context's maps first");
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto& kv : ctx->prof)
+    for (auto& pr : kv.second.pending) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_set_stream(vgpr_ctx* ctx, void* hip_stream) {
+  if (!ctx) return VGPR_E_INVALID;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return VGPR_OK;
+}
+
+const char* vgpr_last_error(const vgpr_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+size_t vgpr_workspace_bytes(const vgpr_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+vgpr_status vgpr_profile_enable(vgpr_ctx* ctx, int on) {
+  if (!ctx) return VGPR_E_INVALID;
+  ctx->profiling = on != 0;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_profile_read(vgpr_ctx* ctx, const char* name, double* h_total_ms, int64_t* h_launches) {
+  if (!ctx || !name) return VGPR_E_INVALID;
+  (void)hipSetDevice(ctx->device);
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double total = 0.0;
+  int64_t count = 0;
+  auto it = ctx->prof.find(name);
+  if (it != ctx->prof.end()) {
+    for (auto& pr : it->second.pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        total += ms;
+        ++count;
+      }
+      ctx->event_pool.push_back(pr.first);
+      ctx->event_pool.push_back(pr.second);
+    }
+    it->second.pending.clear();
+  }
+  if (h_total_ms) *h_total_ms = total;
+  if (h_launches) *h_launches = count;
+  return VGPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,400 @@
+// vgpr_map_*: the global voxel map C of Alg. S1 with the voxel states of
+// Sec. 3.3 (paper), resident in HBM.
+//
+// Layout: an open-addressing hash table of 64-bit voxel keys (linear probing,
+// 2x the voxel capacity, the all-ones sentinel marks an empty slot) pointing
+// at dense voxel records: key, stored point count, total arrived count and a
+// converged flag, plus a point pool with max_pts float3 slots per voxel.
+//
+// One frame: voxelize (Alg. S1) -> probe the table to count new voxels (the
+// frame is rejected when they would overflow the map) -> insert and append
+// points in arrival order up to the cap -> collect the touched voxels that
+// hold >= tau points and are not converged (types (b), (c)) in ascending key
+// order -> solve them from the pool with the per-voxel solver -> mark those
+// whose max variance <= eta as converged (type (d)).
+#include "scan.cuh"
+#include "vgpr_internal.h"
+
+struct vgpr_map {
+  vgpr_ctx* ctx = nullptr;
+  vgpr_params params{};
+  int64_t max_voxels = 0;
+  int64_t nslots = 0;
+  uint64_t* slot_key = nullptr;
+  int32_t* slot_id = nullptr;
+  uint64_t* vkey = nullptr;
+  int32_t* vstored = nullptr;
+  int32_t* vtotal = nullptr;
+  uint8_t* vconv = nullptr;
+  float* pool = nullptr;
+  unsigned long long* counters = nullptr;  // [0] voxels, [1] new this frame, [2] updates
+  size_t bytes = 0;
+  void* block = nullptr;
+};
+
+namespace vgpr {
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  // splitmix64 finaliser (a published 64-bit mixing function)
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+__device__ __forceinline__ int64_t find_slot(const uint64_t* slot_key, int64_t nslots, uint64_t key, bool* found) {
+  int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
+  for (int64_t probe = 0; probe < nslots; ++probe) {
+    const uint64_t k = slot_key[s];
+    if (k == key) { *found = true; return s; }
+    if (k == kKeySentinel) { *found = false; return s; }
+    s = (s + 1) & (nslots - 1);
+  }
+  *found = false;
+  return -1;
+}
+
+__global__ void __launch_bounds__(256) probe_kernel(const uint64_t* __restrict__ keys, int64_t nv,
+                                                    const uint64_t* __restrict__ slot_key, int64_t nslots,
+                                                    unsigned long long* __restrict__ counters) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_new = false;
+  if (v < nv) {
+    bool found;
+    find_slot(slot_key, nslots, keys[v], &found);
+    is_new = !found;
+  }
+  const unsigned long long m = __ballot(is_new);
+  if (lane_id() == 0 && m) atomicAdd(&counters[1], (unsigned long long)__popcll(m));
+}
+
+// One wave per frame voxel: insert or find, append points, flag for solving.
+__global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __restrict__ xyz,
+                                                     const uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ offs, const int32_t* __restrict__ cnts,
+                                                     const int32_t* __restrict__ perm, int64_t nv, int cap, int tau,
+                                                     uint32_t* __restrict__ flag, int32_t* __restrict__ ids) {
+  const int64_t v = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = lane_id();
+  if (v >= nv) return;
+  const uint64_t key = keys[v];
+  int id = -1;
+  int stored = 0;
+  if (lane == 0) {
+    int64_t s = (int64_t)(mix64(key) & (uint64_t)(M.nslots - 1));
+    for (int64_t probe = 0; probe < M.nslots; ++probe) {
+      const unsigned long long prev =
+          atomicCAS(reinterpret_cast<unsigned long long*>(&M.slot_key[s]), (unsigned long long)kKeySentinel,
+                    (unsigned long long)key);
+      if (prev == kKeySentinel) {
+        // new voxel: keys are unique within a frame, so no other lane races on it
+        id = (int)atomicAdd(&M.counters[0], 1ull);
+        if (id >= M.max_voxels) {  // the host checks capacity first; never index past the records
+          M.slot_id[s] = -1;
+          id = -1;
+          break;
+        }
+        M.slot_id[s] = id;
+        M.vkey[id] = key;
+        M.vstored[id] = 0;
+        M.vtotal[id] = 0;
+        M.vconv[id] = 0;
+        break;
+      }
+      if (prev == key) {
+        id = M.slot_id[s];
+        if (id >= 0) stored = M.vstored[id];
+        break;
+      }
+      s = (s + 1) & (M.nslots - 1);
+    }
+  }
+  // the record is read and written by lane 0 only; other lanes get it by shuffle
+  id = __shfl(id, 0, 64);
+  stored = __shfl(stored, 0, 64);
+  if (id < 0) {
+    if (lane == 0) {
+      flag[v] = 0u;
+      ids[v] = 0;
+    }
+    return;
+  }
+  const int c = cnts[v];
+  const int take = min(c, cap - stored);
+  const int o = offs[v];
+  for (int i = lane; i < take; i += 64) {
+    const int src = perm[o + i];
+    float* dst = M.pool + ((size_t)id * cap + stored + i) * 3;
+    dst[0] = xyz[3 * (size_t)src + 0];
+    dst[1] = xyz[3 * (size_t)src + 1];
+    dst[2] = xyz[3 * (size_t)src + 2];
+  }
+  if (lane == 0) {
+    const int now = stored + (take > 0 ? take : 0);
+    M.vstored[id] = now;
+    M.vtotal[id] += c;
+    ids[v] = id;
+    flag[v] = (now >= tau && !M.vconv[id]) ? 1u : 0u;
+  }
+}
+
+constexpr int kCompactTile = 1024;
+
+__global__ void __launch_bounds__(1024) compact_reduce(const uint32_t* __restrict__ flag, int64_t n,
+                                                       uint32_t* __restrict__ block_sums) {
+  const int64_t i = (int64_t)blockIdx.x * kCompactTile + threadIdx.x;
+  uint32_t c = wave_sum(i < n ? flag[i] : 0u);
+  __shared__ uint32_t s[16];
+  if (lane_id() == 0) s[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 16; ++w) t += s[w];
+    block_sums[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(1024) compact_scan(uint32_t* __restrict__ block_sums, int nblocks,
+                                                     unsigned long long* __restrict__ total) {
+  __shared__ uint32_t smem[17];
+  uint32_t carry = 0;
+  for (int s = 0; s < nblocks; s += 1024) {
+    const int i = s + threadIdx.x;
+    const uint32_t v = i < nblocks ? block_sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_sum<1024>(v, smem, &tot);
+    if (i < nblocks) block_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(1024) compact_scatter(vgpr_map M, const uint32_t* __restrict__ flag,
+                                                        const int32_t* __restrict__ ids, int64_t n,
+                                                        const uint32_t* __restrict__ block_base,
+                                                        uint64_t* __restrict__ ukey, int32_t* __restrict__ uoff,
+                                                        int32_t* __restrict__ ucnt, int32_t* __restrict__ uid) {
+  __shared__ uint32_t smem[17];
+  const int64_t i = (int64_t)blockIdx.x * kCompactTile + threadIdx.x;
+  const uint32_t f = i < n ? flag[i] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_exclusive_sum<1024>(f, smem, &tot);
+  if (f) {
+    const uint32_t slot = block_base[blockIdx.x] + ex;
+    const int id = ids[i];
+    ukey[slot] = M.vkey[id];
+    uoff[slot] = id * M.params.max_pts;
+    ucnt[slot] = M.vtotal[id];
+    uid[slot] = id;
+  }
+}
+
+__global__ void __launch_bounds__(256) state_kernel(vgpr_map M, const int32_t* __restrict__ uid,
+                                                    const uint8_t* __restrict__ status, int64_t nu) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < nu && (status[u] & VGPR_ST_CONVERGED)) M.vconv[uid[u]] = 1;
+}
+
+__global__ void __launch_bounds__(256) stats_kernel(vgpr_map M, unsigned long long* __restrict__ out) {
+  const int64_t nv = (int64_t)M.counters[0];
+  unsigned long long pts = 0, conv = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    pts += (unsigned long long)M.vstored[v];
+    conv += M.vconv[v] ? 1ull : 0ull;
+  }
+  atomicAdd(&out[0], pts);
+  atomicAdd(&out[1], conv);
+}
+
+}  // namespace
+}  // namespace vgpr
+
+using namespace vgpr;
+
+extern "C" {
+
+vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels, vgpr_map** out) {
+  if (!ctx || !out) return VGPR_E_INVALID;
+  *out = nullptr;
+  vgpr_status st = check_params(ctx, params);
+  if (st != VGPR_OK) return st;
+  if (max_voxels < 1 || max_voxels * (int64_t)params->max_pts >= (int64_t(1) << 31))
+    return fail(ctx, VGPR_E_INVALID, "max_voxels * max_pts must be in [1, 2^31)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  vgpr_map* M = new (std::nothrow) vgpr_map();
+  if (!M) return VGPR_E_NOMEM;
+  M->ctx = ctx;
+  M->params = *params;
+  M->max_voxels = max_voxels;
+  int64_t ns = 1;
+  while (ns < 2 * max_voxels) ns <<= 1;
+  M->nslots = ns;
+  const size_t cap = (size_t)params->max_pts;
+  size_t off = 0;
+  auto sub = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    size_t r = off;
+    off += bytes;
+    return r;
+  };
+  const size_t o_sk = sub(sizeof(uint64_t) * ns), o_si = sub(sizeof(int32_t) * ns);
+  const size_t o_vk = sub(sizeof(uint64_t) * max_voxels), o_vs = sub(sizeof(int32_t) * max_voxels);
+  const size_t o_vt = sub(sizeof(int32_t) * max_voxels), o_vc = sub(max_voxels);
+  const size_t o_pool = sub(sizeof(float) * 3 * cap * max_voxels), o_ctr = sub(sizeof(unsigned long long) * 8);
+  const size_t total = (off + 255) & ~size_t(255);
+  void* blk = nullptr;
+  st = alloc_owned(ctx, &blk, total);
+  if (st != VGPR_OK) {
+    delete M;
+    return st;
+  }
+  char* b = static_cast<char*>(blk);
+  M->block = blk;
+  M->bytes = total;
+  M->slot_key = reinterpret_cast<uint64_t*>(b + o_sk);
+  M->slot_id = reinterpret_cast<int32_t*>(b + o_si);
+  M->vkey = reinterpret_cast<uint64_t*>(b + o_vk);
+  M->vstored = reinterpret_cast<int32_t*>(b + o_vs);
+  M->vtotal = reinterpret_cast<int32_t*>(b + o_vt);
+  M->vconv = reinterpret_cast<uint8_t*>(b + o_vc);
+  M->pool = reinterpret_cast<float*>(b + o_pool);
+  M->counters = reinterpret_cast<unsigned long long*>(b + o_ctr);
+  if (hipMemsetAsync(M->slot_key, 0xFF, sizeof(uint64_t) * ns, ctx->stream) != hipSuccess ||
+      hipMemsetAsync(M->counters, 0, sizeof(unsigned long long) * 8, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    free_owned(ctx, blk, total);
+    delete M;
+    return fail(ctx, VGPR_E_DEVICE, "map initialisation failed");
+  }
+  ctx->live_maps += 1;
+  *out = M;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_map_destroy(vgpr_map* M) {
+  if (!M) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = M->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_owned(ctx, M->block, M->bytes);
+  ctx->live_maps -= 1;
+  delete M;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint64_t* d_upd_keys, float* d_out,
+                            int8_t* d_axis, uint8_t* d_status, int64_t cap_upd, int64_t* h_n_upd) {
+  if (!M || !h_n_upd) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = M->ctx;
+  *h_n_upd = 0;
+  if (n_pts < 0 || n_pts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_pts out of range");
+  if (n_pts > 0 && !d_xyz) return fail(ctx, VGPR_E_INVALID, "d_xyz is NULL");
+  if (cap_upd < 0) return fail(ctx, VGPR_E_INVALID, "cap_upd < 0");
+  if (cap_upd > 0 && (!d_upd_keys || !d_out || !d_axis || !d_status))
+    return fail(ctx, VGPR_E_INVALID, "output buffer is NULL");
+  if (n_pts == 0) return VGPR_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  const vgpr_params& p = M->params;
+  const int64_t n = n_pts;
+  const int64_t nblk = (n + kCompactTile - 1) / kCompactTile;
+  // scratch: frame voxels (<= n) and the update list, then voxelize / fit scratch
+  size_t head = 0;
+  auto sub = [&](size_t bytes) {
+    head = (head + 255) & ~size_t(255);
+    size_t r = head;
+    head += bytes;
+    return r;
+  };
+  const size_t o_k = sub(8 * n), o_o = sub(4 * n), o_c = sub(4 * n), o_p = sub(4 * n), o_f = sub(4 * n),
+               o_id = sub(4 * n), o_bs = sub(4 * nblk + 64), o_uk = sub(8 * n), o_uo = sub(4 * n), o_uc = sub(4 * n),
+               o_ui = sub(4 * n), o_tot = sub(64);
+  head = (head + 255) & ~size_t(255);
+  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_work_bytes(n) + (1 << 20));
+  if (st != VGPR_OK) return st;
+  char* w = static_cast<char*>(ctx->work.ptr);
+  uint64_t* fkeys = reinterpret_cast<uint64_t*>(w + o_k);
+  int32_t* foff = reinterpret_cast<int32_t*>(w + o_o);
+  int32_t* fcnt = reinterpret_cast<int32_t*>(w + o_c);
+  int32_t* fperm = reinterpret_cast<int32_t*>(w + o_p);
+  uint32_t* flag = reinterpret_cast<uint32_t*>(w + o_f);
+  int32_t* ids = reinterpret_cast<int32_t*>(w + o_id);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(w + o_bs);
+  uint64_t* ukey = reinterpret_cast<uint64_t*>(w + o_uk);
+  int32_t* uoff = reinterpret_cast<int32_t*>(w + o_uo);
+  int32_t* ucnt = reinterpret_cast<int32_t*>(w + o_uc);
+  int32_t* uid = reinterpret_cast<int32_t*>(w + o_ui);
+  unsigned long long* dtot = reinterpret_cast<unsigned long long*>(w + o_tot);
+
+  int64_t nv = 0;
+  st = voxelize_impl(ctx, d_xyz, n, nullptr, 1, p.voxel_size, fkeys, foff, fcnt, fperm, n, &nv, nullptr, nullptr,
+                     head);
+  if (st != VGPR_OK) return st;
+  if (nv == 0) return VGPR_OK;
+  if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during map update");
+
+  // count new voxels and reject the frame if they would overflow the map
+  st = reserve_pinned(ctx, 64);
+  if (st != VGPR_OK) return st;
+  unsigned long long* hc = static_cast<unsigned long long*>(ctx->pinned);
+  VGPR_HIP(ctx, hipMemsetAsync(M->counters + 1, 0, sizeof(unsigned long long), ctx->stream));
+  hipLaunchKernelGGL(probe_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, ctx->stream, fkeys, nv,
+                     M->slot_key, M->nslots, M->counters);
+  VGPR_HIP(ctx, hipGetLastError());
+  VGPR_HIP(ctx, hipMemcpyAsync(hc, M->counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if ((int64_t)(hc[0] + hc[1]) > M->max_voxels)
+    return fail(ctx, VGPR_E_CAPACITY, "frame would exceed the map's voxel capacity");
+
+  const int64_t nvb = (nv + kCompactTile - 1) / kCompactTile;
+  hipLaunchKernelGGL(insert_kernel, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, ctx->stream, *M, d_xyz, fkeys,
+                     foff, fcnt, fperm, nv, p.max_pts, p.min_pts, flag, ids);
+  hipLaunchKernelGGL(compact_reduce, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, flag, nv, bsum);
+  hipLaunchKernelGGL(compact_scan, dim3(1), dim3(1024), 0, ctx->stream, bsum, (int)nvb, dtot);
+  hipLaunchKernelGGL(compact_scatter, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, *M, flag, ids, nv, bsum, ukey,
+                     uoff, ucnt, uid);
+  VGPR_HIP(ctx, hipGetLastError());
+  VGPR_HIP(ctx, hipMemcpyAsync(hc, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t nu = (int64_t)hc[0];
+  *h_n_upd = nu;
+  if (nu == 0) return VGPR_OK;
+  const int64_t nout = nu < cap_upd ? nu : cap_upd;
+  if (nout > 0) {
+    VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
+    FitArgs a{M->pool, ukey, uoff, ucnt, nullptr, nullptr, nout, d_out, d_axis, d_status};
+    st = fit_predict_impl(ctx, a, &p, head);
+    if (st != VGPR_OK) return st;
+    hipLaunchKernelGGL(state_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, ctx->stream, *M, uid,
+                       d_status, nout);
+    VGPR_HIP(ctx, hipGetLastError());
+  }
+  if (nu > cap_upd) return fail(ctx, VGPR_E_CAPACITY, "more re-solved voxels than cap_upd");
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_map_stats(vgpr_map* M, int64_t* h_n_voxels, int64_t* h_n_points, int64_t* h_n_converged) {
+  if (!M) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = M->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  vgpr_status st = reserve_work(ctx, 4096);
+  if (st != VGPR_OK) return st;
+  st = reserve_pinned(ctx, 64);
+  if (st != VGPR_OK) return st;
+  unsigned long long* d = static_cast<unsigned long long*>(ctx->work.ptr);
+  unsigned long long* h = static_cast<unsigned long long*>(ctx->pinned);
+  VGPR_HIP(ctx, hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), ctx->stream));
+  hipLaunchKernelGGL(stats_kernel, dim3(256), dim3(256), 0, ctx->stream, *M, d);
+  VGPR_HIP(ctx, hipGetLastError());
+  VGPR_HIP(ctx, hipMemcpyAsync(h, d, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipMemcpyAsync(h + 2, M->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h_n_voxels) *h_n_voxels = (int64_t)h[2];
+  if (h_n_points) *h_n_points = (int64_t)h[0];
+  if (h_n_converged) *h_n_converged = (int64_t)h[1];
+  return VGPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libvgpr.so (the C ABI in include/vgpr.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library.
+PyTorch provides device memory (tensors' data_ptr) and the stream. Loading
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import weakref
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvgpr.so")
+
+OK, E_INVALID, E_NOMEM, E_CAPACITY, E_RANGE, E_BUDGET, E_DEVICE, E_UNSUPPORTED = range(8)
+ST_SOLVED, ST_BELOW_TAU, ST_CAPPED, ST_REFINED, ST_FACTOR_FAIL, ST_CONVERGED, ST_AXIS_TIE = 1, 2, 4, 8, 16, 32, 64
+PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
+
+# every entry point include/vgpr.h declares
+SYMBOLS = [
+    "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
+    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create",
+    "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("voxel_size", C.c_float), ("max_pts", C.c_int32), ("min_pts", C.c_int32), ("grid_side", C.c_int32),
+        ("signal_var", C.c_float), ("length_scale", C.c_float), ("noise_var", C.c_float),
+        ("ls_mode", C.c_int32), ("frame_mode", C.c_int32), ("precision", C.c_int32),
+        ("refine_threshold", C.c_float), ("converge_var", C.c_float),
+    ]
+
+    def replace(self, **kw) -> "Params":
+        p = Params()
+        C.pointer(p)[0] = self
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class VgprError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libvgpr.so and declare its signatures. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "vgpr_params_default": (None, [P(Params)]),
+        "vgpr_status_str": (C.c_char_p, [C.c_int]),
+        "vgpr_create": (C.c_int, [C.c_int, vp, sz, P(vp)]),
+        "vgpr_destroy": (C.c_int, [vp]),
+        "vgpr_set_stream": (C.c_int, [vp, vp]),
+        "vgpr_last_error": (C.c_char_p, [vp]),
+        "vgpr_workspace_bytes": (sz, [vp]),
+        "vgpr_voxelize": (C.c_int, [vp, vp, i64, P(i64), i32, P(Params), vp, vp, vp, vp, i64, P(i64), P(i64),
+                                    P(i64)]),
+        "vgpr_fit_predict": (C.c_int, [vp, vp, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
+        "vgpr_map_create": (C.c_int, [vp, P(Params), i64, P(vp)]),
+        "vgpr_map_destroy": (C.c_int, [vp]),
+        "vgpr_map_update": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, P(i64)]),
+        "vgpr_map_stats": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
+        "vgpr_profile_enable": (C.c_int, [vp, C.c_int]),
+        "vgpr_profile_read": (C.c_int, [vp, C.c_char_p, P(C.c_double), P(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().vgpr_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Voxels:
+    keys: object      # (V,) int64 tensor holding the uint64 key bits
+    offsets: object   # (V,) int32
+    counts: object    # (V,) int32
+    perm: object      # (N,) int32
+    n_vox: int
+    frame_vox: list
+    n_invalid: int
+
+
+class Context:
+    """One vgpr_ctx on a device, enqueuing on a torch stream (default: the current one)."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = self.lib.vgpr_create(device, C.c_void_p(self.stream.cuda_stream), hbm_budget, C.byref(h))
+        if st != OK:
+            raise VgprError(st, f"vgpr_create failed: {self.lib.vgpr_status_str(st).decode()}")
+        self.h = h
+        self._maps = weakref.WeakSet()
+
+    def close(self):
+        if getattr(self, "h", None):
+            for m in list(self._maps):
+                m.close()
+            self._check(self.lib.vgpr_destroy(self.h), "vgpr_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != OK:
+            msg = self.lib.vgpr_last_error(self.h).decode()
+            raise VgprError(st, f"{what}: {self.lib.vgpr_status_str(st).decode()}: {msg}")
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.vgpr_set_stream(self.h, C.c_void_p(stream.cuda_stream)), "vgpr_set_stream")
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.vgpr_workspace_bytes(self.h))
+
+    # -- vgpr_voxelize -------------------------------------------------------
+    def voxelize(self, xyz, params: Params, frame_offsets=None, cap_vox: int | None = None) -> Voxels:
+        torch = self.torch
+        assert xyz.is_cuda and xyz.dtype == torch.float32 and xyz.is_contiguous()
+        n = xyz.numel() // 3
+        dev = xyz.device
+        cap = n if cap_vox is None else int(cap_vox)
+        keys = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+        offs = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        cnts = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        nf = 1 if frame_offsets is None else len(frame_offsets) - 1
+        fo = None if frame_offsets is None else (C.c_int64 * (nf + 1))(*[int(x) for x in frame_offsets])
+        fv = (C.c_int64 * (nf + 1))()
+        nv = C.c_int64()
+        ninv = C.c_int64()
+        st = self.lib.vgpr_voxelize(self.h, _ptr(xyz), n, fo, nf, C.byref(params), _ptr(keys), _ptr(offs),
+                                    _ptr(cnts), _ptr(perm), cap, C.byref(nv), fv, C.byref(ninv))
+        self._check(st, "vgpr_voxelize")
+        v = nv.value
+        return Voxels(keys[:v], offs[:v], cnts[:v], perm[:n], v, list(fv), ninv.value)
+
+    # -- vgpr_fit_predict ----------------------------------------------------
+    def fit_predict(self, xyz, vox: Voxels, params: Params, noise_var=None, out=None):
+        torch = self.torch
+        m = params.grid_side * params.grid_side
+        dev = xyz.device
+        v = vox.n_vox
+        if out is None:
+            out = (torch.empty((max(v, 1), m, 4), dtype=torch.float32, device=dev),
+                   torch.empty(max(v, 1), dtype=torch.int8, device=dev),
+                   torch.empty(max(v, 1), dtype=torch.uint8, device=dev))
+        o, ax, stt = out
+        st = self.lib.vgpr_fit_predict(self.h, _ptr(xyz), _ptr(vox.keys), _ptr(vox.offsets), _ptr(vox.counts),
+                                       _ptr(vox.perm), v, _ptr(noise_var), C.byref(params), _ptr(o), _ptr(ax),
+                                       _ptr(stt))
+        self._check(st, "vgpr_fit_predict")
+        return o[:v], ax[:v], stt[:v]
+
+    # -- timing ---------------------------------------------------------------
+    def profile(self, on: bool = True):
+        self._check(self.lib.vgpr_profile_enable(self.h, 1 if on else 0), "vgpr_profile_enable")
+
+    def profile_read(self, name: str):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(self.lib.vgpr_profile_read(self.h, name.encode(), C.byref(ms), C.byref(cnt)),
+                    "vgpr_profile_read")
+        return ms.value, cnt.value
+
+
+class Map:
+    """A device-resident voxel map (vgpr_map) bound to a Context."""
+
+    def __init__(self, ctx: Context, params: Params, max_voxels: int):
+        self.ctx = ctx
+        self.params = params
+        h = C.c_void_p()
+        ctx._check(ctx.lib.vgpr_map_create(ctx.h, C.byref(params), int(max_voxels), C.byref(h)), "vgpr_map_create")
+        self.h = h
+        ctx._maps.add(self)
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.vgpr_map_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, xyz, cap_upd: int | None = None, out=None):
+        torch = self.ctx.torch
+        n = xyz.numel() // 3
+        m = self.params.grid_side ** 2
+        cap = n if cap_upd is None else int(cap_upd)
+        dev = xyz.device
+        if out is None:
+            out = (torch.empty(max(cap, 1), dtype=torch.int64, device=dev),
+                   torch.empty((max(cap, 1), m, 4), dtype=torch.float32, device=dev),
+                   torch.empty(max(cap, 1), dtype=torch.int8, device=dev),
+                   torch.empty(max(cap, 1), dtype=torch.uint8, device=dev))
+        k, o, ax, st_ = out
+        nu = C.c_int64()
+        st = self.ctx.lib.vgpr_map_update(self.h, _ptr(xyz), n, _ptr(k), _ptr(o), _ptr(ax), _ptr(st_), cap,
+                                          C.byref(nu))
+        self.ctx._check(st, "vgpr_map_update")
+        u = nu.value
+        return k[:u], o[:u], ax[:u], st_[:u]
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self.ctx._check(self.ctx.lib.vgpr_map_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "vgpr_map_stats")
+        return {"voxels": a.value, "points": b.value, "converged": c.value}

@@ -1,0 +1,102 @@
+"""Shared helpers of the GPU parity tests: run the oracle and the HIP path on the
+same inputs and compare them element by element.
+
+Tolerances (stated per output):
+- voxel keys, offsets, counts, permutation, voxel counts: bit-exact;
+- query-grid coordinates (u, w): bit-exact (both sides evaluate the same
+  float32 grid);
+- predicted coordinate (the posterior mean): |gpu - oracle| <= 1e-4 m;
+- predicted variance: |gpu - oracle| <= 1e-3 * s_f^2 (the prior variance);
+- value axis: equal unless the oracle or the GPU flags the decision as a
+  near-tie, where the oracle is re-evaluated with the GPU's axis;
+- status bits SOLVED / BELOW_TAU / CAPPED: equal; CONVERGED: equal unless the
+  oracle's max variance is within the variance tolerance of eta.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import vgpr_oracle as O
+
+MEAN_TOL = 1e-4
+VAR_TOL_REL = 1e-3
+
+
+def oracle_params(d: dict) -> O.Params:
+    keys = {f for f in O.Params.__dataclass_fields__}
+    return O.Params(**{k: v for k, v in d.items() if k in keys})
+
+
+def gpu_params(vgpr, d: dict, **kw):
+    fields = {f for f, _ in vgpr.Params._fields_}
+    p = vgpr.default_params(**{k: v for k, v in d.items() if k in fields})
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def as_u64(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def compare_voxelize(ov: dict, gv) -> None:
+    V = len(ov["keys"])
+    assert gv.n_vox == V, (gv.n_vox, V)
+    assert np.array_equal(as_u64(gv.keys), ov["keys"])
+    assert np.array_equal(gv.offsets.cpu().numpy().astype(np.int64), ov["offsets"])
+    assert np.array_equal(gv.counts.cpu().numpy().astype(np.int64), ov["counts"])
+    assert np.array_equal(gv.perm.cpu().numpy().astype(np.int64), ov["perm"])
+    assert gv.n_invalid == ov["n_invalid"]
+    assert list(gv.frame_vox) == ov["frame_vox"].tolist()
+
+
+def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, voxels=None,
+                noise=None) -> dict:
+    """Compare GPU outputs with the oracle voxel by voxel; returns error stats."""
+    out = out.cpu().numpy().astype(np.float64)
+    axis = axis.cpu().numpy().astype(np.int64)
+    status = status.cpu().numpy().astype(np.int64)
+    V = len(ov["keys"])
+    idx = range(V) if voxels is None else voxels
+    max_mean = 0.0
+    max_var = 0.0
+    n_solved = 0
+    n_refined = 0
+    n_tie = 0
+    for v in idx:
+        P = O.voxel_points(xyz, ov, v)
+        nz = None
+        if noise is not None:
+            o, c = int(ov["offsets"][v]), int(ov["counts"][v])
+            nz = noise[ov["perm"][o:o + c]]
+        r = O.fit_predict_voxel(P, ov["keys"][v], prm, noise_var=nz)
+        st = status[v]
+        for bit in (O.ST_SOLVED, O.ST_BELOW_TAU, O.ST_CAPPED):
+            assert bool(st & bit) == bool(r["status"] & bit), (v, st, r["status"])
+        if not r["status"] & O.ST_SOLVED:
+            assert axis[v] == -1 and np.isnan(out[v]).all(), v
+            continue
+        n_solved += 1
+        n_refined += bool(st & O.ST_REFINED)
+        a = r["axis"]
+        if axis[v] != a:
+            assert r["ambiguous"] or (st & O.ST_AXIS_TIE), (v, axis[v], a)
+            n_tie += 1
+            a = int(axis[v])
+            r = O.fit_predict_voxel(P, ov["keys"][v], prm, axis=a, noise_var=nz)
+        u, w = O.PARAM_AXES[a]
+        g = out[v]
+        e = r["out"]
+        assert np.array_equal(g[:, u].astype(np.float32), e[:, u].astype(np.float32)), v
+        assert np.array_equal(g[:, w].astype(np.float32), e[:, w].astype(np.float32)), v
+        em = np.abs(g[:, a] - e[:, a]).max()
+        ev = np.abs(g[:, 3] - e[:, 3]).max()
+        max_mean = max(max_mean, em)
+        max_var = max(max_var, ev)
+        assert em <= MEAN_TOL, (v, em, r["n"])
+        assert ev <= VAR_TOL_REL * prm.signal_var, (v, ev, r["n"])
+        mv = e[:, 3].max()
+        if abs(mv - prm.converge_var) > VAR_TOL_REL * prm.signal_var:
+            assert bool(st & O.ST_CONVERGED) == bool(mv <= prm.converge_var), (v, mv)
+    return {"max_mean_err": max_mean, "max_var_err": max_var, "solved": n_solved, "refined": n_refined,
+            "axis_ties": n_tie}
