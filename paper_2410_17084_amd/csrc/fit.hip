@@ -1,30 +1,38 @@
 // vgpr_fit_predict: Alg. 1 after STORE, Eq. (1)-(3) of the paper, per voxel.
 //
-// Design (MI355X): one workgroup solves one voxel at a time, pulling voxel
-// indices from a size bucket's list with an atomic counter (persistent grid).
-// The workgroup's lanes own the rows of the augmented system
+// Three kernels per call (plus a re-solve pass in FP32 mode):
 //
-//          [ K + S ]   n data rows      (S = noise variances on the diagonal)
-//          [ f~^T  ]   1 right-hand-side row (f minus its mean)
-//          [ K*^T  ]   m query rows
-//
-// restricted to the n columns of the data points. A right-looking LDL^T
-// elimination over those n columns (no square roots) turns the data rows into
-// the factor, the f row into y = L^-1 f~ and every query row into L^-1 k*_q, so
-// the posterior of Eq. (3) accumulates on the fly:
-//   var_q  = s_f^2 - sum_j a_qj^2 / d_j          (diagonal of Sigma*)
-//   mean_q = mu    + sum_j a_qj * y_j / d_j       (K*^T (K+S)^-1 f~)
-// where d_j is the j-th pivot and a_qj the query row's entry at step j. Each
-// lane keeps its row in registers; after step j the row is shifted by one
-// register so the active column is always element 0 (no dynamic register
-// indexing). Column j of the data rows is broadcast through LDS, double
-// buffered, with one barrier per step. K, K* and K** are never stored.
+// 1. prep (one thread per voxel): kept count n, tau test, the PCA frame of
+//    Alg. 1 in double (centroid, covariance, cyclic Jacobi eigen-solve, value
+//    axis = world axis closest to the smallest-eigenvalue eigenvector, cyclic
+//    parameter axes, near-tie flag, optional per-voxel length scale) written
+//    as a 48-byte record, and the voxel appended to its size bucket with one
+//    atomic per wavefront and bucket.
+// 2. solve: the posterior of Eq. (3) from an LDL^T elimination of the
+//    augmented system whose rows are
+//          [ K + S | f~ ]   n data rows      (S = noise variances on the diagonal)
+//          [ K*^T       ]   m query rows
+//    restricted to the n data columns. Eliminating the data columns turns
+//    each query row into L^-1 k*_q and the right-hand side f~ (f minus its
+//    mean, one extra value per data row) into y = L^-1 f~, so
+//      var_q  = s_f^2 - sum_j a_qj^2 / d_j      (diagonal of Sigma*)
+//      mean_q = mu    + sum_j a_qj * y_j / d_j   (K*^T (K+S)^-1 f~)
+//    accumulate on the fly (d_j = pivots, a_qj = the query row's entry at
+//    step j). K, K* and K** are never stored. Each row lives in registers;
+//    after step j it shifts by one register so the active column is always
+//    element 0 (no dynamic register indexing).
+//    - wave solver (n <= 64, m <= 64): one voxel per wavefront, lane l holds
+//      query row l and data row l; column j is broadcast with readlane, so
+//      the elimination has no barriers at all.
+//    - block solver (larger voxels or grids): one voxel per workgroup, one
+//      row per lane, column j broadcast through LDS with one barrier a step.
+// 3. NaN rows for voxels below tau.
 //
 // The elimination type T is float or double. In FP32 mode every voxel runs
-// in float and those whose refinement score sum_j |y_j| / d_j exceeds the
-// threshold (the FP32 rounding amplification of K^-1 f~) are re-solved in
-// double; in FP64 mode every voxel runs in double. The PCA frame is double in
-// both.
+// in float and voxels whose refinement score sum_j |y_j| / d_j exceeds the
+// threshold (the amplification of FP32 rounding in K^-1 f~) are re-solved in
+// double; in FP64 mode every voxel runs in double.
+#include <algorithm>
 #include <cfloat>
 
 #include "scan.cuh"
@@ -33,7 +41,10 @@
 namespace vgpr {
 namespace {
 
-constexpr int kFitThreads = 256;  // upper bound of the workgroup size
+constexpr int kBlockThreads = 256;  // upper bound of the block solver's workgroup
+constexpr int kWaveThreads = 256;   // workgroup of the wave solver: 4 independent wavefronts
+constexpr int kLists = kNumBuckets + 1;  // size buckets + the below-tau list
+constexpr int kNanList = kNumBuckets;
 
 struct FitParams {
   int cap;          // max_pts
@@ -42,6 +53,7 @@ struct FitParams {
   int m;            // nq * nq
   int ls_mode;
   int mode;         // 0 = FP32 first pass (flags), 1 = FP64 re-solve pass, 2 = FP64 only
+  int bcap[kNumBuckets];  // bucket capacities
   float sf2;
   float noise;
   float eta;
@@ -50,16 +62,34 @@ struct FitParams {
   double ell;       // fixed length scale
 };
 
-struct WorkList {
-  const int32_t* list;        // voxel indices
-  const uint32_t* count;      // number of entries (device)
-  uint32_t* next;             // fetch counter (device)
-  int32_t* refine_list;       // FP32 pass: voxels to re-solve (nullable)
-  uint32_t* refine_count;
+// Per-voxel frame of Alg. 1, written by prep and read by the solvers.
+struct FrameRec {
+  double mu;        // mean of the value coordinate
+  double anc_u;     // voxel corner along u
+  double anc_w;     // voxel corner along w
+  double lam;       // 1 / (2 l^2)
+  int ku, kw;       // voxel indices along u and w
+  int axes;         // value axis | u << 2 | w << 4 | tie << 6
+  int n;            // kept points
+};
+
+struct Lists {
+  int32_t* list;         // kLists lists of `stride` entries
+  uint32_t* count;       // kLists counters
+  int64_t stride;
 };
 
 __device__ __forceinline__ float k_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double k_exp(double x) { return exp(x); }
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
 
 // Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (double).
 // On return w[] holds the eigenvalues and column k of V the k-th eigenvector.
@@ -78,23 +108,24 @@ __device__ void jacobi3(double A[3][3], double w[3], double V[3][3]) {
       const int q = pq == 0 ? 1 : 2;
       const int r = 3 - p - q;
       const double apq = A[p][q];
-      if (apq == 0.0) continue;
-      // rotation angle that annihilates A[p][q]: tan via the smaller root
-      const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
-      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      const double c = 1.0 / sqrt(t * t + 1.0);
-      const double s = t * c;
-      const double arp = A[r][p], arq = A[r][q];
-      A[p][p] -= t * apq;
-      A[q][q] += t * apq;
-      A[p][q] = A[q][p] = 0.0;
-      A[r][p] = A[p][r] = c * arp - s * arq;
-      A[r][q] = A[q][r] = s * arp + c * arq;
+      if (apq != 0.0) {
+        // rotation angle that annihilates A[p][q]: tan via the smaller root
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0);
+        const double s = t * c;
+        const double arp = A[r][p], arq = A[r][q];
+        A[p][p] -= t * apq;
+        A[q][q] += t * apq;
+        A[p][q] = A[q][p] = 0.0;
+        A[r][p] = A[p][r] = c * arp - s * arq;
+        A[r][q] = A[q][r] = s * arp + c * arq;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double vkp = V[k][p], vkq = V[k][q];
-        V[k][p] = c * vkp - s * vkq;
-        V[k][q] = s * vkp + c * vkq;
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
       }
     }
   }
@@ -103,80 +134,48 @@ __device__ void jacobi3(double A[3][3], double w[3], double V[3][3]) {
   w[2] = A[2][2];
 }
 
-struct FrameInfo {
-  double mu;        // mean of the value coordinate
-  double anc_u;     // voxel corner along u
-  double anc_w;     // voxel corner along w
-  double lam;       // 1 / (2 l^2)
-  int axis, u, w;
-  int ku, kw;
-  int tie;
-};
+__device__ __forceinline__ float pick(int axis, float x, float y, float z) { return axis == 0 ? x : (axis == 1 ? y : z); }
 
-template <typename T, int NMAX>
-__global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs io, WorkList wl) {
-  __shared__ float sp[3][NMAX];
-  __shared__ T su[NMAX + 4], sw[NMAX + 4], sf[NMAX + 4];
-  __shared__ __attribute__((aligned(16))) T col[2][NMAX + 8];
-  __shared__ T piv[2][2];
-  __shared__ FrameInfo fr;
-  __shared__ int s_item;
-  __shared__ unsigned s_maxvar;
-  __shared__ int s_flag;
-
-  const int tid = threadIdx.x;
-  const int NT = blockDim.x;
-  const int lane = tid & 63;
-
-  for (;;) {
-    if (tid == 0) {
-      s_item = (int)atomicAdd(wl.next, 1u);
-      s_maxvar = 0u;
-      s_flag = 0;
-    }
-    __syncthreads();
-    const int item = s_item;
-    if (item >= (int)*wl.count) break;
-    const int v = wl.list[item];
-    const int off = io.offsets[v];
-    const int cnt = io.counts[v];
-    const int n = cnt < P.cap ? cnt : P.cap;
-    const int* perm = io.perm;
-
-    // ---- gather the voxel's points (coalesced over consecutive sorted slots)
-    for (int i = tid; i < n; i += NT) {
-      const int idx = perm ? perm[off + i] : off + i;
-      sp[0][i] = io.xyz[3 * (size_t)idx + 0];
-      sp[1][i] = io.xyz[3 * (size_t)idx + 1];
-      sp[2][i] = io.xyz[3 * (size_t)idx + 2];
-    }
-    __syncthreads();
-
-    // ---- PCA frame and value-axis switch (wave 0, double)
-    if (tid < 64) {
-      double c0 = 0, c1 = 0, c2 = 0;
-      for (int i = 0; i < n; ++i) {
-        c0 += (double)sp[0][i];
-        c1 += (double)sp[1][i];
-        c2 += (double)sp[2][i];
+// ---------------------------------------------------------------------------
+// 1. prep: tau test, PCA frame, bucketing (one thread per voxel)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, FrameRec* __restrict__ frames,
+                                                   Lists L) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = v < io.n_vox;
+  int lst = -1;
+  if (valid) {
+    const int c = io.counts[v];
+    const int n = c < P.cap ? c : P.cap;
+    if (n < P.tau) {
+      io.status[v] = (uint8_t)(VGPR_ST_BELOW_TAU | (c > P.cap ? VGPR_ST_CAPPED : 0));
+      io.axis[v] = -1;
+      lst = kNanList;
+    } else {
+      const int off = io.offsets[v];
+      const int* perm = io.perm;
+      // one pass about the first point: S1 = sum d, S2 = sum d d^T, d = p - p0
+      const int i0 = perm ? perm[off] : off;
+      const double p0x = io.xyz[3 * (size_t)i0], p0y = io.xyz[3 * (size_t)i0 + 1], p0z = io.xyz[3 * (size_t)i0 + 2];
+      double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+      for (int i = 1; i < n; ++i) {
+        const int idx = perm ? perm[off + i] : off + i;
+        const double d0 = (double)io.xyz[3 * (size_t)idx] - p0x;
+        const double d1 = (double)io.xyz[3 * (size_t)idx + 1] - p0y;
+        const double d2 = (double)io.xyz[3 * (size_t)idx + 2] - p0z;
+        s0 += d0; s1 += d1; s2 += d2;
+        a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
+        a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
       }
       const double inv_n = 1.0 / (double)n;
-      c0 *= inv_n;
-      c1 *= inv_n;
-      c2 *= inv_n;
-      double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      for (int i = 0; i < n; ++i) {
-        const double d0 = (double)sp[0][i] - c0, d1 = (double)sp[1][i] - c1, d2 = (double)sp[2][i] - c2;
-        A[0][0] += d0 * d0;
-        A[0][1] += d0 * d1;
-        A[0][2] += d0 * d2;
-        A[1][1] += d1 * d1;
-        A[1][2] += d1 * d2;
-        A[2][2] += d2 * d2;
-      }
-      A[0][0] *= inv_n; A[0][1] *= inv_n; A[0][2] *= inv_n;
-      A[1][1] *= inv_n; A[1][2] *= inv_n; A[2][2] *= inv_n;
-      A[1][0] = A[0][1]; A[2][0] = A[0][2]; A[2][1] = A[1][2];
+      const double m0 = s0 * inv_n, m1 = s1 * inv_n, m2 = s2 * inv_n;
+      double A[3][3];
+      A[0][0] = a00 * inv_n - m0 * m0;
+      A[0][1] = A[1][0] = a01 * inv_n - m0 * m1;
+      A[0][2] = A[2][0] = a02 * inv_n - m0 * m2;
+      A[1][1] = a11 * inv_n - m1 * m1;
+      A[1][2] = A[2][1] = a12 * inv_n - m1 * m2;
+      A[2][2] = a22 * inv_n - m2 * m2;
       const double tr = A[0][0] + A[1][1] + A[2][2];
       double w[3], V[3][3];
       jacobi3(A, w, V);
@@ -188,13 +187,12 @@ __global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs i
       const double wlo = fmin(fmin(w[0], w[1]), w[2]);
       const double whi = fmax(fmax(w[0], w[1]), w[2]);
       const double wmid = fmax(fmin(w[0], w[1]), fmin(fmax(w[0], w[1]), w[2]));
-      const double a0 = fabs(v0), a1 = fabs(v1), a2 = fabs(v2);
+      const double b0 = fabs(v0), b1 = fabs(v1), b2 = fabs(v2);
       int ax = 0;
-      double best = a0;
-      if (a1 > best) { ax = 1; best = a1; }
-      if (a2 > best) { ax = 2; best = a2; }
-      // second largest |v_k|
-      const double second = (ax == 0) ? fmax(a1, a2) : (ax == 1 ? fmax(a0, a2) : fmax(a0, a1));
+      double best = b0;
+      if (b1 > best) { ax = 1; best = b1; }
+      if (b2 > best) { ax = 2; best = b2; }
+      const double second = (ax == 0) ? fmax(b1, b2) : (ax == 1 ? fmax(b0, b2) : fmax(b0, b1));
       const int tie = (best - second < 1e-6) || (wmid - wlo <= 1e-8 * tr);
       const int u = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
       const int wv = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
@@ -203,93 +201,290 @@ __global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs i
         const double e = sqrt(3.0) * sqrt(fmax((wmid + whi) * 0.5, 0.0));
         ell = fmin(fmax(e, 0.05 * P.s), 2.0 * P.s);
       }
-      if (tid == 0) {
-        const uint64_t key = io.keys[v];
-        const int64_t mask = (int64_t(1) << kKeyFieldBits) - 1;
-        const int kx = (int)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias);
-        const int ky = (int)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias);
-        const int kz = (int)((int64_t)(key & mask) - kKeyBias);
-        const int ku = u == 0 ? kx : (u == 1 ? ky : kz);
-        const int kw = wv == 0 ? kx : (wv == 1 ? ky : kz);
-        fr.axis = ax;
-        fr.u = u;
-        fr.w = wv;
-        fr.ku = ku;
-        fr.kw = kw;
-        fr.mu = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
-        fr.anc_u = (double)ku * P.s;
-        fr.anc_w = (double)kw * P.s;
-        fr.lam = 1.0 / (2.0 * ell * ell);
-        fr.tie = tie;
+      const uint64_t key = io.keys[v];
+      const int64_t mask = (int64_t(1) << kKeyFieldBits) - 1;
+      const int kx = (int)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias);
+      const int ky = (int)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias);
+      const int kz = (int)((int64_t)(key & mask) - kKeyBias);
+      FrameRec fr;
+      fr.ku = u == 0 ? kx : (u == 1 ? ky : kz);
+      fr.kw = wv == 0 ? kx : (wv == 1 ? ky : kz);
+      const double pa = ax == 0 ? p0x : (ax == 1 ? p0y : p0z);
+      const double ma = ax == 0 ? m0 : (ax == 1 ? m1 : m2);
+      fr.mu = pa + ma;
+      fr.anc_u = (double)fr.ku * P.s;
+      fr.anc_w = (double)fr.kw * P.s;
+      fr.lam = 1.0 / (2.0 * ell * ell);
+      fr.axes = ax | (u << 2) | (wv << 4) | (tie << 6);
+      fr.n = n;
+      frames[v] = fr;
+      lst = 0;
+      while (lst < kNumBuckets - 1 && n > P.bcap[lst]) ++lst;
+    }
+  }
+  // append to the lists with one atomic per wavefront and list
+  const int lane = lane_id();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int l = 0; l < kLists; ++l) {
+    const unsigned long long mk = __ballot(lst == l);
+    if (mk) {
+      const int leader = __ffsll((long long)mk) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&L.count[l], (uint32_t)__popcll(mk));
+      base = __shfl(base, leader, 64);
+      if (lst == l) L.list[l * L.stride + base + __popcll(mk & lt)] = (int32_t)v;
+    }
+  }
+}
+
+// Zero the list counters with a kernel (no memset node when a caller captures the call in a graph).
+__global__ void zero_kernel(uint32_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// 3. NaN rows of voxels below tau (one wavefront per voxel, coalesced rows)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) nan_kernel(FitParams P, float* __restrict__ out, Lists L) {
+  const int lane = lane_id();
+  const int gw = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
+  const int count = (int)L.count[kNanList];
+  const float nan = __int_as_float(0x7fc00000);
+  for (int it = gw; it < count; it += nw) {
+    const int v = L.list[kNanList * L.stride + it];
+    float4* o = reinterpret_cast<float4*>(out) + (size_t)v * P.m;
+    for (int q = lane; q < P.m; q += 64) o[q] = make_float4(nan, nan, nan, nan);
+  }
+}
+
+// Status of a solved (or flagged) voxel; lane / thread 0 only.
+__device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& io, int v, int cnt, int axes,
+                                             bool failed, bool flag, float maxvar, int32_t* rlist,
+                                             uint32_t* rcount) {
+  uint8_t st = VGPR_ST_SOLVED;
+  if (cnt > P.cap) st |= VGPR_ST_CAPPED;
+  if ((axes >> 6) & 1) st |= VGPR_ST_AXIS_TIE;
+  if (flag) {
+    // FP32 pass: hand the voxel to the FP64 re-solve list
+    const uint32_t slot = atomicAdd(rcount, 1u);
+    rlist[slot] = v;
+    if (failed) st |= VGPR_ST_FACTOR_FAIL;
+  } else {
+    if (P.mode == 1) st |= VGPR_ST_REFINED | (io.status[v] & VGPR_ST_FACTOR_FAIL);
+    if (failed) st = (uint8_t)((st & ~VGPR_ST_SOLVED) | VGPR_ST_FACTOR_FAIL);
+    else if (maxvar <= P.eta) st |= VGPR_ST_CONVERGED;
+  }
+  io.status[v] = st;
+  io.axis[v] = (int8_t)(axes & 3);
+}
+
+__device__ __forceinline__ void query_coords(const FitParams& P, const FrameRec& fr, int q, float* gu, float* gw) {
+  const int i = q / P.nq, j = q - (q / P.nq) * P.nq;
+  const double ti = __ddiv_rn((double)i + 0.5, (double)P.nq);
+  const double tj = __ddiv_rn((double)j + 0.5, (double)P.nq);
+  *gu = (float)__dmul_rn(__dadd_rn((double)fr.ku, ti), P.s);
+  *gw = (float)__dmul_rn(__dadd_rn((double)fr.kw, tj), P.s);
+}
+
+__device__ __forceinline__ float4 out_row(int ax, int u, float mv, float gu, float gw, float vv) {
+  float4 o;
+  o.x = ax == 0 ? mv : (u == 0 ? gu : gw);
+  o.y = ax == 1 ? mv : (u == 1 ? gu : gw);
+  o.z = ax == 2 ? mv : (u == 2 ? gu : gw);
+  o.w = vv;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
+// ---------------------------------------------------------------------------
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
+                                                                const FrameRec* __restrict__ frames,
+                                                                const int32_t* __restrict__ list,
+                                                                const uint32_t* __restrict__ count,
+                                                                int32_t* __restrict__ rlist,
+                                                                uint32_t* __restrict__ rcount) {
+  const int lane = lane_id();
+  const int gw = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
+  const int cnt_items = (int)*count;
+  const T sf2 = (T)P.sf2;
+  for (int it = gw; it < cnt_items; it += nw) {
+    const int v = list[it];
+    const FrameRec fr = frames[v];
+    const int n = fr.n;
+    const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
+    const int off = io.offsets[v];
+    const int cnt = io.counts[v];
+    const T lam = (T)fr.lam;
+    // this lane's data point (lanes < n)
+    T xu = 0, xw = 0, fv = 0, nz = (T)P.noise;
+    if (lane < n) {
+      const int idx = io.perm ? io.perm[off + lane] : off + lane;
+      const float px = io.xyz[3 * (size_t)idx], py = io.xyz[3 * (size_t)idx + 1], pz = io.xyz[3 * (size_t)idx + 2];
+      xu = (T)((double)pick(u, px, py, pz) - fr.anc_u);
+      xw = (T)((double)pick(wax, px, py, pz) - fr.anc_w);
+      fv = (T)((double)pick(ax, px, py, pz) - fr.mu);
+      if (io.noise) nz = (T)io.noise[idx];
+    }
+    // this lane's query point (lanes < m)
+    float gu = 0.f, gwv = 0.f;
+    query_coords(P, fr, lane < P.m ? lane : 0, &gu, &gwv);
+    const T qu = (T)((double)gu - fr.anc_u), qw = (T)((double)gwv - fr.anc_w);
+    const bool dlane = lane < n;
+
+    // rows: A = query row (lanes < m), B = data row (lanes < n) with its right-hand side fy
+    T A[NMAX], B[NMAX];
+    T fy = fv;
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) {
+      if (c < n) {
+        const T uc = bcast(xu, c), wc = bcast(xw, c);
+        const T du = qu - uc, dw = qw - wc;
+        A[c] = sf2 * k_exp(-(du * du + dw * dw) * lam);
+        const T eu = xu - uc, ew = xw - wc;
+        const T kb = sf2 * k_exp(-(eu * eu + ew * ew) * lam) + (c == lane ? nz : (T)0);
+        B[c] = dlane ? kb : (T)0;
+      } else {
+        A[c] = 0;
+        B[c] = 0;
       }
     }
+    T var = sf2, mean = 0, minpiv = (T)FLT_MAX, score = 0;
+    for (int j = 0; j < n; ++j) {
+      const T cjA = A[0], cjB = B[0];
+      const T d = bcast(cjB, j);
+      const T y = bcast(fy, j);  // y_j = (L^-1 f~)_j, final once step j is reached
+      const T inv = (T)1 / d;
+      const T tA = cjA * inv, tB = cjB * inv;
+      var -= tA * cjA;
+      mean += tA * y;
+      fy -= tB * y;
+      minpiv = d < minpiv ? d : minpiv;
+      score += (y < 0 ? -y : y) * inv;
+      const int Lc = n - j - 1;
+#pragma unroll
+      for (int c0 = 0; c0 < NMAX - 1; c0 += 8) {
+        if (c0 < Lc) {
+#pragma unroll
+          for (int k = c0; k < c0 + 8; ++k) {
+            if (k < NMAX - 1) {
+              // lane j+1+k holds data row j+1+k; past row n-1 the value is unused
+              const T col = bcast(cjB, (j + 1 + k) & 63);
+              A[k] = A[k + 1] - tA * col;
+              B[k] = B[k + 1] - tB * col;
+            }
+          }
+        }
+      }
+    }
+    const bool failed = !(minpiv > (T)0) || !isfinite((double)score);
+    const bool flag = P.mode == 0 && (failed || score > (T)P.refine_thr);
+    float mv_lane = 0.f;
+    if (!flag && lane < P.m) {
+      const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > (T)0 ? var : (T)0);
+      const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean);
+      reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + lane] = out_row(ax, u, mv, gu, gwv, vv);
+      mv_lane = failed ? 0.f : vv;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mv_lane = fmaxf(mv_lane, __shfl_xor(mv_lane, d, 64));
+    if (lane == 0) finish_voxel(P, io, v, cnt, fr.axes, failed, flag, mv_lane, rlist, rcount);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2b. block solver: one voxel per workgroup, one row per lane
+// ---------------------------------------------------------------------------
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, FitArgs io,
+                                                                  const FrameRec* __restrict__ frames,
+                                                                  const int32_t* __restrict__ list,
+                                                                  const uint32_t* __restrict__ count,
+                                                                  uint32_t* __restrict__ next,
+                                                                  int32_t* __restrict__ rlist,
+                                                                  uint32_t* __restrict__ rcount) {
+  __shared__ T su[NMAX + 4], sw[NMAX + 4], sf[NMAX + 4];
+  __shared__ __attribute__((aligned(16))) T col[2][NMAX + 8];
+  __shared__ T piv[2][2];
+  __shared__ int s_item;
+  __shared__ unsigned s_maxvar;
+  __shared__ int s_flag;
+
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  const int cnt_items = (int)*count;
+  const T sf2 = (T)P.sf2;
+
+  for (;;) {
+    if (tid == 0) {
+      s_item = (int)atomicAdd(next, 1u);
+      s_maxvar = 0u;
+      s_flag = 0;
+    }
     __syncthreads();
-    const int ax = fr.axis, u = fr.u, wax = fr.w;
-    const double mu = fr.mu;
+    const int item = s_item;
+    if (item >= cnt_items) break;
+    const int v = list[item];
+    const FrameRec fr = frames[v];
+    const int n = fr.n;
+    const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
+    const int off = io.offsets[v];
+    const int cnt = io.counts[v];
+    const int* perm = io.perm;
     for (int i = tid; i < n; i += NT) {
-      su[i] = (T)((double)sp[u][i] - fr.anc_u);
-      sw[i] = (T)((double)sp[wax][i] - fr.anc_w);
-      sf[i] = (T)((double)sp[ax][i] - mu);
+      const int idx = perm ? perm[off + i] : off + i;
+      const float px = io.xyz[3 * (size_t)idx], py = io.xyz[3 * (size_t)idx + 1], pz = io.xyz[3 * (size_t)idx + 2];
+      su[i] = (T)((double)pick(u, px, py, pz) - fr.anc_u);
+      sw[i] = (T)((double)pick(wax, px, py, pz) - fr.anc_w);
+      sf[i] = (T)((double)pick(ax, px, py, pz) - fr.mu);
     }
     __syncthreads();
 
     const T lam = (T)fr.lam;
-    const T sf2 = (T)P.sf2;
-    const int qchunk = NT - n - 1;
+    const int qchunk = NT - n;
     bool failed = false;
-    T minpiv = (T)FLT_MAX;
-    T score = 0;
     for (int q0 = 0; q0 < P.m; q0 += qchunk) {
-      // ---- row roles for this chunk
       const bool is_data = tid < n;
-      const bool is_f = tid == n;
-      const int q = q0 + tid - n - 1;
-      const bool is_query = tid > n && q < P.m;
+      const int q = q0 + tid - n;
+      const bool is_query = tid >= n && q < P.m;
       T a[NMAX];
-      float gu = 0.f, gw = 0.f;
-      T xu = 0, xw = 0, nz = 0;
+      float gu = 0.f, gwv = 0.f;
+      T xu = 0, xw = 0, nz = 0, fy = 0;
       if (is_data) {
         xu = su[tid];
         xw = sw[tid];
+        fy = sf[tid];
         nz = (T)P.noise;
         if (io.noise) nz = (T)io.noise[perm ? perm[off + tid] : off + tid];
       } else if (is_query) {
-        const int i = q / P.nq, j = q - (q / P.nq) * P.nq;
-        const double ti = __ddiv_rn((double)i + 0.5, (double)P.nq);
-        const double tj = __ddiv_rn((double)j + 0.5, (double)P.nq);
-        gu = (float)__dmul_rn(__dadd_rn((double)fr.ku, ti), P.s);
-        gw = (float)__dmul_rn(__dadd_rn((double)fr.kw, tj), P.s);
+        query_coords(P, fr, q, &gu, &gwv);
         xu = (T)((double)gu - fr.anc_u);
-        xw = (T)((double)gw - fr.anc_w);
+        xw = (T)((double)gwv - fr.anc_w);
       }
-      if (is_data || is_query) {
-        // kernel row: kappa(x_row, x_c) for the n data points, noise on the diagonal
 #pragma unroll
-        for (int c = 0; c < NMAX; ++c) {
-          if (c < n) {
-            const T du = xu - su[c], dw = xw - sw[c];
-            a[c] = sf2 * k_exp(-(du * du + dw * dw) * lam) + (c == tid ? nz : (T)0);
-          } else {
-            a[c] = 0;
-          }
+      for (int c = 0; c < NMAX; ++c) {
+        if (c < n) {
+          const T du = xu - su[c], dw = xw - sw[c];
+          const T kv = sf2 * k_exp(-(du * du + dw * dw) * lam) + (c == tid ? nz : (T)0);
+          a[c] = (is_data || is_query) ? kv : (T)0;
+        } else {
+          a[c] = 0;
         }
-      } else {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) a[c] = (is_f && c < n) ? sf[c] : (T)0;
       }
-      T var = sf2;
-      T mean = 0;
-      minpiv = (T)FLT_MAX;
-      score = 0;
-
-      // ---- right-looking LDL^T over the n data columns
+      T var = sf2, mean = 0, minpiv = (T)FLT_MAX, score = 0;
       for (int j = 0; j < n; ++j) {
         const int b = j & 1;
-        if (is_data && tid >= j) {
-          if (tid == j) piv[b][0] = a[0];
-          else col[b][tid - j - 1] = a[0];
+        if (tid == j) {
+          piv[b][0] = a[0];
+          piv[b][1] = fy;  // y_j, final at its own step
+        } else if (is_data && tid > j) {
+          col[b][tid - j - 1] = a[0];
         }
-        if (is_f) piv[b][1] = a[0];
         __syncthreads();
         const T d = piv[b][0];
         const T yj = piv[b][1];
@@ -297,15 +492,16 @@ __global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs i
         const T t = a[0] * inv;
         minpiv = d < minpiv ? d : minpiv;
         score += (yj < 0 ? -yj : yj) * inv;
+        fy -= t * yj;
         if (is_query) {
           var -= t * a[0];
           mean += t * yj;
         }
-        const int L = n - j - 1;
+        const int Lc = n - j - 1;
         const T* cb = col[b];
 #pragma unroll
         for (int c0 = 0; c0 < NMAX - 1; c0 += 8) {
-          if (c0 < L) {
+          if (c0 < Lc) {
 #pragma unroll
             for (int k = c0; k < c0 + 8; ++k)
               if (k < NMAX - 1) a[k] = a[k + 1] - t * cb[k];
@@ -314,17 +510,10 @@ __global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs i
       }
       failed = !(minpiv > (T)0) || !isfinite((double)score);
       const bool flag = P.mode == 0 && (failed || score > (T)P.refine_thr);
-
-      // ---- outputs
       if (is_query && !flag) {
         const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > (T)0 ? var : (T)0);
-        const float mv = failed ? __int_as_float(0x7fc00000) : (float)(mu + (double)mean);
-        float4 o;
-        o.x = ax == 0 ? mv : (u == 0 ? gu : gw);
-        o.y = ax == 1 ? mv : (u == 1 ? gu : gw);
-        o.z = ax == 2 ? mv : (u == 2 ? gu : gw);
-        o.w = vv;
-        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = o;
+        const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean);
+        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = out_row(ax, u, mv, gu, gwv, vv);
         if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
       }
       if (flag) {
@@ -333,109 +522,94 @@ __global__ void __launch_bounds__(kFitThreads) fit_kernel(FitParams P, FitArgs i
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      uint8_t st = VGPR_ST_SOLVED;
-      if (cnt > P.cap) st |= VGPR_ST_CAPPED;
-      if (fr.tie) st |= VGPR_ST_AXIS_TIE;
-      if (s_flag) {
-        // FP32 pass: hand the voxel to the FP64 re-solve list
-        const uint32_t slot = atomicAdd(wl.refine_count, 1u);
-        wl.refine_list[slot] = v;
-        if (s_flag == 2) st |= VGPR_ST_FACTOR_FAIL;
-        io.status[v] = st;
-      } else {
-        if (P.mode == 1) st |= VGPR_ST_REFINED | (io.status[v] & VGPR_ST_FACTOR_FAIL);
-        if (failed) {
-          st = (uint8_t)((st & ~VGPR_ST_SOLVED) | VGPR_ST_FACTOR_FAIL);
-        } else if (__uint_as_float(s_maxvar) <= P.eta) {
-          st |= VGPR_ST_CONVERGED;
-        }
-        io.status[v] = st;
-      }
-      io.axis[v] = (int8_t)ax;
-    }
+    if (tid == 0)
+      finish_voxel(P, io, v, cnt, fr.axes, s_flag == 2 || (!s_flag && failed), s_flag != 0,
+                   __uint_as_float(s_maxvar), rlist, rcount);
     __syncthreads();
   }
 }
 
-// Sort voxels into size buckets; voxels below tau get NaN rows.
-__global__ void __launch_bounds__(256) classify_kernel(const int32_t* __restrict__ counts, int64_t n_vox, int cap,
-                                                       int tau, int m, int32_t* __restrict__ lists,
-                                                       uint32_t* __restrict__ list_counts, int64_t list_stride,
-                                                       float* __restrict__ out, int8_t* __restrict__ axis,
-                                                       uint8_t* __restrict__ status) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n_vox) return;
-  const int c = counts[v];
-  const int n = c < cap ? c : cap;
-  if (n < tau) {
-    status[v] = (uint8_t)(VGPR_ST_BELOW_TAU | (c > cap ? VGPR_ST_CAPPED : 0));
-    axis[v] = -1;
-    const float nan = __int_as_float(0x7fc00000);
-    float4* o = reinterpret_cast<float4*>(out) + (size_t)v * m;
-    for (int q = 0; q < m; ++q) o[q] = make_float4(nan, nan, nan, nan);
-    return;
-  }
-  int b = 0;
-  while (b < kNumBuckets - 1 && n > kBucketCap[b]) ++b;
-  const uint32_t slot = atomicAdd(&list_counts[b], 1u);
-  lists[b * list_stride + slot] = (int32_t)v;
+template <typename K>
+int occupancy(K kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+// Timing family of each launch: pass (FP32, FP64 re-solve, FP64 only) and bucket capacity.
+const char* const kFam[3][kNumBuckets] = {
+    {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n128"},
+    {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n128"},
+    {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n128"}};
+
+struct Launch {
+  const int32_t* list;
+  const uint32_t* count;
+  uint32_t* next;
+  int32_t* rlist;
+  uint32_t* rcount;
+  int64_t max_items;
+  const char* fam;
+};
+
+template <typename T, int NMAX>
+vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const FrameRec* frames,
+                        const Launch& l) {
+  static int per_cu = -1;
+  if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX>, kWaveThreads);
+  int64_t grid = (int64_t)per_cu * ctx->cu_count;
+  const int64_t need = (l.max_items + kWaveThreads / 64 - 1) / (kWaveThreads / 64);
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  ProfScope ps(ctx, l.fam);
+  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX>), dim3((unsigned)grid), dim3(kWaveThreads), 0, ctx->stream, P, io,
+                     frames, l.list, l.count, l.rlist, l.rcount);
+  VGPR_HIP(ctx, hipGetLastError());
+  return VGPR_OK;
 }
 
 template <typename T, int NMAX>
-int blocks_per_cu() {
-  static int cached = -1;
-  if (cached < 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_kernel<T, NMAX>, kFitThreads, 0) != hipSuccess ||
-        nb < 1)
-      nb = 1;
-    cached = nb;
-  }
-  return cached;
-}
-
-// Timing family of each launch: precision, pass and bucket capacity.
-const char* const kFamFit32[kNumBuckets] = {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n128"};
-const char* const kFamFit64[kNumBuckets] = {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n128"};
-const char* const kFamRefine[kNumBuckets] = {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64",
-                                             "refine_f64_n128"};
-
-template <typename T>
-vgpr_status launch_bucket(vgpr_ctx* ctx, int b, const FitParams& P, const FitArgs& io, const WorkList& wl,
-                          int64_t max_items, const char* fam) {
-  const int nmax = kBucketCap[b];
-  int threads = nmax + 1 + P.m;
-  if (threads > kFitThreads) threads = kFitThreads;
+vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const FrameRec* frames,
+                         const Launch& l) {
+  int threads = NMAX + P.m;
+  if (threads > kBlockThreads) threads = kBlockThreads;
   threads = (threads + 63) & ~63;
-  int per_cu = 1;
-  switch (b) {
-    case 0: per_cu = blocks_per_cu<T, 16>(); break;
-    case 1: per_cu = blocks_per_cu<T, 32>(); break;
-    case 2: per_cu = blocks_per_cu<T, 64>(); break;
-    default: per_cu = blocks_per_cu<T, 128>(); break;
-  }
-  // occupancy was computed for the largest workgroup; smaller groups fit more
-  per_cu = per_cu * (kFitThreads / threads);
-  int64_t grid = (int64_t)per_cu * ctx->cu_count;
-  if (grid > max_items) grid = max_items;
+  static int per_cu = -1;
+  if (per_cu < 0) per_cu = occupancy(fit_block_kernel<T, NMAX>, kBlockThreads);
+  int64_t grid = (int64_t)per_cu * (kBlockThreads / threads) * ctx->cu_count;
+  if (grid > l.max_items) grid = l.max_items;
   if (grid < 1) grid = 1;
-  ProfScope ps(ctx, fam);
-  switch (b) {
-    case 0: hipLaunchKernelGGL((fit_kernel<T, 16>), dim3(grid), dim3(threads), 0, ctx->stream, P, io, wl); break;
-    case 1: hipLaunchKernelGGL((fit_kernel<T, 32>), dim3(grid), dim3(threads), 0, ctx->stream, P, io, wl); break;
-    case 2: hipLaunchKernelGGL((fit_kernel<T, 64>), dim3(grid), dim3(threads), 0, ctx->stream, P, io, wl); break;
-    default: hipLaunchKernelGGL((fit_kernel<T, 128>), dim3(grid), dim3(threads), 0, ctx->stream, P, io, wl); break;
-  }
+  ProfScope ps(ctx, l.fam);
+  hipLaunchKernelGGL((fit_block_kernel<T, NMAX>), dim3((unsigned)grid), dim3(threads), 0, ctx->stream, P, io,
+                     frames, l.list, l.count, l.next, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
+}
+
+// One solver launch for bucket b, in precision T.
+template <typename T>
+vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, const FitArgs& io,
+                          const FrameRec* frames, const Launch& l) {
+  if (wave) {
+    switch (b) {
+      case 0: return launch_wave<T, 16>(ctx, P, io, frames, l);
+      case 1: return launch_wave<T, 32>(ctx, P, io, frames, l);
+      default: return launch_wave<T, 64>(ctx, P, io, frames, l);
+    }
+  }
+  switch (b) {
+    case 0: return launch_block<T, 16>(ctx, P, io, frames, l);
+    case 1: return launch_block<T, 32>(ctx, P, io, frames, l);
+    case 2: return launch_block<T, 64>(ctx, P, io, frames, l);
+    default: return launch_block<T, 128>(ctx, P, io, frames, l);
+  }
 }
 
 }  // namespace
 
 size_t fit_work_bytes(int64_t n_vox) {
-  return Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) * 2 + Carver::round(sizeof(uint32_t) * 64) +
-         1024;
+  return Carver::round(sizeof(FrameRec) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kLists) +
+         Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(uint32_t) * 64) + 2048;
 }
 
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset) {
@@ -445,62 +619,60 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     return fail(ctx, VGPR_E_INVALID, "null device pointer");
   if (reinterpret_cast<uintptr_t>(a.out) & 15) return fail(ctx, VGPR_E_INVALID, "d_out must be 16-byte aligned");
   const int m = p->grid_side * p->grid_side;
-  if (kBucketCap[kNumBuckets - 1] + 2 > kFitThreads - 1)
-    return fail(ctx, VGPR_E_UNSUPPORTED, "workgroup too small");
   vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(a.n_vox));
   if (st != VGPR_OK) return st;
   Carver cv(static_cast<char*>(ctx->work.ptr) + work_offset);
-  int32_t* lists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
+  FrameRec* frames = cv.take<FrameRec>((size_t)a.n_vox);
+  int32_t* lists = cv.take<int32_t>((size_t)a.n_vox * kLists);
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
-  uint32_t* ctr = cv.take<uint32_t>(64);  // [0,4) counts, [4,8) next, [8,12) refine counts, [12,16) refine next
-  VGPR_HIP(ctx, hipMemsetAsync(ctr, 0, sizeof(uint32_t) * 64, ctx->stream));
+  uint32_t* ctr = cv.take<uint32_t>(64);  // [0,5) counts, [8,12) fetch, [16,20) re-solve counts, [24,28) fetch
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
 
-  {
-    ProfScope ps(ctx, "classify");
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)((a.n_vox + 255) / 256)), dim3(256), 0, ctx->stream, a.counts,
-                       a.n_vox, p->max_pts, p->min_pts, m, lists, ctr, a.n_vox, a.out, a.axis, a.status);
-  }
-  VGPR_HIP(ctx, hipGetLastError());
-
+  // the wave solver holds one query row per lane: grids up to 64 points
+  const bool wave_ok = m <= 64;
   FitParams P;
   P.cap = p->max_pts;
   P.tau = p->min_pts;
   P.nq = p->grid_side;
   P.m = m;
   P.ls_mode = p->ls_mode;
+  for (int b = 0; b < kNumBuckets; ++b) P.bcap[b] = kBucketCap[b];
   P.sf2 = p->signal_var;
   P.noise = p->noise_var;
   P.eta = p->converge_var;
   P.refine_thr = p->refine_threshold;
   P.s = (double)p->voxel_size;
   P.ell = (double)p->length_scale;
-
   const bool fp32 = p->precision == VGPR_PREC_FP32;
   P.mode = fp32 ? 0 : 2;
-  for (int b = 0; b < kNumBuckets; ++b) {
-    if (p->max_pts <= (b ? kBucketCap[b - 1] : 0)) break;
-    WorkList wl;
-    wl.list = lists + (size_t)b * a.n_vox;
-    wl.count = ctr + b;
-    wl.next = ctr + 4 + b;
-    wl.refine_list = rlists + (size_t)b * a.n_vox;
-    wl.refine_count = ctr + 8 + b;
-    st = fp32 ? launch_bucket<float>(ctx, b, P, a, wl, a.n_vox, kFamFit32[b])
-              : launch_bucket<double>(ctx, b, P, a, wl, a.n_vox, kFamFit64[b]);
+
+  Lists L{lists, ctr, a.n_vox};
+  {
+    ProfScope ps(ctx, "classify");
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((a.n_vox + 255) / 256)), dim3(256), 0, ctx->stream, P, a,
+                       frames, L);
+    VGPR_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(nan_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 4096)), dim3(256), 0,
+                       ctx->stream, P, a.out, L);
+    VGPR_HIP(ctx, hipGetLastError());
+  }
+  // largest voxels first so that their long solves start early
+  for (int b = kNumBuckets - 1; b >= 0; --b) {
+    if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
+    const bool wave = wave_ok && b < kNumBuckets - 1;
+    Launch l{lists + (size_t)b * a.n_vox, ctr + b, ctr + 8 + b, rlists + (size_t)b * a.n_vox, ctr + 16 + b,
+             a.n_vox, kFam[fp32 ? 0 : 2][b]};
+    st = fp32 ? launch_bucket<float>(ctx, b, wave, P, a, frames, l) : launch_bucket<double>(ctx, b, wave, P, a, frames, l);
     if (st != VGPR_OK) return st;
   }
   if (fp32) {
     FitParams R = P;
     R.mode = 1;
-    for (int b = 0; b < kNumBuckets; ++b) {
-      if (p->max_pts <= (b ? kBucketCap[b - 1] : 0)) break;
-      WorkList wl;
-      wl.list = rlists + (size_t)b * a.n_vox;
-      wl.count = ctr + 8 + b;
-      wl.next = ctr + 12 + b;
-      wl.refine_list = nullptr;
-      wl.refine_count = nullptr;
-      st = launch_bucket<double>(ctx, b, R, a, wl, a.n_vox, kFamRefine[b]);
+    for (int b = kNumBuckets - 1; b >= 0; --b) {
+      if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
+      const bool wave = wave_ok && b < kNumBuckets - 1;
+      Launch l{rlists + (size_t)b * a.n_vox, ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
+      st = launch_bucket<double>(ctx, b, wave, R, a, frames, l);
       if (st != VGPR_OK) return st;
     }
   }
