@@ -74,8 +74,9 @@ enum {
 
 /* Arithmetic of the posterior (kernel entries and factorisation). */
 enum {
-  VGPR_PREC_FP32 = 0,  /* FP32 build and LDL^T; voxels whose refinement score exceeds
-                          refine_threshold are re-solved in FP64 */
+  VGPR_PREC_FP32 = 0,  /* voxels of up to 16 points: FP32 build and LDL^T, and those whose
+                          refinement score exceeds refine_threshold are re-solved in FP64;
+                          larger voxels run in FP64 directly */
   VGPR_PREC_MIXED = 1, /* reserved: BF16-MFMA cross-covariance form (returns E_UNSUPPORTED) */
   VGPR_PREC_FP64 = 2   /* FP64 build and LDL^T for every voxel */
 };
@@ -230,7 +231,7 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
  * launches since the last read of that family, then resets it. Families:
  * "voxelize_key", "voxelize_sort" (all radix passes of a call),
  * "voxelize_segment", "classify", "fit_f32_n<C>" / "fit_f64_n<C>" (the
- * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 128) and
+ * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 96, 128) and
  * "refine_f64_n<C>" (the FP64 re-solve of flagged voxels of that bucket).
  */
 VGPR_API vgpr_status vgpr_profile_enable(vgpr_ctx* ctx, int on);

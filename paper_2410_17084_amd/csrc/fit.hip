@@ -538,9 +538,9 @@ int occupancy(K kernel, int threads) {
 
 // Timing family of each launch: pass (FP32, FP64 re-solve, FP64 only) and bucket capacity.
 const char* const kFam[3][kNumBuckets] = {
-    {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n128"},
-    {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n128"},
-    {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n128"}};
+    {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n96", "fit_f32_n128"},
+    {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n96", "refine_f64_n128"},
+    {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128"}};
 
 struct Launch {
   const int32_t* list;
@@ -601,6 +601,7 @@ vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, c
     case 0: return launch_block<T, 16>(ctx, P, io, frames, l);
     case 1: return launch_block<T, 32>(ctx, P, io, frames, l);
     case 2: return launch_block<T, 64>(ctx, P, io, frames, l);
+    case 3: return launch_block<T, 96>(ctx, P, io, frames, l);
     default: return launch_block<T, 128>(ctx, P, io, frames, l);
   }
 }
@@ -644,7 +645,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   P.s = (double)p->voxel_size;
   P.ell = (double)p->length_scale;
   const bool fp32 = p->precision == VGPR_PREC_FP32;
-  P.mode = fp32 ? 0 : 2;
+  P.mode = 2;
 
   Lists L{lists, ctr, a.n_vox};
   {
@@ -659,18 +660,22 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   // largest voxels first so that their long solves start early
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
-    const bool wave = wave_ok && b < kNumBuckets - 1;
+    const bool wave = wave_ok && b <= 2;
+    const bool in_fp32 = fp32 && b <= kFp32LastBucket;
+    FitParams Pb = P;
+    Pb.mode = in_fp32 ? 0 : 2;
     Launch l{lists + (size_t)b * a.n_vox, ctr + b, ctr + 8 + b, rlists + (size_t)b * a.n_vox, ctr + 16 + b,
-             a.n_vox, kFam[fp32 ? 0 : 2][b]};
-    st = fp32 ? launch_bucket<float>(ctx, b, wave, P, a, frames, l) : launch_bucket<double>(ctx, b, wave, P, a, frames, l);
+             a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
+    st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, frames, l)
+                 : launch_bucket<double>(ctx, b, wave, Pb, a, frames, l);
     if (st != VGPR_OK) return st;
   }
   if (fp32) {
     FitParams R = P;
     R.mode = 1;
-    for (int b = kNumBuckets - 1; b >= 0; --b) {
+    for (int b = std::min(kFp32LastBucket, kNumBuckets - 1); b >= 0; --b) {
       if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
-      const bool wave = wave_ok && b < kNumBuckets - 1;
+      const bool wave = wave_ok && b <= 2;
       Launch l{rlists + (size_t)b * a.n_vox, ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
       st = launch_bucket<double>(ctx, b, wave, R, a, frames, l);
       if (st != VGPR_OK) return st;

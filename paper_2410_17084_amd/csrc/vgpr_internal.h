@@ -23,8 +23,11 @@ constexpr int kMaxGridSide = 16;
 
 // Size buckets of the per-voxel solver: a voxel with n kept points runs in the
 // smallest bucket whose capacity is >= n.
-constexpr int kNumBuckets = 4;
-constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 128};
+constexpr int kNumBuckets = 5;
+constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 96, 128};
+// FP32 mode runs the buckets up to this index in float (with the FP64 re-solve of
+// flagged voxels); larger voxels are flagged so often that they go to FP64 directly.
+constexpr int kFp32LastBucket = 0;
 
 struct DeviceBuffer {
   void* ptr = nullptr;
