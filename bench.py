@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -124,6 +126,15 @@ def main():
     t0 = time.perf_counter()
     xyz_np, fo = synth.scan_batch(2, args.frames, n_beams=wl["n_beams"], n_az=wl["n_az"])
     log(f"generated {args.frames} scans, {len(xyz_np)} points in {time.perf_counter() - t0:.1f} s")
+
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
+        del src, dst
 
     prec = vgpr.PREC_FP32 if args.precision == "fp32" else vgpr.PREC_FP64
     p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
@@ -226,7 +237,8 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat[5:] if len(lat) > 10 else lat)
-    log(f"latency p50 {np.percentile(lat, 50):.3f} ms")
+    if len(lat):
+        log(f"latency p50 {np.percentile(lat, 50):.3f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,8 +260,9 @@ def main():
                    "parallelism": "1 GPU"},
         "dense_pts_per_s": dense,
         "solved_per_step": n_solved, "refined_per_step": int(refined.sum()),
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "frames": int(len(lat)), "what": "one scan: voxelize + fit_predict + sync"},
+        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "frames": int(len(lat)), "what": "one scan: voxelize + fit_predict + sync"}
+                       if len(lat) else None),
         "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -163,7 +163,11 @@ VGPR_API vgpr_status vgpr_voxelize(vgpr_ctx* ctx, const float* d_xyz, int64_t n_
  *
  * For voxel v, its kept points are d_xyz[d_perm[d_offsets[v] + i]],
  * i < min(d_counts[v], max_pts) (d_perm may be NULL: then the points are
- * d_xyz[d_offsets[v] + i]). With n kept points and n >= min_pts:
+ * d_xyz[d_offsets[v] + i]). n_pts is the number of points d_xyz holds (the
+ * length of d_perm); it sizes a staging scratch of 16 * n_pts bytes. Voxels
+ * must satisfy 0 <= d_offsets[v] and d_offsets[v] + min(d_counts[v], max_pts)
+ * <= n_pts; a voxel that does not is skipped (status 0, NaN rows).
+ * With n kept points and n >= min_pts:
  *  - PCA (double): centroid c, covariance (1/n) sum (p - c)(p - c)^T, eigenvector
  *    of its smallest eigenvalue v; value axis a = argmax_k |v_k| (ties to the
  *    lower index); parameter axes (u, w) = (Y,Z), (Z,X), (X,Y) for a = X, Y, Z.
@@ -182,7 +186,7 @@ VGPR_API vgpr_status vgpr_voxelize(vgpr_ctx* ctx, const float* d_xyz, int64_t n_
  *   d_status[n_vox]       VGPR_ST_* bits
  * Asynchronous: returns after enqueueing.
  */
-VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, const uint64_t* d_keys,
+VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, const uint64_t* d_keys,
                              const int32_t* d_offsets, const int32_t* d_counts,
                              const int32_t* d_perm, int64_t n_vox, const float* d_noise_var,
                              const vgpr_params* params, float* d_out, int8_t* d_axis,

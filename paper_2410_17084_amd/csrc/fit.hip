@@ -2,12 +2,14 @@
 //
 // Three kernels per call (plus a re-solve pass in FP32 mode):
 //
-// 1. prep (one thread per voxel): kept count n, tau test, the PCA frame of
-//    Alg. 1 in double (centroid, covariance, cyclic Jacobi eigen-solve, value
-//    axis = world axis closest to the smallest-eigenvalue eigenvector, cyclic
-//    parameter axes, near-tie flag, optional per-voxel length scale) written
-//    as a 48-byte record, and the voxel appended to its size bucket with one
-//    atomic per wavefront and bucket.
+// 1. prep (one thread per voxel): kept count n, tau test, a slot in the
+//    voxel's size bucket (one atomic per wavefront and bucket), the PCA frame
+//    of Alg. 1 in double (centroid, covariance, cyclic Jacobi eigen-solve,
+//    value axis = world axis closest to the smallest-eigenvalue eigenvector,
+//    cyclic parameter axes, near-tie flag, optional per-voxel length scale)
+//    written as a 64-byte slot record, and the kept points staged as float4
+//    (x, y, z, noise variance) at their sorted positions, so that the solvers
+//    read one record and one coalesced row of points per voxel.
 // 2. solve: the posterior of Eq. (3) from an LDL^T elimination of the
 //    augmented system whose rows are
 //          [ K + S | f~ ]   n data rows      (S = noise variances on the diagonal)
@@ -73,8 +75,18 @@ struct FrameRec {
   int n;            // kept points
 };
 
+// One bucket slot: the voxel's frame and where its staged points are.
+struct SlotRec {
+  FrameRec fr;
+  int v;            // voxel index (output row block)
+  int off;          // first staged point (the voxel's sorted offset)
+  int cnt;          // points before the cap
+  int pad;
+};
+
 struct Lists {
-  int32_t* list;         // kLists lists of `stride` entries
+  SlotRec* recs;         // kNumBuckets lists of `stride` slot records
+  int32_t* nan_list;     // voxels below tau
   uint32_t* count;       // kLists counters
   int64_t stride;
 };
@@ -139,92 +151,30 @@ __device__ __forceinline__ float pick(int axis, float x, float y, float z) { ret
 // ---------------------------------------------------------------------------
 // 1. prep: tau test, PCA frame, bucketing (one thread per voxel)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, FrameRec* __restrict__ frames,
+__global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, float4* __restrict__ staged,
                                                    Lists L) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = v < io.n_vox;
-  int lst = -1;
+  int lst = -1, n = 0, c = 0, off = 0;
   if (valid) {
-    const int c = io.counts[v];
-    const int n = c < P.cap ? c : P.cap;
-    if (n < P.tau) {
-      io.status[v] = (uint8_t)(VGPR_ST_BELOW_TAU | (c > P.cap ? VGPR_ST_CAPPED : 0));
+    c = io.counts[v];
+    off = io.offsets[v];
+    n = c < P.cap ? c : P.cap;
+    if (n < P.tau || off < 0 || (int64_t)off + n > io.n_pts) {
+      // below tau (type (a)); a voxel whose points lie outside [0, n_pts) is not solved either
+      const bool in_range = off >= 0 && (int64_t)off + n <= io.n_pts;
+      io.status[v] = in_range ? (uint8_t)(VGPR_ST_BELOW_TAU | (c > P.cap ? VGPR_ST_CAPPED : 0)) : (uint8_t)0;
       io.axis[v] = -1;
       lst = kNanList;
     } else {
-      const int off = io.offsets[v];
-      const int* perm = io.perm;
-      // one pass about the first point: S1 = sum d, S2 = sum d d^T, d = p - p0
-      const int i0 = perm ? perm[off] : off;
-      const double p0x = io.xyz[3 * (size_t)i0], p0y = io.xyz[3 * (size_t)i0 + 1], p0z = io.xyz[3 * (size_t)i0 + 2];
-      double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
-      for (int i = 1; i < n; ++i) {
-        const int idx = perm ? perm[off + i] : off + i;
-        const double d0 = (double)io.xyz[3 * (size_t)idx] - p0x;
-        const double d1 = (double)io.xyz[3 * (size_t)idx + 1] - p0y;
-        const double d2 = (double)io.xyz[3 * (size_t)idx + 2] - p0z;
-        s0 += d0; s1 += d1; s2 += d2;
-        a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
-        a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
-      }
-      const double inv_n = 1.0 / (double)n;
-      const double m0 = s0 * inv_n, m1 = s1 * inv_n, m2 = s2 * inv_n;
-      double A[3][3];
-      A[0][0] = a00 * inv_n - m0 * m0;
-      A[0][1] = A[1][0] = a01 * inv_n - m0 * m1;
-      A[0][2] = A[2][0] = a02 * inv_n - m0 * m2;
-      A[1][1] = a11 * inv_n - m1 * m1;
-      A[1][2] = A[2][1] = a12 * inv_n - m1 * m2;
-      A[2][2] = a22 * inv_n - m2 * m2;
-      const double tr = A[0][0] + A[1][1] + A[2][2];
-      double w[3], V[3][3];
-      jacobi3(A, w, V);
-      // eigenvector of the smallest eigenvalue (ties to the lower index)
-      const int imin = (w[1] < w[0]) ? ((w[2] < w[1]) ? 2 : 1) : ((w[2] < w[0]) ? 2 : 0);
-      const double v0 = imin == 0 ? V[0][0] : (imin == 1 ? V[0][1] : V[0][2]);
-      const double v1 = imin == 0 ? V[1][0] : (imin == 1 ? V[1][1] : V[1][2]);
-      const double v2 = imin == 0 ? V[2][0] : (imin == 1 ? V[2][1] : V[2][2]);
-      const double wlo = fmin(fmin(w[0], w[1]), w[2]);
-      const double whi = fmax(fmax(w[0], w[1]), w[2]);
-      const double wmid = fmax(fmin(w[0], w[1]), fmin(fmax(w[0], w[1]), w[2]));
-      const double b0 = fabs(v0), b1 = fabs(v1), b2 = fabs(v2);
-      int ax = 0;
-      double best = b0;
-      if (b1 > best) { ax = 1; best = b1; }
-      if (b2 > best) { ax = 2; best = b2; }
-      const double second = (ax == 0) ? fmax(b1, b2) : (ax == 1 ? fmax(b0, b2) : fmax(b0, b1));
-      const int tie = (best - second < 1e-6) || (wmid - wlo <= 1e-8 * tr);
-      const int u = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
-      const int wv = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
-      double ell = P.ell;
-      if (P.ls_mode == 1) {
-        const double e = sqrt(3.0) * sqrt(fmax((wmid + whi) * 0.5, 0.0));
-        ell = fmin(fmax(e, 0.05 * P.s), 2.0 * P.s);
-      }
-      const uint64_t key = io.keys[v];
-      const int64_t mask = (int64_t(1) << kKeyFieldBits) - 1;
-      const int kx = (int)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias);
-      const int ky = (int)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias);
-      const int kz = (int)((int64_t)(key & mask) - kKeyBias);
-      FrameRec fr;
-      fr.ku = u == 0 ? kx : (u == 1 ? ky : kz);
-      fr.kw = wv == 0 ? kx : (wv == 1 ? ky : kz);
-      const double pa = ax == 0 ? p0x : (ax == 1 ? p0y : p0z);
-      const double ma = ax == 0 ? m0 : (ax == 1 ? m1 : m2);
-      fr.mu = pa + ma;
-      fr.anc_u = (double)fr.ku * P.s;
-      fr.anc_w = (double)fr.kw * P.s;
-      fr.lam = 1.0 / (2.0 * ell * ell);
-      fr.axes = ax | (u << 2) | (wv << 4) | (tie << 6);
-      fr.n = n;
-      frames[v] = fr;
       lst = 0;
       while (lst < kNumBuckets - 1 && n > P.bcap[lst]) ++lst;
     }
   }
-  // append to the lists with one atomic per wavefront and list
+  // slot in the voxel's list: one atomic per wavefront and list
   const int lane = lane_id();
   const unsigned long long lt = (1ull << lane) - 1ull;
+  int slot = 0;
 #pragma unroll
   for (int l = 0; l < kLists; ++l) {
     const unsigned long long mk = __ballot(lst == l);
@@ -233,9 +183,86 @@ __global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, Fram
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(&L.count[l], (uint32_t)__popcll(mk));
       base = __shfl(base, leader, 64);
-      if (lst == l) L.list[l * L.stride + base + __popcll(mk & lt)] = (int32_t)v;
+      if (lst == l) slot = (int)(base + __popcll(mk & lt));
     }
   }
+  if (lst == kNanList) L.nan_list[slot] = (int32_t)v;
+  if (lst < 0 || lst == kNanList) return;
+
+  // stage the kept points and accumulate the covariance about the first point:
+  // S1 = sum d, S2 = sum d d^T with d = p - p0
+  const int* perm = io.perm;
+  const int i0 = perm ? perm[off] : off;
+  const float x0 = io.xyz[3 * (size_t)i0], y0 = io.xyz[3 * (size_t)i0 + 1], z0 = io.xyz[3 * (size_t)i0 + 2];
+  staged[off] = make_float4(x0, y0, z0, io.noise ? io.noise[i0] : P.noise);
+  const double p0x = x0, p0y = y0, p0z = z0;
+  double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+  for (int i = 1; i < n; ++i) {
+    const int idx = perm ? perm[off + i] : off + i;
+    const float x = io.xyz[3 * (size_t)idx], y = io.xyz[3 * (size_t)idx + 1], z = io.xyz[3 * (size_t)idx + 2];
+    staged[off + i] = make_float4(x, y, z, io.noise ? io.noise[idx] : P.noise);
+    const double d0 = (double)x - p0x;
+    const double d1 = (double)y - p0y;
+    const double d2 = (double)z - p0z;
+    s0 += d0; s1 += d1; s2 += d2;
+    a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
+    a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
+  }
+  const double inv_n = 1.0 / (double)n;
+  const double m0 = s0 * inv_n, m1 = s1 * inv_n, m2 = s2 * inv_n;
+  double A[3][3];
+  A[0][0] = a00 * inv_n - m0 * m0;
+  A[0][1] = A[1][0] = a01 * inv_n - m0 * m1;
+  A[0][2] = A[2][0] = a02 * inv_n - m0 * m2;
+  A[1][1] = a11 * inv_n - m1 * m1;
+  A[1][2] = A[2][1] = a12 * inv_n - m1 * m2;
+  A[2][2] = a22 * inv_n - m2 * m2;
+  const double tr = A[0][0] + A[1][1] + A[2][2];
+  double w[3], V[3][3];
+  jacobi3(A, w, V);
+  // eigenvector of the smallest eigenvalue (ties to the lower index)
+  const int imin = (w[1] < w[0]) ? ((w[2] < w[1]) ? 2 : 1) : ((w[2] < w[0]) ? 2 : 0);
+  const double v0 = imin == 0 ? V[0][0] : (imin == 1 ? V[0][1] : V[0][2]);
+  const double v1 = imin == 0 ? V[1][0] : (imin == 1 ? V[1][1] : V[1][2]);
+  const double v2 = imin == 0 ? V[2][0] : (imin == 1 ? V[2][1] : V[2][2]);
+  const double wlo = fmin(fmin(w[0], w[1]), w[2]);
+  const double whi = fmax(fmax(w[0], w[1]), w[2]);
+  const double wmid = fmax(fmin(w[0], w[1]), fmin(fmax(w[0], w[1]), w[2]));
+  const double b0 = fabs(v0), b1 = fabs(v1), b2 = fabs(v2);
+  int ax = 0;
+  double best = b0;
+  if (b1 > best) { ax = 1; best = b1; }
+  if (b2 > best) { ax = 2; best = b2; }
+  const double second = (ax == 0) ? fmax(b1, b2) : (ax == 1 ? fmax(b0, b2) : fmax(b0, b1));
+  const int tie = (best - second < 1e-6) || (wmid - wlo <= 1e-8 * tr);
+  const int u = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
+  const int wv = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
+  double ell = P.ell;
+  if (P.ls_mode == 1) {
+    const double e = sqrt(3.0) * sqrt(fmax((wmid + whi) * 0.5, 0.0));
+    ell = fmin(fmax(e, 0.05 * P.s), 2.0 * P.s);
+  }
+  const uint64_t key = io.keys[v];
+  const int64_t mask = (int64_t(1) << kKeyFieldBits) - 1;
+  const int kx = (int)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias);
+  const int ky = (int)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias);
+  const int kz = (int)((int64_t)(key & mask) - kKeyBias);
+  SlotRec r;
+  r.fr.ku = u == 0 ? kx : (u == 1 ? ky : kz);
+  r.fr.kw = wv == 0 ? kx : (wv == 1 ? ky : kz);
+  const double pa = ax == 0 ? p0x : (ax == 1 ? p0y : p0z);
+  const double ma = ax == 0 ? m0 : (ax == 1 ? m1 : m2);
+  r.fr.mu = pa + ma;
+  r.fr.anc_u = (double)r.fr.ku * P.s;
+  r.fr.anc_w = (double)r.fr.kw * P.s;
+  r.fr.lam = 1.0 / (2.0 * ell * ell);
+  r.fr.axes = ax | (u << 2) | (wv << 4) | (tie << 6);
+  r.fr.n = n;
+  r.v = (int)v;
+  r.off = off;
+  r.cnt = c;
+  r.pad = 0;
+  L.recs[lst * L.stride + slot] = r;
 }
 
 // Zero the list counters with a kernel (no memset node when a caller captures the call in a graph).
@@ -254,23 +281,23 @@ __global__ void __launch_bounds__(256) nan_kernel(FitParams P, float* __restrict
   const int count = (int)L.count[kNanList];
   const float nan = __int_as_float(0x7fc00000);
   for (int it = gw; it < count; it += nw) {
-    const int v = L.list[kNanList * L.stride + it];
+    const int v = L.nan_list[it];
     float4* o = reinterpret_cast<float4*>(out) + (size_t)v * P.m;
     for (int q = lane; q < P.m; q += 64) o[q] = make_float4(nan, nan, nan, nan);
   }
 }
 
 // Status of a solved (or flagged) voxel; lane / thread 0 only.
-__device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& io, int v, int cnt, int axes,
-                                             bool failed, bool flag, float maxvar, int32_t* rlist,
+__device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& io, int v, int slot, int cnt,
+                                             int axes, bool failed, bool flag, float maxvar, int32_t* rlist,
                                              uint32_t* rcount) {
   uint8_t st = VGPR_ST_SOLVED;
   if (cnt > P.cap) st |= VGPR_ST_CAPPED;
   if ((axes >> 6) & 1) st |= VGPR_ST_AXIS_TIE;
   if (flag) {
     // FP32 pass: hand the voxel to the FP64 re-solve list
-    const uint32_t slot = atomicAdd(rcount, 1u);
-    rlist[slot] = v;
+    const uint32_t k = atomicAdd(rcount, 1u);
+    rlist[k] = slot;
     if (failed) st |= VGPR_ST_FACTOR_FAIL;
   } else {
     if (P.mode == 1) st |= VGPR_ST_REFINED | (io.status[v] & VGPR_ST_FACTOR_FAIL);
@@ -303,33 +330,50 @@ __device__ __forceinline__ float4 out_row(int ax, int u, float mv, float gu, flo
 // ---------------------------------------------------------------------------
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
-                                                                const FrameRec* __restrict__ frames,
-                                                                const int32_t* __restrict__ list,
+                                                                const SlotRec* __restrict__ recs,
+                                                                const float4* __restrict__ staged,
+                                                                const int32_t* __restrict__ slots,
                                                                 const uint32_t* __restrict__ count,
                                                                 int32_t* __restrict__ rlist,
                                                                 uint32_t* __restrict__ rcount) {
   const int lane = lane_id();
-  const int gw = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  // wavefront-uniform indices (scalar registers): record loads become scalar loads
+  const int gw = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
   const int cnt_items = (int)*count;
   const T sf2 = (T)P.sf2;
-  for (int it = gw; it < cnt_items; it += nw) {
-    const int v = list[it];
-    const FrameRec fr = frames[v];
+  // two-stage software pipeline: the record of item it + 2 nw and the points of
+  // item it + nw are in flight while item it is solved
+  int it = gw;
+  SlotRec rn{};
+  float4 pn = make_float4(0.f, 0.f, 0.f, 0.f);
+  SlotRec rnn{};
+  if (it < cnt_items) {
+    rn = recs[slots ? slots[it] : it];
+    if (lane < rn.fr.n) pn = staged[rn.off + lane];
+  }
+  if (it + nw < cnt_items) rnn = recs[slots ? slots[it + nw] : it + nw];
+  for (; it < cnt_items; it += nw) {
+    const SlotRec r = rn;
+    const float4 pt = pn;
+    if (it + nw < cnt_items) {
+      rn = rnn;
+      if (lane < rn.fr.n) pn = staged[rn.off + lane];
+    }
+    if (it + 2 * nw < cnt_items) rnn = recs[slots ? slots[it + 2 * nw] : it + 2 * nw];
+    const FrameRec& fr = r.fr;
+    const int v = r.v;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
-    const int off = io.offsets[v];
-    const int cnt = io.counts[v];
+    const int cnt = r.cnt;
     const T lam = (T)fr.lam;
     // this lane's data point (lanes < n)
-    T xu = 0, xw = 0, fv = 0, nz = (T)P.noise;
+    T xu = 0, xw = 0, fv = 0, nz = 0;
     if (lane < n) {
-      const int idx = io.perm ? io.perm[off + lane] : off + lane;
-      const float px = io.xyz[3 * (size_t)idx], py = io.xyz[3 * (size_t)idx + 1], pz = io.xyz[3 * (size_t)idx + 2];
-      xu = (T)((double)pick(u, px, py, pz) - fr.anc_u);
-      xw = (T)((double)pick(wax, px, py, pz) - fr.anc_w);
-      fv = (T)((double)pick(ax, px, py, pz) - fr.mu);
-      if (io.noise) nz = (T)io.noise[idx];
+      xu = (T)((double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u);
+      xw = (T)((double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w);
+      fv = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
+      nz = (T)pt.w;
     }
     // this lane's query point (lanes < m)
     float gu = 0.f, gwv = 0.f;
@@ -393,7 +437,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mv_lane = fmaxf(mv_lane, __shfl_xor(mv_lane, d, 64));
-    if (lane == 0) finish_voxel(P, io, v, cnt, fr.axes, failed, flag, mv_lane, rlist, rcount);
+    if (lane == 0) finish_voxel(P, io, v, slots ? slots[it] : it, cnt, fr.axes, failed, flag, mv_lane, rlist, rcount);
   }
 }
 
@@ -402,13 +446,14 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
 // ---------------------------------------------------------------------------
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, FitArgs io,
-                                                                  const FrameRec* __restrict__ frames,
-                                                                  const int32_t* __restrict__ list,
+                                                                  const SlotRec* __restrict__ recs,
+                                                                  const float4* __restrict__ staged,
+                                                                  const int32_t* __restrict__ slots,
                                                                   const uint32_t* __restrict__ count,
                                                                   uint32_t* __restrict__ next,
                                                                   int32_t* __restrict__ rlist,
                                                                   uint32_t* __restrict__ rcount) {
-  __shared__ T su[NMAX + 4], sw[NMAX + 4], sf[NMAX + 4];
+  __shared__ T su[NMAX + 4], sw[NMAX + 4], sf[NMAX + 4], sn[NMAX + 4];
   __shared__ __attribute__((aligned(16))) T col[2][NMAX + 8];
   __shared__ T piv[2][2];
   __shared__ int s_item;
@@ -429,19 +474,19 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
     __syncthreads();
     const int item = s_item;
     if (item >= cnt_items) break;
-    const int v = list[item];
-    const FrameRec fr = frames[v];
+    const int slot = slots ? slots[item] : item;
+    const SlotRec r = recs[slot];
+    const FrameRec& fr = r.fr;
+    const int v = r.v;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
-    const int off = io.offsets[v];
-    const int cnt = io.counts[v];
-    const int* perm = io.perm;
+    const int cnt = r.cnt;
     for (int i = tid; i < n; i += NT) {
-      const int idx = perm ? perm[off + i] : off + i;
-      const float px = io.xyz[3 * (size_t)idx], py = io.xyz[3 * (size_t)idx + 1], pz = io.xyz[3 * (size_t)idx + 2];
-      su[i] = (T)((double)pick(u, px, py, pz) - fr.anc_u);
-      sw[i] = (T)((double)pick(wax, px, py, pz) - fr.anc_w);
-      sf[i] = (T)((double)pick(ax, px, py, pz) - fr.mu);
+      const float4 pt = staged[r.off + i];
+      su[i] = (T)((double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u);
+      sw[i] = (T)((double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w);
+      sf[i] = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
+      sn[i] = (T)pt.w;
     }
     __syncthreads();
 
@@ -459,8 +504,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
         xu = su[tid];
         xw = sw[tid];
         fy = sf[tid];
-        nz = (T)P.noise;
-        if (io.noise) nz = (T)io.noise[perm ? perm[off + tid] : off + tid];
+        nz = sn[tid];
       } else if (is_query) {
         query_coords(P, fr, q, &gu, &gwv);
         xu = (T)((double)gu - fr.anc_u);
@@ -523,7 +567,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
     }
     __syncthreads();
     if (tid == 0)
-      finish_voxel(P, io, v, cnt, fr.axes, s_flag == 2 || (!s_flag && failed), s_flag != 0,
+      finish_voxel(P, io, v, slot, cnt, fr.axes, s_flag == 2 || (!s_flag && failed), s_flag != 0,
                    __uint_as_float(s_maxvar), rlist, rcount);
     __syncthreads();
   }
@@ -543,7 +587,8 @@ const char* const kFam[3][kNumBuckets] = {
     {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128"}};
 
 struct Launch {
-  const int32_t* list;
+  const SlotRec* recs;
+  const int32_t* slots;      // nullable: item -> slot indirection (re-solve lists)
   const uint32_t* count;
   uint32_t* next;
   int32_t* rlist;
@@ -553,7 +598,7 @@ struct Launch {
 };
 
 template <typename T, int NMAX>
-vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const FrameRec* frames,
+vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const float4* staged,
                         const Launch& l) {
   static int per_cu = -1;
   if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX>, kWaveThreads);
@@ -563,13 +608,13 @@ vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, co
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam);
   hipLaunchKernelGGL((fit_wave_kernel<T, NMAX>), dim3((unsigned)grid), dim3(kWaveThreads), 0, ctx->stream, P, io,
-                     frames, l.list, l.count, l.rlist, l.rcount);
+                     l.recs, staged, l.slots, l.count, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
 
 template <typename T, int NMAX>
-vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const FrameRec* frames,
+vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const float4* staged,
                          const Launch& l) {
   int threads = NMAX + P.m;
   if (threads > kBlockThreads) threads = kBlockThreads;
@@ -581,7 +626,7 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam);
   hipLaunchKernelGGL((fit_block_kernel<T, NMAX>), dim3((unsigned)grid), dim3(threads), 0, ctx->stream, P, io,
-                     frames, l.list, l.count, l.next, l.rlist, l.rcount);
+                     l.recs, staged, l.slots, l.count, l.next, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -589,42 +634,45 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
 // One solver launch for bucket b, in precision T.
 template <typename T>
 vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, const FitArgs& io,
-                          const FrameRec* frames, const Launch& l) {
+                          const float4* staged, const Launch& l) {
   if (wave) {
     switch (b) {
-      case 0: return launch_wave<T, 16>(ctx, P, io, frames, l);
-      case 1: return launch_wave<T, 32>(ctx, P, io, frames, l);
-      default: return launch_wave<T, 64>(ctx, P, io, frames, l);
+      case 0: return launch_wave<T, 16>(ctx, P, io, staged, l);
+      case 1: return launch_wave<T, 32>(ctx, P, io, staged, l);
+      default: return launch_wave<T, 64>(ctx, P, io, staged, l);
     }
   }
   switch (b) {
-    case 0: return launch_block<T, 16>(ctx, P, io, frames, l);
-    case 1: return launch_block<T, 32>(ctx, P, io, frames, l);
-    case 2: return launch_block<T, 64>(ctx, P, io, frames, l);
-    case 3: return launch_block<T, 96>(ctx, P, io, frames, l);
-    default: return launch_block<T, 128>(ctx, P, io, frames, l);
+    case 0: return launch_block<T, 16>(ctx, P, io, staged, l);
+    case 1: return launch_block<T, 32>(ctx, P, io, staged, l);
+    case 2: return launch_block<T, 64>(ctx, P, io, staged, l);
+    case 3: return launch_block<T, 96>(ctx, P, io, staged, l);
+    default: return launch_block<T, 128>(ctx, P, io, staged, l);
   }
 }
 
 }  // namespace
 
-size_t fit_work_bytes(int64_t n_vox) {
-  return Carver::round(sizeof(FrameRec) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kLists) +
-         Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(uint32_t) * 64) + 2048;
+size_t fit_work_bytes(int64_t n_vox, int64_t n_pts) {
+  return Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
+         Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
+         Carver::round(sizeof(uint32_t) * 64) + 4096;
 }
 
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset) {
   if (a.n_vox < 0 || a.n_vox >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_vox out of range");
+  if (a.n_pts < 0 || a.n_pts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_pts out of range");
   if (a.n_vox == 0) return VGPR_OK;
   if (!a.xyz || !a.keys || !a.offsets || !a.counts || !a.out || !a.axis || !a.status)
     return fail(ctx, VGPR_E_INVALID, "null device pointer");
   if (reinterpret_cast<uintptr_t>(a.out) & 15) return fail(ctx, VGPR_E_INVALID, "d_out must be 16-byte aligned");
   const int m = p->grid_side * p->grid_side;
-  vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(a.n_vox));
+  vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(a.n_vox, a.n_pts));
   if (st != VGPR_OK) return st;
   Carver cv(static_cast<char*>(ctx->work.ptr) + work_offset);
-  FrameRec* frames = cv.take<FrameRec>((size_t)a.n_vox);
-  int32_t* lists = cv.take<int32_t>((size_t)a.n_vox * kLists);
+  SlotRec* recs = cv.take<SlotRec>((size_t)a.n_vox * kNumBuckets);
+  float4* staged = cv.take<float4>((size_t)a.n_pts);
+  int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   uint32_t* ctr = cv.take<uint32_t>(64);  // [0,5) counts, [8,12) fetch, [16,20) re-solve counts, [24,28) fetch
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
@@ -647,11 +695,11 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   const bool fp32 = p->precision == VGPR_PREC_FP32;
   P.mode = 2;
 
-  Lists L{lists, ctr, a.n_vox};
+  Lists L{recs, nan_list, ctr, a.n_vox};
   {
     ProfScope ps(ctx, "classify");
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((a.n_vox + 255) / 256)), dim3(256), 0, ctx->stream, P, a,
-                       frames, L);
+                       staged, L);
     VGPR_HIP(ctx, hipGetLastError());
     hipLaunchKernelGGL(nan_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 4096)), dim3(256), 0,
                        ctx->stream, P, a.out, L);
@@ -664,10 +712,10 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     const bool in_fp32 = fp32 && b <= kFp32LastBucket;
     FitParams Pb = P;
     Pb.mode = in_fp32 ? 0 : 2;
-    Launch l{lists + (size_t)b * a.n_vox, ctr + b, ctr + 8 + b, rlists + (size_t)b * a.n_vox, ctr + 16 + b,
+    Launch l{recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b, rlists + (size_t)b * a.n_vox, ctr + 16 + b,
              a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
-    st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, frames, l)
-                 : launch_bucket<double>(ctx, b, wave, Pb, a, frames, l);
+    st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
+                 : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
     if (st != VGPR_OK) return st;
   }
   if (fp32) {
@@ -676,8 +724,9 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     for (int b = std::min(kFp32LastBucket, kNumBuckets - 1); b >= 0; --b) {
       if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
       const bool wave = wave_ok && b <= 2;
-      Launch l{rlists + (size_t)b * a.n_vox, ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
-      st = launch_bucket<double>(ctx, b, wave, R, a, frames, l);
+      Launch l{recs + (size_t)b * a.n_vox, rlists + (size_t)b * a.n_vox, ctr + 16 + b, ctr + 24 + b, nullptr, nullptr,
+               a.n_vox, kFam[1][b]};
+      st = launch_bucket<double>(ctx, b, wave, R, a, staged, l);
       if (st != VGPR_OK) return st;
     }
   }
@@ -686,7 +735,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
 
 }  // namespace vgpr
 
-extern "C" vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, const uint64_t* d_keys,
+extern "C" vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, const uint64_t* d_keys,
                                         const int32_t* d_offsets, const int32_t* d_counts, const int32_t* d_perm,
                                         int64_t n_vox, const float* d_noise_var, const vgpr_params* params,
                                         float* d_out, int8_t* d_axis, uint8_t* d_status) {
@@ -694,6 +743,6 @@ extern "C" vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, const
   vgpr_status st = vgpr::check_params(ctx, params);
   if (st != VGPR_OK) return st;
   if (hipSetDevice(ctx->device) != hipSuccess) return vgpr::fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
-  vgpr::FitArgs a{d_xyz, d_keys, d_offsets, d_counts, d_perm, d_noise_var, n_vox, d_out, d_axis, d_status};
+  vgpr::FitArgs a{d_xyz, n_pts, d_keys, d_offsets, d_counts, d_perm, d_noise_var, n_vox, d_out, d_axis, d_status};
   return vgpr::fit_predict_impl(ctx, a, params, 0);
 }

@@ -119,6 +119,7 @@ vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, cons
 // `work_offset` is where in ctx->work this call may start carving scratch.
 struct FitArgs {
   const float* xyz;
+  int64_t n_pts;             // points d_xyz holds (and d_perm indexes)
   const uint64_t* keys;
   const int32_t* offsets;
   const int32_t* counts;
@@ -129,7 +130,7 @@ struct FitArgs {
   int8_t* axis;
   uint8_t* status;
 };
-size_t fit_work_bytes(int64_t n_vox);
+size_t fit_work_bytes(int64_t n_vox, int64_t n_pts);
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset);
 
 }  // namespace vgpr

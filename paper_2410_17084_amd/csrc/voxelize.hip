@@ -3,15 +3,20 @@
 // 1. key kernel: one thread per point computes the packed 64-bit voxel key
 //    (one IEEE double multiply by 1/s and a floor per axis) and seeds the
 //    index array; non-finite points get the all-ones sentinel key.
-// 2. stable LSD radix sort of (key, index), 8-bit digits, three kernels per
-//    pass (tile histograms, per-digit scan across tiles, ranked scatter).
+// 2. stable LSD radix sort of (sort key, index), 8-bit digits, three kernels
+//    per pass (tile histograms, per-digit scan across tiles, ranked scatter).
 //    Ranks inside a tile come from 64-lane ballots, so equal digits keep
-//    their input order and the sort is stable. A batch of frames is sorted
-//    by (frame, key): frame digits are extra, most-significant passes whose
-//    digit is read from the point's original index.
+//    their input order and the sort is stable. The sort key is a compacted
+//    form of the voxel key with the same order: each axis index minus the
+//    batch minimum, packed into just the bits the batch's ranges need, then
+//    an invalid-point bit, then the frame index (a batch is sorted by
+//    (frame, key)). A spinning scan needs ~24 key bits, so three or four
+//    passes instead of eight. If the packed form does not fit 64 bits the
+//    frame index gets its own extra passes, read from the point's index.
 // 3. segmentation: voxel heads (key change or frame start), a scan over the
 //    heads, and scatter of keys / starts / counts; per-frame voxel ranges.
 #include <algorithm>
+#include <climits>
 
 #include "scan.cuh"
 #include "vgpr_internal.h"
@@ -25,7 +30,16 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 elements per block
 constexpr int kSortWaves = kSortThreads / 64;
 
 // Result words read back to the host after a voxelize call.
-enum { R_NVOX = 0, R_INVALID = 1, R_RANGE = 2, R_FRAMES = 4 };
+enum { R_NVOX = 0, R_INVALID = 1, R_RANGE = 2, R_NVALID = 3, R_MIN = 4, R_MAX = 7, R_FRAMES = 10 };
+
+// Compacted sort key: fields (k - kmin) in bx / by / bz bits (x highest), the
+// invalid flag at bit B = bx + by + bz, the frame index above it if embedded.
+struct KeyForm {
+  int bx, by, bz, B;
+  int embed;           // frame index in bits [B + 1, ...)
+  int key_passes;      // radix passes over the packed key
+  int64_t mn[3];       // per-axis minimum voxel index
+};
 
 __device__ __forceinline__ int frame_of(uint32_t idx, const int64_t* fo, int nf) {
   // largest f with fo[f] <= idx, for nf frames (fo has nf + 1 entries)
@@ -37,17 +51,31 @@ __device__ __forceinline__ int frame_of(uint32_t idx, const int64_t* fo, int nf)
   return lo;
 }
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t val, int pass, const int64_t* fo, int nf) {
-  if (pass < 8) return (uint32_t)(key >> (8 * pass)) & 0xFFu;
-  return ((uint32_t)frame_of(val, fo, nf) >> (8 * (pass - 8))) & 0xFFu;
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t val, int pass, int key_passes, const int64_t* fo,
+                                             int nf) {
+  if (pass < key_passes) return (uint32_t)(key >> (8 * pass)) & 0xFFu;
+  return ((uint32_t)frame_of(val, fo, nf) >> (8 * (pass - key_passes))) & 0xFFu;
 }
 
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+// Voxel key of every point (packed, biased) and per-block min / max voxel index per axis.
 __global__ void __launch_bounds__(256) key_kernel(const float* __restrict__ xyz, int n, double inv_s,
-                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                  uint64_t* __restrict__ keys, int* __restrict__ part,
                                                   unsigned long long* __restrict__ res) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool invalid = false;
   bool range_err = false;
+  int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
   if (i < n) {
     const float x = xyz[3 * (size_t)i + 0];
     const float y = xyz[3 * (size_t)i + 1];
@@ -61,16 +89,19 @@ __global__ void __launch_bounds__(256) key_kernel(const float* __restrict__ xyz,
       if (fabs(kx) > lim || fabs(ky) > lim || fabs(kz) > lim) {
         range_err = true;
       } else {
-        const uint64_t bx = (uint64_t)((int64_t)kx + kKeyBias);
-        const uint64_t by = (uint64_t)((int64_t)ky + kKeyBias);
-        const uint64_t bz = (uint64_t)((int64_t)kz + kKeyBias);
+        const int ix = (int)kx, iy = (int)ky, iz = (int)kz;
+        mn[0] = mx[0] = ix;
+        mn[1] = mx[1] = iy;
+        mn[2] = mx[2] = iz;
+        const uint64_t bx = (uint64_t)((int64_t)ix + kKeyBias);
+        const uint64_t by = (uint64_t)((int64_t)iy + kKeyBias);
+        const uint64_t bz = (uint64_t)((int64_t)iz + kKeyBias);
         key = (bx << (2 * kKeyFieldBits)) | (by << kKeyFieldBits) | bz;
       }
     } else {
       invalid = true;
     }
     keys[i] = key;
-    vals[i] = (uint32_t)i;
   }
   const unsigned long long inv_mask = __ballot(invalid);
   const unsigned long long rng_mask = __ballot(range_err);
@@ -78,12 +109,91 @@ __global__ void __launch_bounds__(256) key_kernel(const float* __restrict__ xyz,
     if (inv_mask) atomicAdd(&res[R_INVALID], (unsigned long long)__popcll(inv_mask));
     if (rng_mask) atomicOr(&res[R_RANGE], 1ull);
   }
+  __shared__ int s[6][4];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int lo = wave_min_i(mn[a]), hi = wave_max_i(mx[a]);
+    if (lane_id() == 0) {
+      s[a][w] = lo;
+      s[3 + a][w] = hi;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    int r = s[a][0];
+    for (int k = 1; k < 4; ++k) r = a < 3 ? min(r, s[a][k]) : max(r, s[a][k]);
+    part[(size_t)blockIdx.x * 6 + a] = r;
+  }
+}
+
+// Batch min / max per axis from the per-block partials.
+__global__ void __launch_bounds__(1024) minmax_kernel(const int* __restrict__ part, int nparts,
+                                                      unsigned long long* __restrict__ res) {
+  __shared__ int s[6][16];
+  int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+  for (int b = threadIdx.x; b < nparts; b += 1024) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = min(mn[a], part[(size_t)b * 6 + a]);
+      mx[a] = max(mx[a], part[(size_t)b * 6 + 3 + a]);
+    }
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int lo = wave_min_i(mn[a]), hi = wave_max_i(mx[a]);
+    if (lane_id() == 0) {
+      s[a][w] = lo;
+      s[3 + a][w] = hi;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    int r = s[a][0];
+    for (int k = 1; k < 16; ++k) r = a < 3 ? min(r, s[a][k]) : max(r, s[a][k]);
+    res[(a < 3 ? R_MIN : R_MAX - 3) + a] = (unsigned long long)(long long)r;
+  }
+}
+
+// Packed key -> compacted sort key (in place); seeds the index array the first pass reads.
+__global__ void __launch_bounds__(256) compose_kernel(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int n,
+                                                      KeyForm kf, const int64_t* __restrict__ fo, int nf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  vals[i] = (uint32_t)i;
+  const uint64_t key = keys[i];
+  uint64_t tk;
+  if (key == kKeySentinel) {
+    tk = 1ull << kf.B;
+  } else {
+    const int64_t mask = (int64_t(1) << kKeyFieldBits) - 1;
+    const uint64_t ux = (uint64_t)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias - kf.mn[0]);
+    const uint64_t uy = (uint64_t)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias - kf.mn[1]);
+    const uint64_t uz = (uint64_t)((int64_t)(key & mask) - kKeyBias - kf.mn[2]);
+    tk = (ux << (kf.by + kf.bz)) | (uy << kf.bz) | uz;
+  }
+  if (kf.embed && nf > 1) tk |= (uint64_t)frame_of((uint32_t)i, fo, nf) << (kf.B + 1);
+  keys[i] = tk;
+}
+
+// Compacted sort key -> packed voxel key.
+__device__ __forceinline__ uint64_t unpack_sort_key(uint64_t tk, const KeyForm& kf) {
+  const uint64_t mz = (kf.bz ? (1ull << kf.bz) : 1ull) - 1ull, my = (kf.by ? (1ull << kf.by) : 1ull) - 1ull,
+                 mx = (kf.bx ? (1ull << kf.bx) : 1ull) - 1ull;
+  const int64_t kz = (int64_t)(tk & mz) + kf.mn[2];
+  const int64_t ky = (int64_t)((tk >> kf.bz) & my) + kf.mn[1];
+  const int64_t kx = (int64_t)((tk >> (kf.by + kf.bz)) & mx) + kf.mn[0];
+  return ((uint64_t)(kx + kKeyBias) << (2 * kKeyFieldBits)) | ((uint64_t)(ky + kKeyBias) << kKeyFieldBits) |
+         (uint64_t)(kz + kKeyBias);
 }
 
 // Per-tile digit histogram, stored digit-major: hist[d * nblocks + b].
 __global__ void __launch_bounds__(kSortThreads) radix_upsweep(const uint64_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ vals, int n, int pass,
-                                                              const int64_t* __restrict__ fo, int nf,
+                                                              int key_passes, const int64_t* __restrict__ fo, int nf,
                                                               uint32_t* __restrict__ hist, int nblocks) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -92,7 +202,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_upsweep(const uint64_t* __
 #pragma unroll 4
   for (int r = 0; r < kSortItems; ++r) {
     const int i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of(keys[i], vals[i], pass, fo, nf)], 1u);
+    if (i < n) atomicAdd(&h[digit_of(keys[i], vals[i], pass, key_passes, fo, nf)], 1u);
   }
   __syncthreads();
   hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -119,7 +229,7 @@ __global__ void __launch_bounds__(1024) radix_rowscan(uint32_t* __restrict__ his
 // the input order, so ranks from ballots preserve stability.
 __global__ void __launch_bounds__(kSortThreads) radix_downsweep(
     const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint64_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int n, int pass, const int64_t* __restrict__ fo, int nf,
+    uint32_t* __restrict__ vals_out, int n, int pass, int key_passes, const int64_t* __restrict__ fo, int nf,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_total, int nblocks) {
   __shared__ uint32_t cnt[kSortWaves][256];
   __shared__ uint32_t scan_smem[kSortWaves + 1];
@@ -144,7 +254,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep(
     const bool valid = i < n;
     k[r] = valid ? keys_in[i] : 0ull;
     v[r] = valid ? vals_in[i] : 0u;
-    d[r] = valid ? digit_of(k[r], v[r], pass, fo, nf) : 0u;
+    d[r] = valid ? digit_of(k[r], v[r], pass, key_passes, fo, nf) : 0u;
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -186,30 +296,33 @@ __global__ void __launch_bounds__(kSortThreads) radix_downsweep(
   }
 }
 
-__device__ __forceinline__ bool is_head(const uint64_t* keys, int i, const int64_t* fo, int nf) {
+__device__ __forceinline__ bool sort_key_valid(uint64_t k, const KeyForm& kf) { return ((k >> kf.B) & 1ull) == 0; }
+
+__device__ __forceinline__ bool is_head(const uint64_t* keys, int i, const KeyForm& kf, const int64_t* fo, int nf) {
   const uint64_t k = keys[i];
-  if (k == kKeySentinel) return false;
+  if (!sort_key_valid(k, kf)) return false;
   if (i == 0) return true;
   if (keys[i - 1] != k) return true;
-  return nf > 1 && frame_of((uint32_t)i, fo, nf) != frame_of((uint32_t)(i - 1), fo, nf);
+  return !kf.embed && nf > 1 && frame_of((uint32_t)i, fo, nf) != frame_of((uint32_t)(i - 1), fo, nf);
 }
 
-__device__ __forceinline__ bool is_tail(const uint64_t* keys, int i, int n, const int64_t* fo, int nf) {
+__device__ __forceinline__ bool is_tail(const uint64_t* keys, int i, int n, const KeyForm& kf, const int64_t* fo,
+                                        int nf) {
   const uint64_t k = keys[i];
-  if (k == kKeySentinel) return false;
+  if (!sort_key_valid(k, kf)) return false;
   if (i == n - 1) return true;
   if (keys[i + 1] != k) return true;
-  return nf > 1 && frame_of((uint32_t)(i + 1), fo, nf) != frame_of((uint32_t)i, fo, nf);
+  return !kf.embed && nf > 1 && frame_of((uint32_t)(i + 1), fo, nf) != frame_of((uint32_t)i, fo, nf);
 }
 
-__global__ void __launch_bounds__(kSortThreads) seg_reduce(const uint64_t* __restrict__ keys, int n,
+__global__ void __launch_bounds__(kSortThreads) seg_reduce(const uint64_t* __restrict__ keys, int n, KeyForm kf,
                                                            const int64_t* __restrict__ fo, int nf,
                                                            uint32_t* __restrict__ block_sums) {
   uint32_t c = 0;
   const int base = blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
     const int i = base + r * kSortThreads + threadIdx.x;
-    if (i < n && is_head(keys, i, fo, nf)) ++c;
+    if (i < n && is_head(keys, i, kf, fo, nf)) ++c;
   }
   c = wave_sum(c);
   __shared__ uint32_t s[kSortWaves];
@@ -238,7 +351,7 @@ __global__ void __launch_bounds__(1024) seg_scan_blocks(uint32_t* __restrict__ b
 }
 
 // Heads write key and start; tails write end (turned into a count later).
-__global__ void __launch_bounds__(kSortThreads) seg_scatter(const uint64_t* __restrict__ keys, int n,
+__global__ void __launch_bounds__(kSortThreads) seg_scatter(const uint64_t* __restrict__ keys, int n, KeyForm kf,
                                                             const int64_t* __restrict__ fo, int nf,
                                                             const uint32_t* __restrict__ block_base,
                                                             int64_t cap, uint64_t* __restrict__ out_keys,
@@ -249,15 +362,15 @@ __global__ void __launch_bounds__(kSortThreads) seg_scatter(const uint64_t* __re
   uint32_t carry = block_base[blockIdx.x];
   for (int r = 0; r < kSortItems; ++r) {
     const int i = base + r * kSortThreads + threadIdx.x;
-    const bool h = i < n && is_head(keys, i, fo, nf);
+    const bool h = i < n && is_head(keys, i, kf, fo, nf);
     uint32_t tot;
     const uint32_t ex = block_exclusive_sum<kSortThreads>(h ? 1u : 0u, smem, &tot);
     const uint32_t vid_incl = carry + ex + (h ? 1u : 0u);  // heads up to and including i
     if (h && (int64_t)(vid_incl - 1) < cap) {
-      out_keys[vid_incl - 1] = keys[i];
+      out_keys[vid_incl - 1] = unpack_sort_key(keys[i], kf);
       out_off[vid_incl - 1] = i;
     }
-    if (i < n && is_tail(keys, i, n, fo, nf) && (int64_t)(vid_incl - 1) < cap) out_cnt[vid_incl - 1] = i + 1;
+    if (i < n && is_tail(keys, i, n, kf, fo, nf) && (int64_t)(vid_incl - 1) < cap) out_cnt[vid_incl - 1] = i + 1;
     carry += tot;
   }
 }
@@ -314,11 +427,12 @@ vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, cons
   const int nblocks = n ? (n + kSortTile - 1) / kSortTile : 1;
   const size_t res_words = R_FRAMES + nf + 1;
 
+  const int kblocks = n ? (n + 255) / 256 : 1;
   size_t need = work_offset + Carver::round(sizeof(uint64_t) * (size_t)n) * 2 +
                 Carver::round(sizeof(uint32_t) * (size_t)n) + Carver::round(sizeof(uint32_t) * 256 * nblocks) +
                 Carver::round(sizeof(uint32_t) * 256) + Carver::round(sizeof(uint32_t) * nblocks) +
-                Carver::round(sizeof(int64_t) * (nf + 1)) + Carver::round(sizeof(unsigned long long) * res_words) +
-                4096;
+                Carver::round(sizeof(int) * 6 * (size_t)kblocks) + Carver::round(sizeof(int64_t) * (nf + 1)) +
+                Carver::round(sizeof(unsigned long long) * res_words) + 4096;
   vgpr_status st = reserve_work(ctx, need);
   if (st != VGPR_OK) return st;
   st = reserve_pinned(ctx, sizeof(int64_t) * (nf + 1) + sizeof(unsigned long long) * res_words + 64);
@@ -330,6 +444,7 @@ vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, cons
   uint32_t* hist = cv.take<uint32_t>(256 * (size_t)nblocks);
   uint32_t* row_total = cv.take<uint32_t>(256);
   uint32_t* block_sums = cv.take<uint32_t>(nblocks);
+  int* part = cv.take<int>(6 * (size_t)kblocks);
   int64_t* d_fo = cv.take<int64_t>(nf + 1);
   unsigned long long* d_res = cv.take<unsigned long long>(res_words);
 
@@ -340,43 +455,79 @@ vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, cons
   VGPR_HIP(ctx, hipMemsetAsync(d_res, 0, sizeof(unsigned long long) * res_words, ctx->stream));
 
   uint32_t* perm = reinterpret_cast<uint32_t*>(d_perm);
+  KeyForm kf{};
+  kf.B = 0;
   if (n > 0) {
     const double inv_s = 1.0 / (double)voxel_size;
-    // passes: 8 key bytes, then the frame index bytes (most significant)
-    int passes = 8;
-    if (nf > 1) passes += (nf > 256) ? ((nf > 65536) ? 3 : 2) : 1;
-    // choose buffers so that the last pass writes the indices into d_perm
-    uint32_t* vbuf[2] = {perm, vals_tmp};
-    uint64_t* kbuf[2] = {keys_a, keys_b};
-    // pass p writes vbuf[(passes - 1 - p) & 1]; the input of pass 0 is the other one
-    const int first_in = (passes & 1) ? 1 : 0;
+    // keys and the batch's index ranges; the ranges decide the sort key's width
     {
       ProfScope ps(ctx, "voxelize_key");
-      hipLaunchKernelGGL(key_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, d_xyz, n, inv_s,
-                         kbuf[first_in], vbuf[first_in], d_res);
+      hipLaunchKernelGGL(key_kernel, dim3(kblocks), dim3(256), 0, ctx->stream, d_xyz, n, inv_s, keys_a, part,
+                         d_res);
+      hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, ctx->stream, part, kblocks, d_res);
     }
     VGPR_HIP(ctx, hipGetLastError());
+    VGPR_HIP(ctx, hipMemcpyAsync(h_res, d_res, sizeof(unsigned long long) * R_FRAMES, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h_res[R_RANGE]) return fail(ctx, VGPR_E_RANGE, "a point's voxel index is outside +-(2^20 - 1)");
+    auto bits = [](int64_t r) {
+      int b = 0;
+      while (r > 0) {
+        ++b;
+        r >>= 1;
+      }
+      return b;
+    };
+    const bool any_valid = (int64_t)h_res[R_INVALID] < n;
+    for (int a = 0; a < 3; ++a) kf.mn[a] = any_valid ? (int64_t)(long long)h_res[R_MIN + a] : 0;
+    const int b3[3] = {any_valid ? bits((int64_t)(long long)h_res[R_MAX + 0] - kf.mn[0]) : 0,
+                       any_valid ? bits((int64_t)(long long)h_res[R_MAX + 1] - kf.mn[1]) : 0,
+                       any_valid ? bits((int64_t)(long long)h_res[R_MAX + 2] - kf.mn[2]) : 0};
+    kf.bx = b3[0];
+    kf.by = b3[1];
+    kf.bz = b3[2];
+    kf.B = kf.bx + kf.by + kf.bz;
+    const int bf = nf > 1 ? bits(nf - 1) : 0;
+    kf.embed = (kf.B + 1 + bf) <= 64 ? 1 : 0;
+    const int key_bits = kf.B + 1 + (kf.embed ? bf : 0);
+    kf.key_passes = (key_bits + 7) / 8;
+    int passes = kf.key_passes;
+    if (!kf.embed && nf > 1) passes += (bf + 7) / 8;
+    // choose index buffers so that the last pass writes them into d_perm:
+    // pass p writes vbuf[(passes - 1 - p) & 1]; the input of pass 0 is the other one
+    uint32_t* vbuf[2] = {perm, vals_tmp};
+    const int first_in = (passes & 1) ? 1 : 0;
+    hipLaunchKernelGGL(compose_kernel, dim3(kblocks), dim3(256), 0, ctx->stream, keys_a, vbuf[first_in], n, kf, d_fo,
+                       nf);
+    VGPR_HIP(ctx, hipGetLastError());
     int in = first_in;
+    // keys ping-pong separately, starting in keys_a
+    uint64_t* kcur = keys_a;
+    uint64_t* kalt = keys_b;
     {
       ProfScope ps(ctx, "voxelize_sort");
       for (int p = 0; p < passes; ++p) {
         const int out = in ^ 1;
-        hipLaunchKernelGGL(radix_upsweep, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, kbuf[in], vbuf[in], n,
-                           p, d_fo, nf, hist, nblocks);
+        hipLaunchKernelGGL(radix_upsweep, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, kcur, vbuf[in], n, p,
+                           kf.key_passes, d_fo, nf, hist, nblocks);
         hipLaunchKernelGGL(radix_rowscan, dim3(256), dim3(1024), 0, ctx->stream, hist, nblocks, row_total);
-        hipLaunchKernelGGL(radix_downsweep, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, kbuf[in], vbuf[in],
-                           kbuf[out], vbuf[out], n, p, d_fo, nf, hist, row_total, nblocks);
+        hipLaunchKernelGGL(radix_downsweep, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, kcur, vbuf[in], kalt,
+                           vbuf[out], n, p, kf.key_passes, d_fo, nf, hist, row_total, nblocks);
         in = out;
+        uint64_t* t = kcur;
+        kcur = kalt;
+        kalt = t;
       }
     }
     VGPR_HIP(ctx, hipGetLastError());
-    const uint64_t* sorted = kbuf[in];
+    const uint64_t* sorted = kcur;
     {
       ProfScope ps(ctx, "voxelize_segment");
-      hipLaunchKernelGGL(seg_reduce, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, sorted, n, d_fo, nf,
+      hipLaunchKernelGGL(seg_reduce, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, sorted, n, kf, d_fo, nf,
                          block_sums);
       hipLaunchKernelGGL(seg_scan_blocks, dim3(1), dim3(1024), 0, ctx->stream, block_sums, nblocks, d_res);
-      hipLaunchKernelGGL(seg_scatter, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, sorted, n, d_fo, nf,
+      hipLaunchKernelGGL(seg_scatter, dim3(nblocks), dim3(kSortThreads), 0, ctx->stream, sorted, n, kf, d_fo, nf,
                          block_sums, cap_vox, d_keys, d_offsets, d_counts);
       const int64_t fin = std::max<int64_t>(n, nf + 1);
       hipLaunchKernelGGL(seg_finish, dim3((unsigned)((fin + 255) / 256)), dim3(256), 0, ctx->stream, d_offsets,

@@ -74,7 +74,7 @@ def load():
         "vgpr_workspace_bytes": (sz, [vp]),
         "vgpr_voxelize": (C.c_int, [vp, vp, i64, P(i64), i32, P(Params), vp, vp, vp, vp, i64, P(i64), P(i64),
                                     P(i64)]),
-        "vgpr_fit_predict": (C.c_int, [vp, vp, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
+        "vgpr_fit_predict": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
         "vgpr_map_create": (C.c_int, [vp, P(Params), i64, P(vp)]),
         "vgpr_map_destroy": (C.c_int, [vp]),
         "vgpr_map_update": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, P(i64)]),
@@ -187,7 +187,8 @@ class Context:
                    torch.empty(max(v, 1), dtype=torch.int8, device=dev),
                    torch.empty(max(v, 1), dtype=torch.uint8, device=dev))
         o, ax, stt = out
-        st = self.lib.vgpr_fit_predict(self.h, _ptr(xyz), _ptr(vox.keys), _ptr(vox.offsets), _ptr(vox.counts),
+        st = self.lib.vgpr_fit_predict(self.h, _ptr(xyz), xyz.numel() // 3, _ptr(vox.keys), _ptr(vox.offsets),
+                                       _ptr(vox.counts),
                                        _ptr(vox.perm), v, _ptr(noise_var), C.byref(params), _ptr(o), _ptr(ax),
                                        _ptr(stt))
         self._check(st, "vgpr_fit_predict")
