@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the 8-stream 10 Hz serving run (0 skips it)")
+    ap.add_argument("--serve-frames", type=int, default=10, help="distinct frames generated per stream (cycled)")
+    ap.add_argument("--autotune", action="store_true", help="search launch choices first and cache them")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -152,6 +156,20 @@ def main():
     offs = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
     cnts = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
     perm = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+
+    # launch choices: the cached autotuner result for this device (or a fresh search)
+    from paper_2410_17084_amd import autotune
+    dev_name = torch.cuda.get_device_name(0)
+    tuned = None
+    if args.autotune:
+        tuned = autotune.tune(ctx, xyz, vgpr.Voxels(vox.keys, vox.offsets, vox.counts, vox.perm, V, [], 0), p,
+                              log=log)
+        autotune.save_cached(p, dev_name, tuned)
+    else:
+        tuned = autotune.load_cached(p, dev_name)
+        if tuned:
+            ctx.set_tuning(vgpr.Tuning.from_dict(tuned["tuning"]))
+    log(f"tuning: {ctx.tuning().as_dict()}")
 
     def step():
         n = ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm)
@@ -248,6 +266,11 @@ def main():
         cpu = cpu_baseline(xyz_np[: int(fo[1])], w, gpu_f0, args.cpu_budget)
         log(f"cpu baseline {cpu['value']:.1f} solves/s; accuracy {cpu['accuracy']}")
 
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serve_leg(args, vgpr)
+        log(f"serving: {serving}")
+
     rec = {
         "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -259,14 +282,42 @@ def main():
                    "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec == 0 else ""),
                    "parallelism": "1 GPU"},
         "dense_pts_per_s": dense,
+        "tuning": ctx.tuning().as_dict(),
         "solved_per_step": n_solved, "refined_per_step": int(refined.sum()),
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "frames": int(len(lat)), "what": "one scan: voxelize + fit_predict + sync"}
                        if len(lat) else None),
-        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
+        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def serve_leg(args, vgpr) -> dict:
+    """Eight sensor streams at 10 Hz through device maps (paper-shaped parameters).
+
+    Each stream's frames are generated once along its trajectory and cycled;
+    frames arrive on a wall-clock schedule, are admitted as worker slots and the
+    HBM budget allow, and their latency is arrival -> completion.
+    """
+    from paper_2410_17084_amd import serve
+    t0 = time.perf_counter()
+    scene = synth.box_scene(clear_radius=12.0)
+    frames = [synth.stream_frames(j, args.serve_frames, scene=scene) for j in range(len(synth.STREAM_SENSORS))]
+    log(f"serving frames generated in {time.perf_counter() - t0:.1f} s")
+    w = configs.params_for("paper_stream")
+    p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
+    be = serve.GpuBackend(p, frames, max_voxels=250000)
+    be.warmup()
+    sizes = [[len(f) for f in fr] for fr in frames]
+    st = serve.serve(be, sizes, rate_hz=10.0, duration_s=args.serve_seconds, workers=8, budget_bytes=8 << 30,
+                     m=p.grid_side ** 2)
+    out = st.summary()
+    out["streams"] = [f"{b}x{a}" for b, a in synth.STREAM_SENSORS]
+    out["points_per_tick"] = int(sum(s[0] for s in sizes))
+    out["config"] = "voxel 0.2 m, tau 10, cap 64, 9x9 grid, eta 0.3; 10 frames per stream cycled"
+    be.close()
+    return out
 
 
 FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \

@@ -228,6 +228,27 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
                            int64_t* h_n_converged);
 
 /*
+ * Launch choices of vgpr_fit_predict. streams and grid_scale change only
+ * timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
+ * change the rounding (which arithmetic and which solver a voxel gets), and
+ * every choice stays within the stated tolerances. Buckets hold voxels of up to
+ * 16, 32, 64, 96 and 128 kept points (index 0..4). Defaults come from the
+ * project's autotuner on the spinning-scan workload.
+ */
+typedef struct {
+  int32_t fp32_last_bucket;   /* FP32 mode: buckets 0..this run in float first (-1: none) */
+  int32_t wave_last_bucket;   /* grids of up to 64 points: buckets 0..this use the one-voxel-per-
+                                 wavefront solver (max 2), the others one voxel per workgroup */
+  int32_t streams;            /* 1: every bucket on the context's stream; 3: the two largest
+                                 buckets and the next two fork onto two side streams */
+  int32_t grid_scale[5];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
+                                 workgroups the device holds (1..64) */
+} vgpr_tuning;
+
+VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);
+VGPR_API vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t);
+
+/*
  * Kernel timing for measurement. When enabled, the library records HIP
  * events on the context's stream around each launch of its kernels.
  * vgpr_profile_read synchronises the stream and returns, for the kernel

@@ -77,19 +77,30 @@ static hipEvent_t take_event(vgpr_ctx* ctx) {
   return e;
 }
 
-void prof_begin(vgpr_ctx* ctx, const char* family, hipEvent_t* start) {
+void prof_begin(vgpr_ctx* ctx, const char* family, hipStream_t stream, hipEvent_t* start) {
   (void)family;
   *start = nullptr;
   if (!ctx->profiling) return;
   hipEvent_t e = take_event(ctx);
-  if (e && hipEventRecord(e, ctx->stream) == hipSuccess) *start = e;
+  if (e && hipEventRecord(e, stream) == hipSuccess) *start = e;
 }
 
-void prof_end(vgpr_ctx* ctx, const char* family, hipEvent_t start) {
+void prof_end(vgpr_ctx* ctx, const char* family, hipStream_t stream, hipEvent_t start) {
   if (!ctx->profiling || !start) return;
   hipEvent_t e = take_event(ctx);
-  if (!e || hipEventRecord(e, ctx->stream) != hipSuccess) return;
+  if (!e || hipEventRecord(e, stream) != hipSuccess) return;
   ctx->prof[family].pending.emplace_back(start, e);
+}
+
+vgpr_status ensure_aux(vgpr_ctx* ctx) {
+  if (ctx->aux[0]) return VGPR_OK;
+  // default priority on purpose: every stream of the library runs at the same priority
+  for (int i = 0; i < 2; ++i) {
+    VGPR_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+    VGPR_HIP(ctx, hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming));
+  }
+  VGPR_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  return VGPR_OK;
 }
 
 vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
@@ -186,6 +197,14 @@ vgpr_status vgpr_destroy(vgpr_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->aux[i]) {
+      (void)hipStreamSynchronize(ctx->aux[i]);
+      (void)hipStreamDestroy(ctx->aux[i]);
+    }
+    if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   delete ctx;
   return VGPR_OK;
 }
@@ -200,6 +219,25 @@ const char* vgpr_last_error(const vgpr_ctx* ctx) { return ctx ? ctx->last_error.
 
 size_t vgpr_workspace_bytes(const vgpr_ctx* ctx) { return ctx ? ctx->held : 0; }
 
+vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
+  if (!ctx || !t) return VGPR_E_INVALID;
+  if (t->fp32_last_bucket < -1 || t->fp32_last_bucket > kNumBuckets - 1)
+    return fail(ctx, VGPR_E_INVALID, "fp32_last_bucket must be in [-1, 4]");
+  if (t->wave_last_bucket < -1 || t->wave_last_bucket > 2)
+    return fail(ctx, VGPR_E_INVALID, "wave_last_bucket must be in [-1, 2]");
+  if (t->streams != 1 && t->streams != 3) return fail(ctx, VGPR_E_INVALID, "streams must be 1 or 3");
+  for (int b = 0; b < kNumBuckets; ++b)
+    if (t->grid_scale[b] < 1 || t->grid_scale[b] > 64) return fail(ctx, VGPR_E_INVALID, "grid_scale must be in [1, 64]");
+  ctx->tune = *t;
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t) {
+  if (!ctx || !t) return VGPR_E_INVALID;
+  *t = ctx->tune;
+  return VGPR_OK;
+}
+
 vgpr_status vgpr_profile_enable(vgpr_ctx* ctx, int on) {
   if (!ctx) return VGPR_E_INVALID;
   ctx->profiling = on != 0;
@@ -210,6 +248,8 @@ vgpr_status vgpr_profile_read(vgpr_ctx* ctx, const char* name, double* h_total_m
   if (!ctx || !name) return VGPR_E_INVALID;
   (void)hipSetDevice(ctx->device);
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 2; ++i)
+    if (ctx->aux[i]) VGPR_HIP(ctx, hipStreamSynchronize(ctx->aux[i]));
   double total = 0.0;
   int64_t count = 0;
   auto it = ctx->prof.find(name);

@@ -190,23 +190,40 @@ __global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, floa
   if (lst < 0 || lst == kNanList) return;
 
   // stage the kept points and accumulate the covariance about the first point:
-  // S1 = sum d, S2 = sum d d^T with d = p - p0
-  const int* perm = io.perm;
+  // S1 = sum d, S2 = sum d d^T with d = p - p0. Loads of four points are issued
+  // together so that a large voxel's thread keeps several gathers in flight.
+  const int* __restrict__ perm = io.perm;
+  const float* __restrict__ xyz = io.xyz;
+  const float* __restrict__ noise = io.noise;
+  float4* __restrict__ st = staged;
   const int i0 = perm ? perm[off] : off;
-  const float x0 = io.xyz[3 * (size_t)i0], y0 = io.xyz[3 * (size_t)i0 + 1], z0 = io.xyz[3 * (size_t)i0 + 2];
-  staged[off] = make_float4(x0, y0, z0, io.noise ? io.noise[i0] : P.noise);
+  const float x0 = xyz[3 * (size_t)i0], y0 = xyz[3 * (size_t)i0 + 1], z0 = xyz[3 * (size_t)i0 + 2];
+  st[off] = make_float4(x0, y0, z0, noise ? noise[i0] : P.noise);
   const double p0x = x0, p0y = y0, p0z = z0;
   double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
-  for (int i = 1; i < n; ++i) {
-    const int idx = perm ? perm[off + i] : off + i;
-    const float x = io.xyz[3 * (size_t)idx], y = io.xyz[3 * (size_t)idx + 1], z = io.xyz[3 * (size_t)idx + 2];
-    staged[off + i] = make_float4(x, y, z, io.noise ? io.noise[idx] : P.noise);
-    const double d0 = (double)x - p0x;
-    const double d1 = (double)y - p0y;
-    const double d2 = (double)z - p0z;
-    s0 += d0; s1 += d1; s2 += d2;
-    a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
-    a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
+  for (int i = 1; i < n; i += 4) {
+    float px[4], py[4], pz[4], pn[4];
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      const int ii = i + u4 < n ? i + u4 : i;
+      const int idx = perm ? perm[off + ii] : off + ii;
+      px[u4] = xyz[3 * (size_t)idx];
+      py[u4] = xyz[3 * (size_t)idx + 1];
+      pz[u4] = xyz[3 * (size_t)idx + 2];
+      pn[u4] = noise ? noise[idx] : P.noise;
+    }
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      if (i + u4 < n) {
+        st[off + i + u4] = make_float4(px[u4], py[u4], pz[u4], pn[u4]);
+        const double d0 = (double)px[u4] - p0x;
+        const double d1 = (double)py[u4] - p0y;
+        const double d2 = (double)pz[u4] - p0z;
+        s0 += d0; s1 += d1; s2 += d2;
+        a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
+        a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
+      }
+    }
   }
   const double inv_n = 1.0 / (double)n;
   const double m0 = s0 * inv_n, m1 = s1 * inv_n, m2 = s2 * inv_n;
@@ -336,6 +353,12 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
                                                                 const uint32_t* __restrict__ count,
                                                                 int32_t* __restrict__ rlist,
                                                                 uint32_t* __restrict__ rcount) {
+  constexpr bool kKInLds = NMAX <= 32;       // K from its upper triangle through LDS
+  constexpr int kWaves = kWaveThreads / 64;
+  __shared__ T s_xu[kWaves][NMAX + 8], s_xw[kWaves][NMAX + 8];
+  __shared__ T s_tab[kWaves][2 * 8 * NMAX];
+  __shared__ T s_K[kWaves][kKInLds ? NMAX * NMAX : 1];
+  const int wid = threadIdx.x >> 6;
   const int lane = lane_id();
   // wavefront-uniform indices (scalar registers): record loads become scalar loads
   const int gw = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
@@ -375,11 +398,70 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       fv = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
       nz = (T)pt.w;
     }
-    // this lane's query point (lanes < m)
+    // this lane's query point (lanes < m): row i, column j of the grid
     float gu = 0.f, gwv = 0.f;
-    query_coords(P, fr, lane < P.m ? lane : 0, &gu, &gwv);
-    const T qu = (T)((double)gu - fr.anc_u), qw = (T)((double)gwv - fr.anc_w);
+    const int q = lane < P.m ? lane : 0;
+    query_coords(P, fr, q, &gu, &gwv);
+    const int qi = q / P.nq, qj = q - qi * P.nq;
     const bool dlane = lane < n;
+
+    // Kernel entries with few exponentials. The query entries factor as
+    // kappa(x*_q, x_c) = s_f^2 Eu[i][c] Ew[j][c], Eu[i][c] = exp(-lam (u*_i - u_c)^2),
+    // so the wave builds the two nq x n tables; for n <= 32 the symmetric K
+    // is built from its upper triangle. Both are spread over all 64 lanes and
+    // exchanged through this wavefront's LDS region.
+    T* __restrict__ su = s_xu[wid];
+    T* __restrict__ sw = s_xw[wid];
+    T* __restrict__ tu = s_tab[wid];
+    T* __restrict__ tw = s_tab[wid] + 8 * NMAX;
+    if (dlane) {
+      su[lane] = xu;
+      sw[lane] = xw;
+    }
+    if (lane < P.nq) {
+      // grid coordinate i (and j) of the face: the same formula as query_coords
+      float gi, gj;
+      FrameRec f2 = fr;
+      query_coords(P, f2, lane * P.nq + lane, &gi, &gj);
+      su[NMAX + lane] = (T)((double)gi - fr.anc_u);
+      sw[NMAX + lane] = (T)((double)gj - fr.anc_w);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nq = P.nq;
+    for (int e = lane; e < nq * n; e += 64) {
+      const int c = e / nq, i = e - c * nq;
+      const T du = su[NMAX + i] - su[c], dw = sw[NMAX + i] - sw[c];
+      tu[e] = k_exp(-(du * du) * lam);
+      tw[e] = k_exp(-(dw * dw) * lam);
+    }
+    if constexpr (kKInLds) {
+      // upper triangle (r <= c) folded into an (ne/2) x (ne+1) rectangle, ne = n rounded up to even
+      T* __restrict__ Kt = s_K[wid];
+      const int ne = (n + 1) & ~1;
+      const int half = ne >> 1;
+      for (int e = lane; e < half * (ne + 1); e += 64) {
+        const int p = e / (ne + 1), k = e - p * (ne + 1);
+        int r, c;
+        if (k < ne - p) {
+          r = p;
+          c = p + k;
+        } else {
+          r = ne - 1 - p;
+          c = r + (k - (ne - p));
+        }
+        if (c < n) {
+          const T du = su[r] - su[c], dw = sw[r] - sw[c];
+          const T kv = sf2 * k_exp(-(du * du + dw * dw) * lam);
+          Kt[c * NMAX + r] = kv;
+          Kt[r * NMAX + c] = kv;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // rows: A = query row (lanes < m), B = data row (lanes < n) with its right-hand side fy
     T A[NMAX], B[NMAX];
@@ -387,17 +469,24 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) {
       if (c < n) {
-        const T uc = bcast(xu, c), wc = bcast(xw, c);
-        const T du = qu - uc, dw = qw - wc;
-        A[c] = sf2 * k_exp(-(du * du + dw * dw) * lam);
-        const T eu = xu - uc, ew = xw - wc;
-        const T kb = sf2 * k_exp(-(eu * eu + ew * ew) * lam) + (c == lane ? nz : (T)0);
-        B[c] = dlane ? kb : (T)0;
+        A[c] = sf2 * tu[c * nq + qi] * tw[c * nq + qj];
+        T kb;
+        if constexpr (kKInLds) {
+          kb = s_K[wid][c * NMAX + lane];
+        } else {
+          const T eu = xu - su[c], ew = xw - sw[c];
+          kb = sf2 * k_exp(-(eu * eu + ew * ew) * lam);
+        }
+        B[c] = dlane ? kb + (c == lane ? nz : (T)0) : (T)0;
       } else {
         A[c] = 0;
         B[c] = 0;
       }
+      // keep the table loads of later columns from being hoisted (register pressure)
+      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
+    // the LDS region is rewritten for the next voxel only after every lane has read it
+    __builtin_amdgcn_wave_barrier();
     T var = sf2, mean = 0, minpiv = (T)FLT_MAX, score = 0;
     for (int j = 0; j < n; ++j) {
       const T cjA = A[0], cjB = B[0];
@@ -587,6 +676,8 @@ const char* const kFam[3][kNumBuckets] = {
     {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128"}};
 
 struct Launch {
+  hipStream_t stream;
+  int grid_scale;            // x 1/4 of the resident workgroups
   const SlotRec* recs;
   const int32_t* slots;      // nullable: item -> slot indirection (re-solve lists)
   const uint32_t* count;
@@ -602,12 +693,12 @@ vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, co
                         const Launch& l) {
   static int per_cu = -1;
   if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX>, kWaveThreads);
-  int64_t grid = (int64_t)per_cu * ctx->cu_count;
+  int64_t grid = (int64_t)per_cu * ctx->cu_count * l.grid_scale / 4;
   const int64_t need = (l.max_items + kWaveThreads / 64 - 1) / (kWaveThreads / 64);
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  ProfScope ps(ctx, l.fam);
-  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX>), dim3((unsigned)grid), dim3(kWaveThreads), 0, ctx->stream, P, io,
+  ProfScope ps(ctx, l.fam, l.stream);
+  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P, io,
                      l.recs, staged, l.slots, l.count, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
@@ -621,11 +712,11 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
   threads = (threads + 63) & ~63;
   static int per_cu = -1;
   if (per_cu < 0) per_cu = occupancy(fit_block_kernel<T, NMAX>, kBlockThreads);
-  int64_t grid = (int64_t)per_cu * (kBlockThreads / threads) * ctx->cu_count;
+  int64_t grid = (int64_t)per_cu * (kBlockThreads / threads) * ctx->cu_count * l.grid_scale / 4;
   if (grid > l.max_items) grid = l.max_items;
   if (grid < 1) grid = 1;
-  ProfScope ps(ctx, l.fam);
-  hipLaunchKernelGGL((fit_block_kernel<T, NMAX>), dim3((unsigned)grid), dim3(threads), 0, ctx->stream, P, io,
+  ProfScope ps(ctx, l.fam, l.stream);
+  hipLaunchKernelGGL((fit_block_kernel<T, NMAX>), dim3((unsigned)grid), dim3(threads), 0, l.stream, P, io,
                      l.recs, staged, l.slots, l.count, l.next, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
@@ -705,30 +796,43 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
                        ctx->stream, P, a.out, L);
     VGPR_HIP(ctx, hipGetLastError());
   }
-  // largest voxels first so that their long solves start early
+  // Buckets run concurrently: the two largest on side stream 0, the middle two
+  // on side stream 1, the smallest (and its FP64 re-solve) on the caller's
+  // stream, joined back before the call returns. Many small voxels fill the
+  // CUs that the few long large-voxel solves leave idle.
+  st = ensure_aux(ctx);
+  if (st != VGPR_OK) return st;
+  VGPR_HIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int i = 0; i < 2; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+  const vgpr_tuning& tu = ctx->tune;
+  auto stream_of = [&](int b) {
+    if (tu.streams == 1) return ctx->stream;
+    return b >= 3 ? ctx->aux[0] : (b >= 1 ? ctx->aux[1] : ctx->stream);
+  };
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
-    const bool wave = wave_ok && b <= 2;
-    const bool in_fp32 = fp32 && b <= kFp32LastBucket;
+    const bool wave = wave_ok && b <= tu.wave_last_bucket;
+    const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket;
     FitParams Pb = P;
     Pb.mode = in_fp32 ? 0 : 2;
-    Launch l{recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b, rlists + (size_t)b * a.n_vox, ctr + 16 + b,
-             a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
+    Launch l{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b,
+             rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
                  : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
     if (st != VGPR_OK) return st;
-  }
-  if (fp32) {
-    FitParams R = P;
-    R.mode = 1;
-    for (int b = std::min(kFp32LastBucket, kNumBuckets - 1); b >= 0; --b) {
-      if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
-      const bool wave = wave_ok && b <= 2;
-      Launch l{recs + (size_t)b * a.n_vox, rlists + (size_t)b * a.n_vox, ctr + 16 + b, ctr + 24 + b, nullptr, nullptr,
-               a.n_vox, kFam[1][b]};
-      st = launch_bucket<double>(ctx, b, wave, R, a, staged, l);
+    if (in_fp32) {
+      // FP64 re-solve of this bucket's flagged voxels, on the same stream right after it
+      FitParams R = P;
+      R.mode = 1;
+      Launch lr{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rlists + (size_t)b * a.n_vox,
+                ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
+      st = launch_bucket<double>(ctx, b, wave, R, a, staged, lr);
       if (st != VGPR_OK) return st;
     }
+  }
+  for (int i = 0; i < 2; ++i) {
+    VGPR_HIP(ctx, hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
+    VGPR_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
   }
   return VGPR_OK;
 }

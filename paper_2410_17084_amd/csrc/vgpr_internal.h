@@ -25,9 +25,7 @@ constexpr int kMaxGridSide = 16;
 // smallest bucket whose capacity is >= n.
 constexpr int kNumBuckets = 5;
 constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 96, 128};
-// FP32 mode runs the buckets up to this index in float (with the FP64 re-solve of
-// flagged voxels); larger voxels are flagged so often that they go to FP64 directly.
-constexpr int kFp32LastBucket = 0;
+
 
 struct DeviceBuffer {
   void* ptr = nullptr;
@@ -52,6 +50,10 @@ struct vgpr_ctx {
   std::string last_error;
   int cu_count = 0;
   int live_maps = 0;          // maps created on this context and not yet destroyed
+  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4}};
+  hipStream_t aux[2] = {nullptr, nullptr};  // side streams the solver buckets fork onto
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[2] = {nullptr, nullptr};
   bool profiling = false;
   std::map<std::string, vgpr::ProfFamily> prof;
   std::vector<hipEvent_t> event_pool;
@@ -92,17 +94,26 @@ struct Carver {
   static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
 };
 
-// Launch timing (no-ops unless profiling is on).
-void prof_begin(vgpr_ctx* ctx, const char* family, hipEvent_t* start);
-void prof_end(vgpr_ctx* ctx, const char* family, hipEvent_t start);
+// Launch timing (no-ops unless profiling is on); events go on the launch's stream.
+void prof_begin(vgpr_ctx* ctx, const char* family, hipStream_t stream, hipEvent_t* start);
+void prof_end(vgpr_ctx* ctx, const char* family, hipStream_t stream, hipEvent_t start);
 
 struct ProfScope {
   vgpr_ctx* ctx;
   const char* family;
+  hipStream_t stream;
   hipEvent_t start = nullptr;
-  ProfScope(vgpr_ctx* c, const char* f) : ctx(c), family(f) { prof_begin(ctx, family, &start); }
-  ~ProfScope() { prof_end(ctx, family, start); }
+  ProfScope(vgpr_ctx* c, const char* f) : ctx(c), family(f), stream(c->stream) {
+    prof_begin(ctx, family, stream, &start);
+  }
+  ProfScope(vgpr_ctx* c, const char* f, hipStream_t s) : ctx(c), family(f), stream(s) {
+    prof_begin(ctx, family, stream, &start);
+  }
+  ~ProfScope() { prof_end(ctx, family, stream, start); }
 };
+
+// Side streams and fork/join events of a context (created on first use).
+vgpr_status ensure_aux(vgpr_ctx* ctx);
 
 vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p);
 

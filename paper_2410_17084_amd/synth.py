@@ -28,9 +28,13 @@ import numpy as np
 
 __all__ = [
     "BoxScene", "box_scene", "planes_cloud", "spin_directions", "rosette_directions",
-    "cast_rays", "spin_scan", "rosette_scan", "scan_batch", "yaw_matrix",
-    "frame_seed", "SCENE_SEED",
+    "cast_rays", "spin_scan", "rosette_scan", "scan_batch", "yaw_matrix", "rotation_rpy",
+    "spline_trajectory", "stream_frames", "STREAM_SENSORS", "frame_seed", "SCENE_SEED",
 ]
+
+# (beams, azimuth steps) of the eight serving streams: 16- to 128-beam spinning
+# LiDARs at 512..2048 azimuth steps, 630,784 rays per 10 Hz tick in total.
+STREAM_SENSORS = [(16, 512), (16, 2048), (32, 1024), (32, 2048), (64, 512), (64, 1024), (128, 1024), (128, 2048)]
 
 SCENE_SEED = 0
 
@@ -105,6 +109,52 @@ def planes_cloud(seed: int, n_pts: int = 20000, cube: float = 20.0, n_planes: in
 def yaw_matrix(yaw: float) -> np.ndarray:
     c, s = math.cos(yaw), math.sin(yaw)
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def rotation_rpy(roll: float, pitch: float, yaw: float) -> np.ndarray:
+    """Rotation R = Rz(yaw) Ry(pitch) Rx(roll) (sensor to world)."""
+    cr, sr = math.cos(roll), math.sin(roll)
+    cp, sp = math.cos(pitch), math.sin(pitch)
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, cr, -sr], [0.0, sr, cr]])
+    ry = np.array([[cp, 0.0, sp], [0.0, 1.0, 0.0], [-sp, 0.0, cp]])
+    return yaw_matrix(yaw) @ ry @ rx
+
+
+def spline_trajectory(seed: int, n_frames: int, rate_hz: float = 10.0, speed=(1.0, 10.0), radius: float = 9.0,
+                      tilt_deg: float = 2.0):
+    """Poses along a uniform cubic B-spline through seeded waypoints in a disc of `radius`.
+
+    The sensor moves at a seeded constant speed in [speed[0], speed[1]] m/s,
+    yaws along the tangent, and rolls / pitches with N(0, tilt_deg) noise.
+    Returns a list of (position (3,), rotation (3, 3)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.uniform(*speed)
+    n_way = 12
+    ang = np.sort(rng.uniform(0, 2 * np.pi, n_way))
+    rad = radius * np.sqrt(rng.uniform(0.2, 1.0, n_way))
+    way = np.stack([rad * np.cos(ang), rad * np.sin(ang)], 1)
+    way = np.concatenate([way, way[:3]])  # closed loop
+    # dense sampling of the B-spline, then constant-speed reparametrisation
+    ts = np.linspace(0, 1, 64, endpoint=False)
+    basis = np.stack([(1 - ts) ** 3, 3 * ts ** 3 - 6 * ts ** 2 + 4, -3 * ts ** 3 + 3 * ts ** 2 + 3 * ts + 1,
+                      ts ** 3], 1) / 6.0
+    curve = np.concatenate([basis @ way[i:i + 4] for i in range(n_way)])
+    seg = np.linalg.norm(np.diff(curve, axis=0, append=curve[:1]), axis=1)
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    total = arc[-1]
+    poses = []
+    for k in range(n_frames):
+        s_ = (v * k / rate_hz) % total
+        i = int(np.searchsorted(arc, s_, side="right") - 1)
+        i = min(i, len(curve) - 1)
+        a, b = curve[i], curve[(i + 1) % len(curve)]
+        t = (s_ - arc[i]) / max(seg[i], 1e-9)
+        pos = a + t * (b - a)
+        yaw = math.atan2(b[1] - a[1], b[0] - a[0])
+        roll, pitch = np.deg2rad(rng.normal(0, tilt_deg, 2))
+        poses.append((np.array([pos[0], pos[1], 1.8]), rotation_rpy(roll, pitch, yaw)))
+    return poses
 
 
 def spin_directions(n_beams: int, n_az: int, elev_deg=(-15.0, 15.0)) -> np.ndarray:
@@ -186,7 +236,7 @@ def cast_rays(scene: BoxScene, origin: np.ndarray, dirs: np.ndarray, max_range: 
 
 def spin_scan(seed: int, n_beams: int = 32, n_az: int = 1800, position=None, yaw=None,
               scene: BoxScene | None = None, sensor_height: float = 1.8, range_noise: float = 0.02,
-              max_range: float = 120.0, elev_deg=(-15.0, 15.0)) -> np.ndarray:
+              max_range: float = 120.0, elev_deg=(-15.0, 15.0), rotation=None) -> np.ndarray:
     """One spinning-LiDAR scan of the box scene, world frame, misses dropped.
 
     Without an explicit pose the sensor sits at a seeded position within 2 m of
@@ -200,8 +250,10 @@ def spin_scan(seed: int, n_beams: int = 32, n_az: int = 1800, position=None, yaw
         position = (r * math.cos(phi), r * math.sin(phi))
     if yaw is None:
         yaw = rng.uniform(0, 2 * np.pi)
-    o = np.array([position[0], position[1], sensor_height], dtype=np.float64)
-    d = spin_directions(n_beams, n_az, elev_deg) @ yaw_matrix(yaw).T
+    z = position[2] if len(position) > 2 else sensor_height
+    o = np.array([position[0], position[1], z], dtype=np.float64)
+    R = yaw_matrix(yaw) if rotation is None else np.asarray(rotation, dtype=np.float64)
+    d = spin_directions(n_beams, n_az, elev_deg) @ R.T
     t = cast_rays(scene, o, d, max_range)
     ok = np.isfinite(t)
     t = t[ok] + rng.normal(0.0, range_noise, size=int(ok.sum()))
@@ -243,3 +295,16 @@ def scan_batch(config: int, n_frames: int, first: int = 0, **kw):
     offs = np.zeros(n_frames + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(f) for f in frames])
     return np.ascontiguousarray(np.concatenate(frames)), offs
+
+
+def stream_frames(stream: int, n_frames: int, rate_hz: float = 10.0, scene: BoxScene | None = None):
+    """Seeded frames of serving stream `stream` (sensor STREAM_SENSORS[stream]) along its trajectory.
+
+    The scene has a 12 m clearing around the origin so the trajectories stay in
+    free space; seeds: trajectory 10^4 (stream + 1), frame k 10^4 (stream + 1) + k.
+    """
+    scene = scene if scene is not None else box_scene(clear_radius=12.0)
+    beams, az = STREAM_SENSORS[stream % len(STREAM_SENSORS)]
+    poses = spline_trajectory(10 ** 4 * (stream + 1), n_frames, rate_hz)
+    return [spin_scan(10 ** 4 * (stream + 1) + k, n_beams=beams, n_az=az, position=pos, rotation=R, scene=scene)
+            for k, (pos, R) in enumerate(poses)]

@@ -23,6 +23,7 @@ SYMBOLS = [
     "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
     "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
+    "vgpr_set_tuning", "vgpr_get_tuning",
 ]
 
 
@@ -43,6 +44,25 @@ class Params(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
+                ("grid_scale", C.c_int32 * 5)]
+
+    def as_dict(self) -> dict:
+        return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,
+                "streams": self.streams, "grid_scale": list(self.grid_scale)}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tuning":
+        t = cls()
+        t.fp32_last_bucket = d["fp32_last_bucket"]
+        t.wave_last_bucket = d["wave_last_bucket"]
+        t.streams = d["streams"]
+        for i, g in enumerate(d["grid_scale"]):
+            t.grid_scale[i] = g
+        return t
 
 
 class VgprError(RuntimeError):
@@ -81,6 +101,8 @@ def load():
         "vgpr_map_stats": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
         "vgpr_profile_enable": (C.c_int, [vp, C.c_int]),
         "vgpr_profile_read": (C.c_int, [vp, C.c_char_p, P(C.c_double), P(i64)]),
+        "vgpr_set_tuning": (C.c_int, [vp, P(Tuning)]),
+        "vgpr_get_tuning": (C.c_int, [vp, P(Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -193,6 +215,15 @@ class Context:
                                        _ptr(stt))
         self._check(st, "vgpr_fit_predict")
         return o[:v], ax[:v], stt[:v]
+
+    # -- launch tuning ----------------------------------------------------------
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.lib.vgpr_get_tuning(self.h, C.byref(t)), "vgpr_get_tuning")
+        return t
+
+    def set_tuning(self, t: Tuning):
+        self._check(self.lib.vgpr_set_tuning(self.h, C.byref(t)), "vgpr_set_tuning")
 
     # -- timing ---------------------------------------------------------------
     def profile(self, on: bool = True):

@@ -285,3 +285,41 @@ def test_budget_exhaustion(env):
         small.voxelize(dev(torch, xyz), vgpr.default_params(voxel_size=0.5))
     assert ei.value.status == vgpr.E_BUDGET
     small.close()
+
+
+def test_tuning_choices(env):
+    """streams / grid scale are bit-identical; solver and FP32 choices stay within the oracle tolerances."""
+    torch, vgpr, ctx = env
+    xyz = synth.spin_scan(synth.frame_seed(2, 4), n_beams=32, n_az=1024)
+    w = configs.params_for("spin32")
+    p = parity.gpu_params(vgpr, w, precision=vgpr.PREC_FP64)
+    x = dev(torch, xyz)
+    gv = ctx.voxelize(x, p)
+    default = ctx.tuning().as_dict()
+    ref = [t.cpu().numpy() for t in ctx.fit_predict(x, gv, p)]
+    ov = O.voxelize(xyz, w["voxel_size"])
+    prm = parity.oracle_params(w)
+    try:
+        for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3]), dict(streams=1, grid_scale=[64] * 5)]:
+            say("tuning (bit-identical)", change)
+            t = dict(default)
+            t.update(change)
+            ctx.set_tuning(vgpr.Tuning.from_dict(t))
+            got = [t_.cpu().numpy() for t_ in ctx.fit_predict(x, gv, p)]
+            for g, r in zip(got, ref):
+                assert np.array_equal(g, r, equal_nan=True)
+        for change, prec in [(dict(wave_last_bucket=-1), vgpr.PREC_FP64), (dict(wave_last_bucket=0), vgpr.PREC_FP64),
+                             (dict(fp32_last_bucket=2), vgpr.PREC_FP32), (dict(fp32_last_bucket=-1), vgpr.PREC_FP32)]:
+            say("tuning (within tolerance)", change, prec)
+            t = dict(default)
+            t.update(change)
+            ctx.set_tuning(vgpr.Tuning.from_dict(t))
+            out = ctx.fit_predict(x, gv, p.replace(precision=prec))
+            parity.compare_fit(xyz, ov, prm, *out)
+        with pytest.raises(vgpr.VgprError):
+            bad = dict(default)
+            bad["streams"] = 2
+            ctx.set_tuning(vgpr.Tuning.from_dict(bad))
+    finally:
+        ctx.set_tuning(vgpr.Tuning.from_dict(default))
+
