@@ -29,7 +29,7 @@ from paper_2410_17084_amd import configs, synth  # noqa: E402
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # TFLOP/s, MI355X vector FP32 / FP64
 HBM_PEAK = 8000.0                   # GB/s
-BUCKETS = (16, 32, 64, 96, 128)
+BUCKETS = (16, 32, 64, 96, 128, 256, 512)
 
 
 def log(*a):

@@ -89,7 +89,7 @@ enum {
  */
 typedef struct {
   float voxel_size;       /* s, metres, > 0 */
-  int32_t max_pts;        /* cap of points per voxel, 1..128 in this build */
+  int32_t max_pts;        /* cap of points per voxel, 1..512 */
   int32_t min_pts;        /* tau: solve a voxel only with at least this many kept points (>= 1) */
   int32_t grid_side;      /* n_q: queries per side of the voxel face; m = n_q^2, 1..16 */
   float signal_var;       /* s_f^2 of the squared-exponential kernel, > 0 */
@@ -232,8 +232,9 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
  * timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
  * change the rounding (which arithmetic and which solver a voxel gets), and
  * every choice stays within the stated tolerances. Buckets hold voxels of up to
- * 16, 32, 64, 96 and 128 kept points (index 0..4). Defaults come from the
- * project's autotuner on the spinning-scan workload.
+ * 16, 32, 64, 96, 128, 256 and 512 kept points (index 0..6); the last two
+ * always run the tiled FP64 solver. Defaults come from the project's
+ * autotuner on the spinning-scan workload.
  */
 typedef struct {
   int32_t fp32_last_bucket;   /* FP32 mode: buckets 0..this run in float first (-1: none) */
@@ -241,8 +242,9 @@ typedef struct {
                                  wavefront solver (max 2), the others one voxel per workgroup */
   int32_t streams;            /* 1: every bucket on the context's stream; 3: the two largest
                                  buckets and the next two fork onto two side streams */
-  int32_t grid_scale[5];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
-                                 workgroups the device holds (1..64) */
+  int32_t grid_scale[7];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
+                                 workgroups the device holds (1..64; buckets 5 and 6 use at
+                                 most 4, one resident wave of workgroups) */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);
@@ -256,7 +258,7 @@ VGPR_API vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t);
  * launches since the last read of that family, then resets it. Families:
  * "voxelize_key", "voxelize_sort" (all radix passes of a call),
  * "voxelize_segment", "classify", "fit_f32_n<C>" / "fit_f64_n<C>" (the
- * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 96, 128) and
+ * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 96, 128, 256, 512) and
  * "refine_f64_n<C>" (the FP64 re-solve of flagged voxels of that bucket).
  */
 VGPR_API vgpr_status vgpr_profile_enable(vgpr_ctx* ctx, int on);

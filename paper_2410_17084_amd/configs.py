@@ -27,6 +27,20 @@ WORKLOADS = {
         desc="paper-shaped stream: voxel 0.2 m, tau 10, 9x9 grid (n_s = n_r = 3), eta 0.3",
         voxel_size=0.2, max_pts=64, min_pts=10, grid_side=9, signal_var=1.0, length_scale=0.1, noise_var=1e-3,
         converge_var=0.3),
+    # batched uneven voxels: one 128-beam x 1024-azimuth scan (or a rosette
+    # scan) at 1 m voxels, up to 256 points per voxel, 8x8 grid.
+    "batched": dict(
+        desc="batched: 128-beam x 1024-azimuth spinning scan (131k rays) or a 100k-point rosette scan of the box "
+             "scene, voxel 1 m, cap 256, tau 3, 8x8 grid",
+        voxel_size=1.0, max_pts=256, min_pts=3, grid_side=8, signal_var=1.0, length_scale=0.5, noise_var=1e-3,
+        converge_var=0.3, n_beams=128, n_az=1024),
+    # large aggregated map update: 10 scans of 128 x 1024 with pose noise,
+    # voxel 0.1 m, up to 512 points per voxel, length scale from PCA, 16x16 grid.
+    "aggregated": dict(
+        desc="aggregated: 10 scans of 128 beams x 1024 azimuths along a path with N(0, 0.01 m) pose noise "
+             "(about 0.9M points), voxel 0.1 m, cap 512, tau 3, 16x16 grid, length scale from PCA",
+        voxel_size=0.1, max_pts=512, min_pts=3, grid_side=16, signal_var=1.0, length_scale=0.05, noise_var=1e-3,
+        converge_var=0.3, ls_mode=1, n_beams=128, n_az=1024),
 }
 
 

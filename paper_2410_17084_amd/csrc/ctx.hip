@@ -109,7 +109,7 @@ vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
     return fail(ctx, VGPR_E_INVALID, "voxel_size must be a positive finite number");
   if (p->max_pts < 1) return fail(ctx, VGPR_E_INVALID, "max_pts must be >= 1");
   if (p->max_pts > kMaxPtsLimit)
-    return fail(ctx, VGPR_E_UNSUPPORTED, "max_pts above 128 is not supported by this build");
+    return fail(ctx, VGPR_E_UNSUPPORTED, "max_pts above 512 is not supported by this build");
   if (p->min_pts < 1) return fail(ctx, VGPR_E_INVALID, "min_pts must be >= 1");
   if (p->grid_side < 1) return fail(ctx, VGPR_E_INVALID, "grid_side must be >= 1");
   if (p->grid_side > kMaxGridSide)
@@ -222,7 +222,7 @@ size_t vgpr_workspace_bytes(const vgpr_ctx* ctx) { return ctx ? ctx->held : 0; }
 vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
   if (!ctx || !t) return VGPR_E_INVALID;
   if (t->fp32_last_bucket < -1 || t->fp32_last_bucket > kNumBuckets - 1)
-    return fail(ctx, VGPR_E_INVALID, "fp32_last_bucket must be in [-1, 4]");
+    return fail(ctx, VGPR_E_INVALID, "fp32_last_bucket must be in [-1, 6]");
   if (t->wave_last_bucket < -1 || t->wave_last_bucket > 2)
     return fail(ctx, VGPR_E_INVALID, "wave_last_bucket must be in [-1, 2]");
   if (t->streams != 1 && t->streams != 3) return fail(ctx, VGPR_E_INVALID, "streams must be 1 or 3");

@@ -662,6 +662,272 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2c. tiled solver (n up to 512, FP64): one voxel per workgroup of four
+//     wavefronts, 32 x 32 tiles, tile products on the FP64 matrix cores
+// ---------------------------------------------------------------------------
+// The augmented system is processed one block of 32 rows at a time, data rows
+// first, then query rows: left-looking across row blocks and right-looking
+// inside one,
+//     L(I,J) = (A(I,J) - sum_{K<J} L(I,K) L(J,K)^T) L(J,J)^-T,
+// the Cholesky factor of K + S tile by tile. The current row block lives in
+// LDS. Finished data tiles L(I,J) and the inverses L(J,J)^-1 of the diagonal
+// tiles go to the workgroup's scratch area, stored in matrix-core operand
+// order so that a wavefront reads one operand fragment as 512 contiguous
+// bytes. The right-hand side gives y = L^-1 f~ one block at a time, query rows
+// become z_q = L^-1 k*_q, and
+//     var_q = s_f^2 - |z_q|^2,   mean_q = mu + z_q . y      (Eq. (3)).
+// Padding rows and columns of the last data block are identity rows, so they
+// leave the factor of the real block unchanged.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kTile = 32;
+constexpr int kTileThreads = 256;
+constexpr int kTileDoubles = kTile * kTile;
+
+__device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Accumulator layout of the 16 x 16 x 4 FP64 product: lane l, register k holds
+// element (l / 16 + 4 k, l % 16) of the 16 x 16 result.
+//
+// Element (row, col) of a 32 x 32 tile in operand order: fragment (row half h,
+// column quad s) is 64 consecutive doubles, lane l holding (16 h + l % 16, 4 s + l / 16).
+__device__ __forceinline__ int frag_pos(int row, int col) {
+  return (((row >> 4) * 8 + (col >> 2)) << 6) + (row & 15) + ((col & 3) << 4);
+}
+
+// Scratch doubles per workgroup: the lower data tiles and one inverse per diagonal tile.
+constexpr size_t tile_scratch_doubles(int npad) {
+  return (size_t)((npad / kTile) * (npad / kTile + 1) / 2 + npad / kTile) * kTileDoubles;
+}
+
+__device__ __forceinline__ double sum8(double v) {
+#pragma unroll
+  for (int d = 4; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+template <int NPAD>
+__global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, FitArgs io,
+                                                                const SlotRec* __restrict__ recs,
+                                                                const float4* __restrict__ staged,
+                                                                const uint32_t* __restrict__ count,
+                                                                uint32_t* __restrict__ next,
+                                                                double* __restrict__ scratch) {
+  constexpr int NB = NPAD / kTile;
+  constexpr int LD = NPAD + 2;  // row stride of the row block, in doubles
+  __shared__ double rb[kTile * LD];
+  __shared__ double pu[NPAD], pw[NPAD], pf[NPAD], pn[NPAD];
+  __shared__ double sy[NPAD];
+  __shared__ double srhs[kTile], squ[kTile], sqw[kTile];
+  __shared__ int s_item, s_fail;
+  __shared__ unsigned s_maxvar;
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  double* __restrict__ Lt = scratch + (size_t)blockIdx.x * tile_scratch_doubles(NPAD);
+  double* __restrict__ Wt = Lt + (size_t)(NB * (NB + 1) / 2) * kTileDoubles;
+  const int cnt_items = (int)*count;
+  const double sf2 = (double)P.sf2;
+
+  for (;;) {
+    if (tid == 0) {
+      s_item = (int)atomicAdd(next, 1u);
+      s_fail = 0;
+      s_maxvar = 0u;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item >= cnt_items) break;
+    const SlotRec r = recs[item];
+    const FrameRec& fr = r.fr;
+    const int n = fr.n;
+    const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
+    const double lam = fr.lam;
+    for (int i = tid; i < NPAD; i += kTileThreads) {
+      double xu = 0, xw = 0, fv = 0, nz = 0;
+      if (i < n) {
+        const float4 pt = staged[r.off + i];
+        xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
+        xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
+        fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
+        nz = (double)pt.w;
+      }
+      pu[i] = xu;
+      pw[i] = xw;
+      pf[i] = fv;
+      pn[i] = nz;
+    }
+    const int nbd = (n + kTile - 1) / kTile;
+    const int nbe = (P.m + kTile - 1) / kTile;
+    for (int I = 0; I < nbd + nbe; ++I) {
+      const bool data = I < nbd;
+      const int ncols = data ? (I + 1) * kTile : nbd * kTile;
+      if (!data && tid < kTile) {
+        const int q = (I - nbd) * kTile + tid;
+        float gu = 0.f, gw = 0.f;
+        if (q < P.m) query_coords(P, fr, q, &gu, &gw);
+        squ[tid] = (double)gu - fr.anc_u;
+        sqw[tid] = (double)gw - fr.anc_w;
+      }
+      __syncthreads();
+      // the block's rows of the augmented system
+      for (int e = tid; e < kTile * ncols; e += kTileThreads) {
+        const int rr = e / ncols, c = e - rr * ncols;
+        double val;
+        if (data) {
+          const int i = I * kTile + rr;
+          if (i < n && c < n) {
+            const double du = pu[i] - pu[c], dw = pw[i] - pw[c];
+            val = sf2 * exp(-(du * du + dw * dw) * lam) + (i == c ? pn[i] : 0.0);
+          } else {
+            val = i == c ? 1.0 : 0.0;
+          }
+        } else {
+          const int q = (I - nbd) * kTile + rr;
+          if (q < P.m && c < n) {
+            const double du = squ[rr] - pu[c], dw = sqw[rr] - pw[c];
+            val = sf2 * exp(-(du * du + dw * dw) * lam);
+          } else {
+            val = 0.0;
+          }
+        }
+        rb[rr * LD + c] = val;
+      }
+      __syncthreads();
+      const int jend = data ? I : nbd;
+      for (int J = 0; J < jend; ++J) {
+        // finish tile J: X = A(I,J) L(J,J)^-T, one 16 x 16 quarter per wavefront
+        const int a = wid >> 1, b = wid & 1;
+        const double* __restrict__ W = Wt + (size_t)J * kTileDoubles;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const double af = rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4];
+          const double bf = W[((b * 8 + s) << 6) + lane];
+          acc = mfma_f64(af, bf, acc);
+        }
+        __syncthreads();
+        double* __restrict__ Lij = Lt + (size_t)(I * (I + 1) / 2 + J) * kTileDoubles;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int row = a * 16 + l4 + 4 * k, col = b * 16 + l16;
+          rb[row * LD + J * kTile + col] = acc[k];
+          if (data) Lij[frag_pos(row, col)] = acc[k];
+        }
+        __syncthreads();
+        // right-looking update of the block's later tiles: A(I,J') -= X L(J',J)^T
+        const int jlast = data ? I : nbd - 1;
+        const int units = (jlast - J) * 4;
+        for (int un = wid; un < units; un += 4) {
+          const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
+          dbl4 c4;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c4[k] = rb[(a2 * 16 + l4 + 4 * k) * LD + Jp * kTile + b2 * 16 + l16];
+          const bool own = data && Jp == I;  // L(I,J) itself: read it from the row block
+          const double* __restrict__ Lpj = Lt + (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const double af = -rb[(a2 * 16 + l16) * LD + J * kTile + 4 * s + l4];
+            const double bf = own ? rb[(b2 * 16 + l16) * LD + J * kTile + 4 * s + l4] : Lpj[((b2 * 8 + s) << 6) + lane];
+            c4 = mfma_f64(af, bf, c4);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) rb[(a2 * 16 + l4 + 4 * k) * LD + Jp * kTile + b2 * 16 + l16] = c4[k];
+        }
+        __syncthreads();
+      }
+      if (data) {
+        // right-hand side of the block: f~_I - sum_{J<I} L(I,J) y_J, eight lanes per row
+        {
+          const int rr = tid >> 3, sub = tid & 7;
+          double t = 0.0;
+          for (int c = sub; c < I * kTile; c += 8) t += rb[rr * LD + c] * sy[c];
+          t = sum8(t);
+          if (sub == 0) srhs[rr] = pf[I * kTile + rr] - t;
+        }
+        __syncthreads();
+        if (wid == 0) {
+          // diagonal tile by wavefront 0: LDL^T with lane r holding row r (shifted so
+          // that element 0 is the active column), y_I on the fly, L(I,I) = U sqrt(D)
+          double B[kTile];
+          double fy = lane < kTile ? srhs[lane] : 0.0;
+#pragma unroll
+          for (int c = 0; c < kTile; ++c) B[c] = lane < kTile ? rb[lane * LD + I * kTile + c] : 0.0;
+          bool bad = false;
+          for (int j = 0; j < kTile; ++j) {
+            const double cj = B[0];
+            const double d = bcast(cj, j);
+            const double yj = bcast(fy, j);
+            const double t = cj / d;
+            const double sd = sqrt(d);
+            bad |= !(d > 0.0);
+            if (lane == j) {
+              rb[lane * LD + I * kTile + j] = sd;
+              sy[I * kTile + j] = yj / sd;
+            } else if (lane > j && lane < kTile) {
+              rb[lane * LD + I * kTile + j] = cj / sd;
+            }
+            fy -= t * yj;
+#pragma unroll
+            for (int k = 0; k < kTile - 1; ++k) B[k] = B[k + 1] - t * bcast(cj, (j + 1 + k) & 63);
+            B[kTile - 1] = 0.0;
+          }
+          if (bad && lane == 0) s_fail = 1;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // L(I,I)^-1 by forward substitution, lane k computing column k
+          if (lane < kTile) {
+            double x[kTile];
+            const double* __restrict__ Ld = rb + I * kTile;
+#pragma unroll
+            for (int i = 0; i < kTile; ++i) {
+              double s = i == lane ? 1.0 : 0.0;
+#pragma unroll
+              for (int j = 0; j < i; ++j) s -= Ld[i * LD + j] * x[j];
+              x[i] = s / Ld[i * LD + i];
+            }
+            double* __restrict__ Wi = Wt + (size_t)I * kTileDoubles;
+#pragma unroll
+            for (int i = 0; i < kTile; ++i) Wi[frag_pos(i, lane)] = x[i];
+          }
+        }
+        __syncthreads();
+      } else {
+        // query rows of the block: variance and mean, eight lanes per row
+        const int rr = tid >> 3, sub = tid & 7;
+        double zz = 0.0, zy = 0.0;
+        for (int c = sub; c < nbd * kTile; c += 8) {
+          const double z = rb[rr * LD + c];
+          zz += z * z;
+          zy += z * sy[c];
+        }
+        zz = sum8(zz);
+        zy = sum8(zy);
+        const int q = (I - nbd) * kTile + rr;
+        if (sub == 0 && q < P.m) {
+          float gu, gw;
+          query_coords(P, fr, q, &gu, &gw);
+          const bool failed = s_fail != 0;
+          const double var = sf2 - zz;
+          const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > 0.0 ? var : 0.0);
+          const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + zy);
+          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = out_row(ax, u, mv, gu, gw, vv);
+          if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
+        }
+        __syncthreads();
+      }
+    }
+    if (tid == 0)
+      finish_voxel(P, io, r.v, item, r.cnt, fr.axes, s_fail != 0, false, __uint_as_float(s_maxvar), nullptr, nullptr);
+    __syncthreads();
+  }
+}
+
 template <typename K>
 int occupancy(K kernel, int threads) {
   int nb = 0;
@@ -671,9 +937,12 @@ int occupancy(K kernel, int threads) {
 
 // Timing family of each launch: pass (FP32, FP64 re-solve, FP64 only) and bucket capacity.
 const char* const kFam[3][kNumBuckets] = {
-    {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n96", "fit_f32_n128"},
-    {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n96", "refine_f64_n128"},
-    {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128"}};
+    {"fit_f32_n16", "fit_f32_n32", "fit_f32_n64", "fit_f32_n96", "fit_f32_n128", "fit_f32_n256", "fit_f32_n512"},
+    {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n96", "refine_f64_n128", "refine_f64_n256",
+     "refine_f64_n512"},
+    {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128", "fit_f64_n256", "fit_f64_n512"}};
+
+constexpr int kFirstTileBucket = 5;  // buckets of 256 and 512 points: tiled FP64 solver
 
 struct Launch {
   hipStream_t stream;
@@ -722,6 +991,42 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
   return VGPR_OK;
 }
 
+template <int NPAD>
+int tile_per_cu() {
+  static int per_cu = -1;
+  if (per_cu < 0) per_cu = occupancy(fit_tile_kernel<NPAD>, kTileThreads);
+  return per_cu;
+}
+
+// Workgroups of the tiled solver for bucket b: at most one resident wave of them,
+// since each holds a scratch area.
+int tile_grid(const vgpr_ctx* ctx, int b, int grid_scale) {
+  const int per_cu = b == kFirstTileBucket ? tile_per_cu<256>() : tile_per_cu<512>();
+  const int gs = grid_scale < 4 ? grid_scale : 4;
+  const int64_t g = (int64_t)per_cu * ctx->cu_count * gs / 4;
+  return g < 1 ? 1 : (int)g;
+}
+
+size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b) {
+  const int per_cu = b == kFirstTileBucket ? tile_per_cu<256>() : tile_per_cu<512>();
+  return (size_t)per_cu * ctx->cu_count * tile_scratch_doubles(b == kFirstTileBucket ? 256 : 512) * sizeof(double);
+}
+
+vgpr_status launch_tile(vgpr_ctx* ctx, int b, const FitParams& P, const FitArgs& io, const float4* staged,
+                        const Launch& l, double* scratch) {
+  int64_t grid = tile_grid(ctx, b, l.grid_scale);
+  if (grid > l.max_items) grid = l.max_items;
+  ProfScope ps(ctx, l.fam, l.stream);
+  if (b == kFirstTileBucket)
+    hipLaunchKernelGGL(fit_tile_kernel<256>, dim3((unsigned)grid), dim3(kTileThreads), 0, l.stream, P, io, l.recs,
+                       staged, l.count, l.next, scratch);
+  else
+    hipLaunchKernelGGL(fit_tile_kernel<512>, dim3((unsigned)grid), dim3(kTileThreads), 0, l.stream, P, io, l.recs,
+                       staged, l.count, l.next, scratch);
+  VGPR_HIP(ctx, hipGetLastError());
+  return VGPR_OK;
+}
+
 // One solver launch for bucket b, in precision T.
 template <typename T>
 vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, const FitArgs& io,
@@ -744,10 +1049,13 @@ vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, c
 
 }  // namespace
 
-size_t fit_work_bytes(int64_t n_vox, int64_t n_pts) {
+size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts) {
+  size_t tiles = 0;
+  for (int b = kFirstTileBucket; b < kNumBuckets; ++b)
+    if (max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b));
   return Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
          Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
-         Carver::round(sizeof(uint32_t) * 64) + 4096;
+         Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
 }
 
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset) {
@@ -758,14 +1066,17 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     return fail(ctx, VGPR_E_INVALID, "null device pointer");
   if (reinterpret_cast<uintptr_t>(a.out) & 15) return fail(ctx, VGPR_E_INVALID, "d_out must be 16-byte aligned");
   const int m = p->grid_side * p->grid_side;
-  vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(a.n_vox, a.n_pts));
+  vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(ctx, a.n_vox, a.n_pts, p->max_pts));
   if (st != VGPR_OK) return st;
   Carver cv(static_cast<char*>(ctx->work.ptr) + work_offset);
   SlotRec* recs = cv.take<SlotRec>((size_t)a.n_vox * kNumBuckets);
   float4* staged = cv.take<float4>((size_t)a.n_pts);
   int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
-  uint32_t* ctr = cv.take<uint32_t>(64);  // [0,5) counts, [8,12) fetch, [16,20) re-solve counts, [24,28) fetch
+  uint32_t* ctr = cv.take<uint32_t>(64);  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch
+  double* tile_scratch[kNumBuckets] = {};
+  for (int b = kFirstTileBucket; b < kNumBuckets; ++b)
+    if (p->max_pts > kBucketCap[b - 1]) tile_scratch[b] = cv.take<double>(tile_bucket_bytes(ctx, b) / sizeof(double));
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
 
   // the wave solver holds one query row per lane: grids up to 64 points
@@ -811,12 +1122,18 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   };
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
+    const bool tiled = b >= kFirstTileBucket;
     const bool wave = wave_ok && b <= tu.wave_last_bucket;
-    const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket;
+    const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket && !tiled;
     FitParams Pb = P;
     Pb.mode = in_fp32 ? 0 : 2;
     Launch l{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b,
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
+    if (tiled) {
+      st = launch_tile(ctx, b, Pb, a, staged, l, tile_scratch[b]);
+      if (st != VGPR_OK) return st;
+      continue;
+    }
     st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
                  : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
     if (st != VGPR_OK) return st;

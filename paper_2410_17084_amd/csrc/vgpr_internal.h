@@ -18,13 +18,13 @@ constexpr int kKeyFieldBits = 21;
 constexpr int64_t kKeyBias = int64_t(1) << 20;
 constexpr int64_t kKeyAxisLimit = (int64_t(1) << 20) - 1;
 constexpr uint64_t kKeySentinel = ~uint64_t(0);
-constexpr int kMaxPtsLimit = 128;   // largest cap the register-resident solver supports
+constexpr int kMaxPtsLimit = 512;   // largest cap the tiled solver supports
 constexpr int kMaxGridSide = 16;
 
 // Size buckets of the per-voxel solver: a voxel with n kept points runs in the
 // smallest bucket whose capacity is >= n.
-constexpr int kNumBuckets = 5;
-constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 96, 128};
+constexpr int kNumBuckets = 7;
+constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 96, 128, 256, 512};
 
 
 struct DeviceBuffer {
@@ -50,7 +50,7 @@ struct vgpr_ctx {
   std::string last_error;
   int cu_count = 0;
   int live_maps = 0;          // maps created on this context and not yet destroyed
-  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4}};
+  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}};
   hipStream_t aux[2] = {nullptr, nullptr};  // side streams the solver buckets fork onto
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[2] = {nullptr, nullptr};
@@ -141,7 +141,7 @@ struct FitArgs {
   int8_t* axis;
   uint8_t* status;
 };
-size_t fit_work_bytes(int64_t n_vox, int64_t n_pts);
+size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts);
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset);
 
 }  // namespace vgpr

@@ -297,6 +297,28 @@ def scan_batch(config: int, n_frames: int, first: int = 0, **kw):
     return np.ascontiguousarray(np.concatenate(frames)), offs
 
 
+def aggregated_scans(seed: int, n_scans: int = 10, n_beams: int = 128, n_az: int = 1024, spacing: float = 0.3,
+                     pose_noise: float = 0.01, scene: BoxScene | None = None) -> np.ndarray:
+    """A map-update frame: `n_scans` scans taken along a straight path, concatenated.
+
+    Scan k is taken at start + k * spacing along a seeded heading, with the
+    position perturbed by N(0, pose_noise) m per axis (a registration error),
+    and the same heading as yaw. Seeds: path `seed`, scan k seed + 1 + k.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scene = scene if scene is not None else box_scene()
+    heading = rng.uniform(0, 2 * np.pi)
+    start = rng.uniform(-1.0, 1.0, size=2) - 0.5 * (n_scans - 1) * spacing * np.array([math.cos(heading),
+                                                                                        math.sin(heading)])
+    scans = []
+    for k in range(n_scans):
+        xy = start + k * spacing * np.array([math.cos(heading), math.sin(heading)])
+        pos = np.array([xy[0], xy[1], 1.8]) + rng.normal(0.0, pose_noise, size=3)
+        scans.append(spin_scan(seed + 1 + k, n_beams=n_beams, n_az=n_az, position=tuple(pos), yaw=heading,
+                               scene=scene))
+    return np.ascontiguousarray(np.concatenate(scans))
+
+
 def stream_frames(stream: int, n_frames: int, rate_hz: float = 10.0, scene: BoxScene | None = None):
     """Seeded frames of serving stream `stream` (sensor STREAM_SENSORS[stream]) along its trajectory.
 

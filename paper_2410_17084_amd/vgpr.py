@@ -48,7 +48,7 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
-                ("grid_scale", C.c_int32 * 5)]
+                ("grid_scale", C.c_int32 * 7)]
 
     def as_dict(self) -> dict:
         return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,

@@ -169,6 +169,64 @@ def test_fit_every_size_in_one_call(env, prec):
     assert caps.astype(bool).sum() == 32
 
 
+LARGE_SIZES = [3, 40, 100, 129, 130, 160, 161, 200, 255, 256, 257, 300, 384, 511, 512, 513, 700]
+
+
+@pytest.mark.parametrize("nq,ls_mode", [(4, 0), (9, 0), (16, 0), (16, 1)])
+def test_fit_large_voxels(env, nq, ls_mode):
+    """Voxels of 129..512 kept points (tiled solver) beside small ones, every grid size class."""
+    torch, vgpr, ctx = env
+    xyz = _ragged_voxels(21 + nq + ls_mode, LARGE_SIZES)
+    w = dict(configs.params_for("spin32"), max_pts=512, min_pts=3, grid_side=nq, ls_mode=ls_mode)
+    for prec in (vgpr.PREC_FP32, vgpr.PREC_FP64):
+        say("fit large voxels", nq, ls_mode, prec, len(xyz))
+        gv, (out, axis, status) = run_fit(env, xyz, w, precision=prec)
+        ov = O.voxelize(xyz, w["voxel_size"])
+        stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status)
+        assert stats["solved"] == len(LARGE_SIZES)
+        assert (status.cpu().numpy() & vgpr.ST_CAPPED).astype(bool).sum() == 2
+        print(stats)
+
+
+@pytest.mark.parametrize("scan", ["spin128", "rosette"])
+def test_fit_batched_workload(env, scan):
+    """128-beam spinning scan and rosette scan at 1 m voxels, cap 256: every voxel against the oracle."""
+    torch, vgpr, ctx = env
+    if scan == "spin128":
+        xyz = synth.spin_scan(synth.frame_seed(3, 0), n_beams=128, n_az=1024)
+    else:
+        xyz = synth.rosette_scan(synth.frame_seed(3, 1), n_pts=100000)
+    w = configs.params_for("batched")
+    say("fit batched workload", scan, len(xyz))
+    gv, (out, axis, status) = run_fit(env, xyz, w, precision=vgpr.PREC_FP32)
+    ov = O.voxelize(xyz, w["voxel_size"])
+    stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status)
+    print(scan, stats)
+
+
+def test_fit_aggregated_workload_sampled(env):
+    """About 0.9M aggregated points, voxel 0.1 m, cap 512, 16x16 grid, PCA length scale.
+
+    Keys and order are compared in full; GP outputs on every voxel above 64
+    points and a seeded 1% sample of the rest.
+    """
+    torch, vgpr, ctx = env
+    xyz = synth.aggregated_scans(synth.frame_seed(5, 0))
+    w = configs.params_for("aggregated")
+    say("fit aggregated workload", len(xyz))
+    gv, (out, axis, status) = run_fit(env, xyz, w, precision=vgpr.PREC_FP32)
+    ov = O.voxelize(xyz, w["voxel_size"])
+    parity.compare_voxelize(ov, gv)
+    counts = ov["counts"]
+    pick = np.flatnonzero(counts > 64)
+    rest = np.flatnonzero(counts <= 64)
+    pick = np.union1d(pick, rng(15).choice(rest, size=len(rest) // 100, replace=False))
+    stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status, voxels=pick)
+    print(stats)
+    st = status.cpu().numpy()
+    assert (st & vgpr.ST_SOLVED).astype(bool).sum() == int((np.minimum(counts, 512) >= 3).sum())
+
+
 @pytest.mark.parametrize("cap,tau,nq", [(20, 5, 3), (128, 10, 9), (64, 1, 16), (7, 7, 1)])
 def test_fit_cap_tau_grid(env, cap, tau, nq):
     xyz = synth.spin_scan(synth.frame_seed(2, 1), n_beams=16, n_az=1024)
@@ -300,7 +358,7 @@ def test_tuning_choices(env):
     ov = O.voxelize(xyz, w["voxel_size"])
     prm = parity.oracle_params(w)
     try:
-        for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3]), dict(streams=1, grid_scale=[64] * 5)]:
+        for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3, 2, 1]), dict(streams=1, grid_scale=[64] * 7)]:
             say("tuning (bit-identical)", change)
             t = dict(default)
             t.update(change)
