@@ -159,7 +159,9 @@ def main():
 
     # launch choices: the cached autotuner result for this device (or a fresh search)
     from paper_2410_17084_amd import autotune
-    dev_name = torch.cuda.get_device_name(0)
+    props = torch.cuda.get_device_properties(0)
+    dev_name = f"{getattr(props, 'gcnArchName', 'gpu').split(':')[0]}x{props.multi_processor_count}cu"
+    log(f"device key for cached tuning: {dev_name}")
     tuned = None
     if args.autotune:
         tuned = autotune.tune(ctx, xyz, vgpr.Voxels(vox.keys, vox.offsets, vox.counts, vox.perm, V, [], 0), p,

@@ -232,8 +232,8 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
  * timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
  * change the rounding (which arithmetic and which solver a voxel gets), and
  * every choice stays within the stated tolerances. Buckets hold voxels of up to
- * 16, 32, 64, 96, 128, 256 and 512 kept points (index 0..6); the last two
- * always run the tiled FP64 solver. Defaults come from the project's
+ * 16, 32, 64, 96, 128, 256 and 512 kept points (index 0..6); buckets from
+ * tile_first_bucket on run the tiled FP64 solver. Defaults come from the project's
  * autotuner on the spinning-scan workload.
  */
 typedef struct {
@@ -245,6 +245,8 @@ typedef struct {
   int32_t grid_scale[7];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
                                  workgroups the device holds (1..64; buckets 5 and 6 use at
                                  most 4, one resident wave of workgroups) */
+  int32_t tile_first_bucket;  /* buckets from this one on (3..5) run the tiled FP64 solver on
+                                 the matrix cores; buckets 5 and 6 always do */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);

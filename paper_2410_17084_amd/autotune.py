@@ -1,8 +1,9 @@
 """Launch autotuner of vgpr_fit_predict.
 
 Searches the launch choices of `vgpr_tuning` (which buckets try FP32 first,
-which use the one-voxel-per-wavefront solver, one or three streams, the
-persistent grid size of each bucket) by coordinate descent, timing the real
+which use the one-voxel-per-wavefront solver, which use the tiled
+matrix-core solver, one or three streams, the persistent grid size of each
+bucket) by coordinate descent, timing the real
 workload on the device with HIP events. A candidate is accepted only if its
 outputs stay within the accuracy tolerances of an FP64 reference run of the
 same call (mean 1e-4 m, variance 1e-3 s_f^2, identical status and axis), so
@@ -97,6 +98,8 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
     log(f"[autotune] baseline {base:.3f} ms {cur}")
     fp32_opts = [-1, 0, 1, 2] if params.precision == vgpr.PREC_FP32 else [cur["fp32_last_bucket"]]
     space = [("streams", [1, 3]), ("wave_last_bucket", [0, 1, 2]), ("fp32_last_bucket", fp32_opts)]
+    if params.max_pts > 64:
+        space.append(("tile_first_bucket", [3, 4, 5]))
     caps = (0, 16, 32, 64, 96, 128, 256)  # lower bound of each bucket
     space += [(("grid_scale", b), [2, 4, 8, 16]) for b in range(7) if params.max_pts > caps[b]]
     t0 = time.perf_counter()

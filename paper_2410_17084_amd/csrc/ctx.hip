@@ -228,6 +228,8 @@ vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
   if (t->streams != 1 && t->streams != 3) return fail(ctx, VGPR_E_INVALID, "streams must be 1 or 3");
   for (int b = 0; b < kNumBuckets; ++b)
     if (t->grid_scale[b] < 1 || t->grid_scale[b] > 64) return fail(ctx, VGPR_E_INVALID, "grid_scale must be in [1, 64]");
+  if (t->tile_first_bucket < 3 || t->tile_first_bucket > 5)
+    return fail(ctx, VGPR_E_INVALID, "tile_first_bucket must be in [3, 5]");
   ctx->tune = *t;
   return VGPR_OK;
 }

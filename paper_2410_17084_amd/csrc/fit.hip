@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
 }
 
 // ---------------------------------------------------------------------------
-// 2c. tiled solver (n up to 512, FP64): one voxel per workgroup of four
+// 2c. tiled solver (FP64, n up to 512): one voxel per workgroup of eight
 //     wavefronts, 32 x 32 tiles, tile products on the FP64 matrix cores
 // ---------------------------------------------------------------------------
 // The augmented system is processed one block of 32 rows at a time, data rows
@@ -681,8 +681,10 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
 // leave the factor of the real block unchanged.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kTile = 32;
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 512;
+constexpr int kTileWaves = kTileThreads / 64;
 constexpr int kTileDoubles = kTile * kTile;
+constexpr int kXS = kTile + 1;  // row stride of the finished-tile buffer
 
 __device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -702,9 +704,9 @@ constexpr size_t tile_scratch_doubles(int npad) {
   return (size_t)((npad / kTile) * (npad / kTile + 1) / 2 + npad / kTile) * kTileDoubles;
 }
 
-__device__ __forceinline__ double sum8(double v) {
+__device__ __forceinline__ double sum16(double v) {
 #pragma unroll
-  for (int d = 4; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  for (int d = 8; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
 }
 
@@ -718,7 +720,9 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
   constexpr int NB = NPAD / kTile;
   constexpr int LD = NPAD + 2;  // row stride of the row block, in doubles
   __shared__ double rb[kTile * LD];
-  __shared__ double pu[NPAD], pw[NPAD], pf[NPAD], pn[NPAD];
+  __shared__ double xb[kTile * kXS];  // the tile finished in the current step
+  __shared__ double pu[NPAD], pw[NPAD], pf[NPAD];
+  __shared__ float pn[NPAD];
   __shared__ double sy[NPAD];
   __shared__ double srhs[kTile], squ[kTile], sqw[kTile];
   __shared__ int s_item, s_fail;
@@ -748,13 +752,14 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
     const double lam = fr.lam;
     for (int i = tid; i < NPAD; i += kTileThreads) {
-      double xu = 0, xw = 0, fv = 0, nz = 0;
+      double xu = 0, xw = 0, fv = 0;
+      float nz = 0.f;
       if (i < n) {
         const float4 pt = staged[r.off + i];
         xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
         xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
         fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
-        nz = (double)pt.w;
+        nz = pt.w;
       }
       pu[i] = xu;
       pw[i] = xw;
@@ -782,7 +787,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
           const int i = I * kTile + rr;
           if (i < n && c < n) {
             const double du = pu[i] - pu[c], dw = pw[i] - pw[c];
-            val = sf2 * exp(-(du * du + dw * dw) * lam) + (i == c ? pn[i] : 0.0);
+            val = sf2 * exp(-(du * du + dw * dw) * lam) + (i == c ? (double)pn[i] : 0.0);
           } else {
             val = i == c ? 1.0 : 0.0;
           }
@@ -800,53 +805,72 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
       __syncthreads();
       const int jend = data ? I : nbd;
       for (int J = 0; J < jend; ++J) {
-        // finish tile J: X = A(I,J) L(J,J)^-T, one 16 x 16 quarter per wavefront
-        const int a = wid >> 1, b = wid & 1;
-        const double* __restrict__ W = Wt + (size_t)J * kTileDoubles;
+        // finish tile J: X = A(I,J) L(J,J)^-T, one 16 x 16 quarter on each of
+        // wavefronts 0-3, into the tile buffer (the row block is still being read)
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int a = (wid >> 1) & 1, b = wid & 1;
+        if (wid < 4) {
+          const double* __restrict__ W = Wt + (size_t)J * kTileDoubles;
+          double wf[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const double af = rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4];
-          const double bf = W[((b * 8 + s) << 6) + lane];
-          acc = mfma_f64(af, bf, acc);
+          for (int s = 0; s < 8; ++s) wf[s] = W[((b * 8 + s) << 6) + lane];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) acc = mfma_f64(rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4], wf[s], acc);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) xb[(a * 16 + l4 + 4 * k) * kXS + b * 16 + l16] = acc[k];
         }
         __syncthreads();
-        double* __restrict__ Lij = Lt + (size_t)(I * (I + 1) / 2 + J) * kTileDoubles;
+        if (wid < 4) {
+          double* __restrict__ Lij = Lt + (size_t)(I * (I + 1) / 2 + J) * kTileDoubles;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int row = a * 16 + l4 + 4 * k, col = b * 16 + l16;
-          rb[row * LD + J * kTile + col] = acc[k];
-          if (data) Lij[frag_pos(row, col)] = acc[k];
+          for (int k = 0; k < 4; ++k) {
+            const int row = a * 16 + l4 + 4 * k, col = b * 16 + l16;
+            rb[row * LD + J * kTile + col] = acc[k];
+            if (data) Lij[frag_pos(row, col)] = acc[k];
+          }
         }
-        __syncthreads();
-        // right-looking update of the block's later tiles: A(I,J') -= X L(J',J)^T
+        // right-looking update of the block's later tiles: A(I,J') -= X L(J',J)^T,
+        // one 16 x 16 quarter per unit; the next unit's operand is fetched while
+        // the current one runs
         const int jlast = data ? I : nbd - 1;
         const int units = (jlast - J) * 4;
-        for (int un = wid; un < units; un += 4) {
+        int un = wid;
+        double bf[8], bn[8];
+        auto fetch = [&](int uu, double* dst) {
+          const int Jp = J + 1 + (uu >> 2), b2 = uu & 1;
+          if (data && Jp == I) {  // L(I,J) itself: the tile buffer
+#pragma unroll
+            for (int s = 0; s < 8; ++s) dst[s] = xb[(b2 * 16 + l16) * kXS + 4 * s + l4];
+          } else {
+            const double* __restrict__ Lpj = Lt + (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) dst[s] = Lpj[((b2 * 8 + s) << 6) + lane];
+          }
+        };
+        if (un < units) fetch(un, bf);
+        for (; un < units; un += kTileWaves) {
+          if (un + kTileWaves < units) fetch(un + kTileWaves, bn);
           const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
+          double* __restrict__ cp = rb + Jp * kTile + b2 * 16 + l16;
           dbl4 c4;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) c4[k] = rb[(a2 * 16 + l4 + 4 * k) * LD + Jp * kTile + b2 * 16 + l16];
-          const bool own = data && Jp == I;  // L(I,J) itself: read it from the row block
-          const double* __restrict__ Lpj = Lt + (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles;
+          for (int k = 0; k < 4; ++k) c4[k] = cp[(a2 * 16 + l4 + 4 * k) * LD];
 #pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            const double af = -rb[(a2 * 16 + l16) * LD + J * kTile + 4 * s + l4];
-            const double bf = own ? rb[(b2 * 16 + l16) * LD + J * kTile + 4 * s + l4] : Lpj[((b2 * 8 + s) << 6) + lane];
-            c4 = mfma_f64(af, bf, c4);
-          }
+          for (int s = 0; s < 8; ++s) c4 = mfma_f64(-xb[(a2 * 16 + l16) * kXS + 4 * s + l4], bf[s], c4);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) rb[(a2 * 16 + l4 + 4 * k) * LD + Jp * kTile + b2 * 16 + l16] = c4[k];
+          for (int k = 0; k < 4; ++k) cp[(a2 * 16 + l4 + 4 * k) * LD] = c4[k];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) bf[s] = bn[s];
         }
         __syncthreads();
       }
       if (data) {
-        // right-hand side of the block: f~_I - sum_{J<I} L(I,J) y_J, eight lanes per row
+        // right-hand side of the block: f~_I - sum_{J<I} L(I,J) y_J, sixteen lanes per row
         {
-          const int rr = tid >> 3, sub = tid & 7;
+          const int rr = tid >> 4, sub = tid & 15;
           double t = 0.0;
-          for (int c = sub; c < I * kTile; c += 8) t += rb[rr * LD + c] * sy[c];
-          t = sum8(t);
+          for (int c = sub; c < I * kTile; c += 16) t += rb[rr * LD + c] * sy[c];
+          t = sum16(t);
           if (sub == 0) srhs[rr] = pf[I * kTile + rr] - t;
         }
         __syncthreads();
@@ -898,16 +922,16 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
         }
         __syncthreads();
       } else {
-        // query rows of the block: variance and mean, eight lanes per row
-        const int rr = tid >> 3, sub = tid & 7;
+        // query rows of the block: variance and mean, sixteen lanes per row
+        const int rr = tid >> 4, sub = tid & 15;
         double zz = 0.0, zy = 0.0;
-        for (int c = sub; c < nbd * kTile; c += 8) {
+        for (int c = sub; c < nbd * kTile; c += 16) {
           const double z = rb[rr * LD + c];
           zz += z * z;
           zy += z * sy[c];
         }
-        zz = sum8(zz);
-        zy = sum8(zy);
+        zz = sum16(zz);
+        zy = sum16(zy);
         const int q = (I - nbd) * kTile + rr;
         if (sub == 0 && q < P.m) {
           float gu, gw;
@@ -942,7 +966,6 @@ const char* const kFam[3][kNumBuckets] = {
      "refine_f64_n512"},
     {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128", "fit_f64_n256", "fit_f64_n512"}};
 
-constexpr int kFirstTileBucket = 5;  // buckets of 256 and 512 points: tiled FP64 solver
 
 struct Launch {
   hipStream_t stream;
@@ -998,18 +1021,28 @@ int tile_per_cu() {
   return per_cu;
 }
 
+int tile_per_cu_of(int b) {
+  switch (kBucketCap[b]) {
+    case 96: return tile_per_cu<96>();
+    case 128: return tile_per_cu<128>();
+    case 256: return tile_per_cu<256>();
+    default: return tile_per_cu<512>();
+  }
+}
+
+// Buckets from this one on run the tiled solver.
+int first_tile_bucket(const vgpr_ctx* ctx) { return ctx->tune.tile_first_bucket; }
+
 // Workgroups of the tiled solver for bucket b: at most one resident wave of them,
 // since each holds a scratch area.
 int tile_grid(const vgpr_ctx* ctx, int b, int grid_scale) {
-  const int per_cu = b == kFirstTileBucket ? tile_per_cu<256>() : tile_per_cu<512>();
   const int gs = grid_scale < 4 ? grid_scale : 4;
-  const int64_t g = (int64_t)per_cu * ctx->cu_count * gs / 4;
+  const int64_t g = (int64_t)tile_per_cu_of(b) * ctx->cu_count * gs / 4;
   return g < 1 ? 1 : (int)g;
 }
 
 size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b) {
-  const int per_cu = b == kFirstTileBucket ? tile_per_cu<256>() : tile_per_cu<512>();
-  return (size_t)per_cu * ctx->cu_count * tile_scratch_doubles(b == kFirstTileBucket ? 256 : 512) * sizeof(double);
+  return (size_t)tile_per_cu_of(b) * ctx->cu_count * tile_scratch_doubles(kBucketCap[b]) * sizeof(double);
 }
 
 vgpr_status launch_tile(vgpr_ctx* ctx, int b, const FitParams& P, const FitArgs& io, const float4* staged,
@@ -1017,12 +1050,21 @@ vgpr_status launch_tile(vgpr_ctx* ctx, int b, const FitParams& P, const FitArgs&
   int64_t grid = tile_grid(ctx, b, l.grid_scale);
   if (grid > l.max_items) grid = l.max_items;
   ProfScope ps(ctx, l.fam, l.stream);
-  if (b == kFirstTileBucket)
-    hipLaunchKernelGGL(fit_tile_kernel<256>, dim3((unsigned)grid), dim3(kTileThreads), 0, l.stream, P, io, l.recs,
-                       staged, l.count, l.next, scratch);
-  else
-    hipLaunchKernelGGL(fit_tile_kernel<512>, dim3((unsigned)grid), dim3(kTileThreads), 0, l.stream, P, io, l.recs,
-                       staged, l.count, l.next, scratch);
+  const dim3 g((unsigned)grid), t(kTileThreads);
+  switch (kBucketCap[b]) {
+    case 96:
+      hipLaunchKernelGGL(fit_tile_kernel<96>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
+      break;
+    case 128:
+      hipLaunchKernelGGL(fit_tile_kernel<128>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
+      break;
+    case 256:
+      hipLaunchKernelGGL(fit_tile_kernel<256>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
+      break;
+    default:
+      hipLaunchKernelGGL(fit_tile_kernel<512>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
+      break;
+  }
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -1051,7 +1093,7 @@ vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, c
 
 size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts) {
   size_t tiles = 0;
-  for (int b = kFirstTileBucket; b < kNumBuckets; ++b)
+  for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
     if (max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b));
   return Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
          Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
@@ -1075,7 +1117,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   uint32_t* ctr = cv.take<uint32_t>(64);  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch
   double* tile_scratch[kNumBuckets] = {};
-  for (int b = kFirstTileBucket; b < kNumBuckets; ++b)
+  for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
     if (p->max_pts > kBucketCap[b - 1]) tile_scratch[b] = cv.take<double>(tile_bucket_bytes(ctx, b) / sizeof(double));
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
 
@@ -1122,7 +1164,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   };
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
-    const bool tiled = b >= kFirstTileBucket;
+    const bool tiled = b >= first_tile_bucket(ctx);
     const bool wave = wave_ok && b <= tu.wave_last_bucket;
     const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket && !tiled;
     FitParams Pb = P;

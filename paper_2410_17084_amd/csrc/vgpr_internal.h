@@ -50,7 +50,7 @@ struct vgpr_ctx {
   std::string last_error;
   int cu_count = 0;
   int live_maps = 0;          // maps created on this context and not yet destroyed
-  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}};
+  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}, 5};
   hipStream_t aux[2] = {nullptr, nullptr};  // side streams the solver buckets fork onto
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[2] = {nullptr, nullptr};

@@ -48,20 +48,24 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
-                ("grid_scale", C.c_int32 * 7)]
+                ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,
-                "streams": self.streams, "grid_scale": list(self.grid_scale)}
+                "streams": self.streams, "grid_scale": list(self.grid_scale),
+                "tile_first_bucket": self.tile_first_bucket}
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tuning":
+        """Entries missing from `d` (older caches) take the library defaults."""
         t = cls()
-        t.fp32_last_bucket = d["fp32_last_bucket"]
-        t.wave_last_bucket = d["wave_last_bucket"]
-        t.streams = d["streams"]
-        for i, g in enumerate(d["grid_scale"]):
-            t.grid_scale[i] = g
+        t.fp32_last_bucket = d.get("fp32_last_bucket", 0)
+        t.wave_last_bucket = d.get("wave_last_bucket", 2)
+        t.streams = d.get("streams", 3)
+        gs = list(d.get("grid_scale", []))
+        for i in range(7):
+            t.grid_scale[i] = gs[i] if i < len(gs) else 4
+        t.tile_first_bucket = d.get("tile_first_bucket", 5)
         return t
 
 

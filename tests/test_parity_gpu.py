@@ -367,17 +367,19 @@ def test_tuning_choices(env):
             for g, r in zip(got, ref):
                 assert np.array_equal(g, r, equal_nan=True)
         for change, prec in [(dict(wave_last_bucket=-1), vgpr.PREC_FP64), (dict(wave_last_bucket=0), vgpr.PREC_FP64),
-                             (dict(fp32_last_bucket=2), vgpr.PREC_FP32), (dict(fp32_last_bucket=-1), vgpr.PREC_FP32)]:
+                             (dict(fp32_last_bucket=2), vgpr.PREC_FP32), (dict(fp32_last_bucket=-1), vgpr.PREC_FP32),
+                             (dict(tile_first_bucket=3), vgpr.PREC_FP64), (dict(tile_first_bucket=4), vgpr.PREC_FP32)]:
             say("tuning (within tolerance)", change, prec)
             t = dict(default)
             t.update(change)
             ctx.set_tuning(vgpr.Tuning.from_dict(t))
             out = ctx.fit_predict(x, gv, p.replace(precision=prec))
             parity.compare_fit(xyz, ov, prm, *out)
-        with pytest.raises(vgpr.VgprError):
-            bad = dict(default)
-            bad["streams"] = 2
-            ctx.set_tuning(vgpr.Tuning.from_dict(bad))
+        for key, val in (("streams", 2), ("tile_first_bucket", 2), ("wave_last_bucket", 3)):
+            with pytest.raises(vgpr.VgprError):
+                bad = dict(default)
+                bad[key] = val
+                ctx.set_tuning(vgpr.Tuning.from_dict(bad))
     finally:
         ctx.set_tuning(vgpr.Tuning.from_dict(default))
 
