@@ -29,6 +29,37 @@ from paper_2410_17084_amd import configs, synth  # noqa: E402
 
 PEAK = {"f32": 157.3, "f64": 78.6}  # TFLOP/s, MI355X vector FP32 / FP64
 HBM_PEAK = 8000.0                   # GB/s
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_spin32_batch64.json")
+
+
+def source_hash() -> str:
+    """Hash of the library sources (kernels and ABI header): ties stored counter readings to the code."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2410_17084_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)) + [os.path.join(HERE, "include", "vgpr.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family: str, tuning: dict, precision: str):
+    """HBM bytes per launch of `family` from the stored FETCH_SIZE / WRITE_SIZE readings.
+
+    None unless the readings were taken on the current sources with the same
+    launch choices and precision.
+    """
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash() or d.get("tuning") != tuning or d.get("precision") != precision:
+        return None
+    e = d.get("families", {}).get(family)
+    return None if e is None else float(e["bytes_per_launch"])
 BUCKETS = (16, 32, 64, 96, 128, 256, 512)
 
 
@@ -240,6 +271,7 @@ def main():
                     "voxels_per_launch": int(sel.sum() / launches_per_step),
                     "algorithmic_bytes_per_launch": float(by[sel].sum() / launches_per_step),
                     "hbm_frac": float(by[sel].sum() / launches_per_step) / per_launch_s / 1e9 / HBM_PEAK}
+            roof["traffic"] = measured_traffic(dom, ctx.tuning().as_dict(), args.precision)
         tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
