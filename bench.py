@@ -142,6 +142,8 @@ def main():
                     help="length of the 8-stream 10 Hz serving run (0 skips it)")
     ap.add_argument("--serve-frames", type=int, default=10, help="distinct frames generated per stream (cycled)")
     ap.add_argument("--autotune", action="store_true", help="search launch choices first and cache them")
+    ap.add_argument("--graph-steps", type=int, default=20,
+                    help="steps of the captured-graph form of the batch (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -276,8 +278,51 @@ def main():
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
 
+    # batched form captured as a graph: the same batch voxelized into fixed
+    # buffers, then one replay of the captured fit_predict per step
+    graph = None
+    if args.graph_steps > 0:
+        gst = torch.cuda.Stream()
+        gctx = vgpr.Context(0, stream=gst)
+        gctx.set_tuning(ctx.tuning())
+        torch.cuda.synchronize()
+        n0 = ctypes_voxelize(gctx, vgpr, xyz, p, fo, keys, offs, cnts, perm)
+        gv = vgpr.Voxels(keys[:n0], offs[:n0], cnts[:n0], perm, n0, [], 0)
+        gout = (torch.empty_like(out[0]), torch.empty_like(out[1]), torch.empty_like(out[2]))
+        g = gctx.fit_graph(xyz, gv, p, out=gout)
+        for _ in range(args.warmup):
+            g.launch()
+        gst.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            if ctypes_voxelize(gctx, vgpr, xyz, p, fo, keys, offs, cnts, perm) != n0:
+                raise RuntimeError("batch voxel count changed between graph replays")
+            g.launch()
+        gst.synchronize()
+        g_step = (time.perf_counter() - t1) / args.graph_steps
+        t1 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            g.launch()
+        gst.synchronize()
+        g_fit = (time.perf_counter() - t1) / args.graph_steps
+        t1 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            gctx.fit_predict(xyz, gv, p, out=gout)
+        gst.synchronize()
+        e_fit = (time.perf_counter() - t1) / args.graph_steps
+        same = all(bool(torch.equal(a[:n0], b[:n0])) if a.dtype != torch.float32 else
+                   bool(torch.equal(torch.nan_to_num(a[:n0], nan=-7.0), torch.nan_to_num(b[:n0], nan=-7.0)))
+                   for a, b in zip(gout, out))
+        graph = {"ms_per_step": g_step * 1e3, "solves_per_s": n_solved / g_step,
+                 "fit_ms_graph": g_fit * 1e3, "fit_ms_eager": e_fit * 1e3, "outputs_equal_eager": same,
+                 "what": "voxelize + one replay of the captured fit_predict per step, same batch"}
+        g.close()
+        gctx.close()
+        log(f"graph: {graph}")
+
     # single-frame latency (voxelize + fit of one scan, host clock, synchronised)
     lat = []
+    lat_solved = []
     for i in range(args.latency_frames):
         f = i % args.frames
         a, b = int(fo[f]), int(fo[f + 1])
@@ -285,10 +330,12 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         vf = ctx.voxelize(xf, p)
-        ctx.fit_predict(xf, vf, p)
+        _, _, sf = ctx.fit_predict(xf, vf, p)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
+        lat_solved.append(int(((sf & vgpr.ST_SOLVED) != 0).sum().item()))
     lat = np.array(lat[5:] if len(lat) > 10 else lat)
+    lat_solved = np.array(lat_solved[5:] if len(lat_solved) > 10 else lat_solved)
     if len(lat):
         log(f"latency p50 {np.percentile(lat, 50):.3f} ms")
 
@@ -321,6 +368,10 @@ def main():
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "frames": int(len(lat)), "what": "one scan: voxelize + fit_predict + sync"}
                        if len(lat) else None),
+        "plain_single_scan": ({"solves_per_s": float(lat_solved.sum() / (lat.sum() / 1e3)),
+                               "what": "one scan per call, synchronised (the unbatched path)"}
+                              if len(lat) else None),
+        "batched_graph": graph,
         "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(rec), flush=True)

@@ -228,6 +228,37 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
                            int64_t* h_n_converged);
 
 /*
+ * Captured form of vgpr_fit_predict (the batching form: every size bucket's
+ * persistent launch, the side-stream fork and join, recorded once as a HIP
+ * graph and replayed with one launch).
+ *
+ * vgpr_fit_graph_create takes exactly the arguments of vgpr_fit_predict and
+ * records that call on the context's stream, which must not be the default
+ * (NULL) stream. Nothing runs at capture time. Every buffer pointer, n_pts,
+ * n_vox, the parameters and the context's launch choices are fixed in the
+ * graph; the buffers' contents are read when the graph runs, so a replay
+ * after the inputs were rewritten (for example a new batch voxelized into the
+ * same buffers with the same n_vox) computes that batch. The caller keeps the
+ * buffers alive and unchanged in size until vgpr_graph_destroy. The graph owns
+ * its scratch (allocated at creation inside the context's HBM budget).
+ * Errors: E_INVALID (default stream, n_vox or n_pts <= 0), E_BUDGET / E_NOMEM
+ * for the scratch, E_DEVICE if capture or instantiation fails.
+ *
+ * vgpr_graph_launch enqueues one replay on the context's stream (asynchronous,
+ * like vgpr_fit_predict). vgpr_graph_destroy waits for the context's stream
+ * and frees the graph; a context cannot be destroyed while graphs are alive.
+ */
+typedef struct vgpr_graph vgpr_graph;
+
+VGPR_API vgpr_status vgpr_fit_graph_create(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts,
+                                           const uint64_t* d_keys, const int32_t* d_offsets,
+                                           const int32_t* d_counts, const int32_t* d_perm, int64_t n_vox,
+                                           const float* d_noise_var, const vgpr_params* params, float* d_out,
+                                           int8_t* d_axis, uint8_t* d_status, vgpr_graph** out);
+VGPR_API vgpr_status vgpr_graph_launch(vgpr_graph* graph);
+VGPR_API vgpr_status vgpr_graph_destroy(vgpr_graph* graph);
+
+/*
  * Launch choices of vgpr_fit_predict. streams and grid_scale change only
  * timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
  * change the rounding (which arithmetic and which solver a voxel gets), and

@@ -187,6 +187,7 @@ vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget_bytes, v
 vgpr_status vgpr_destroy(vgpr_ctx* ctx) {
   if (!ctx) return VGPR_E_INVALID;
   if (ctx->live_maps > 0) return fail(ctx, VGPR_E_INVALID, "destroy the context's maps first");
+  if (ctx->live_graphs > 0) return fail(ctx, VGPR_E_INVALID, "destroy the context's graphs first");
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);

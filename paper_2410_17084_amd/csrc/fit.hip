@@ -1100,7 +1100,8 @@ size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max
          Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
 }
 
-vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset) {
+vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset,
+                             char* fixed_work) {
   if (a.n_vox < 0 || a.n_vox >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_vox out of range");
   if (a.n_pts < 0 || a.n_pts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_pts out of range");
   if (a.n_vox == 0) return VGPR_OK;
@@ -1108,9 +1109,12 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     return fail(ctx, VGPR_E_INVALID, "null device pointer");
   if (reinterpret_cast<uintptr_t>(a.out) & 15) return fail(ctx, VGPR_E_INVALID, "d_out must be 16-byte aligned");
   const int m = p->grid_side * p->grid_side;
-  vgpr_status st = reserve_work(ctx, work_offset + fit_work_bytes(ctx, a.n_vox, a.n_pts, p->max_pts));
-  if (st != VGPR_OK) return st;
-  Carver cv(static_cast<char*>(ctx->work.ptr) + work_offset);
+  vgpr_status st = VGPR_OK;
+  if (!fixed_work) {
+    st = reserve_work(ctx, work_offset + fit_work_bytes(ctx, a.n_vox, a.n_pts, p->max_pts));
+    if (st != VGPR_OK) return st;
+  }
+  Carver cv(fixed_work ? fixed_work : static_cast<char*>(ctx->work.ptr) + work_offset);
   SlotRec* recs = cv.take<SlotRec>((size_t)a.n_vox * kNumBuckets);
   float4* staged = cv.take<float4>((size_t)a.n_pts);
   int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
@@ -1208,4 +1212,94 @@ extern "C" vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64
   if (hipSetDevice(ctx->device) != hipSuccess) return vgpr::fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
   vgpr::FitArgs a{d_xyz, n_pts, d_keys, d_offsets, d_counts, d_perm, d_noise_var, n_vox, d_out, d_axis, d_status};
   return vgpr::fit_predict_impl(ctx, a, params, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Captured fit_predict: the same launches recorded once as a HIP graph and
+// replayed. The graph owns its scratch, so later calls that grow the context
+// workspace cannot invalidate it.
+// ---------------------------------------------------------------------------
+struct vgpr_graph {
+  vgpr_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* work = nullptr;
+  size_t bytes = 0;
+};
+
+extern "C" vgpr_status vgpr_fit_graph_create(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts,
+                                             const uint64_t* d_keys, const int32_t* d_offsets,
+                                             const int32_t* d_counts, const int32_t* d_perm, int64_t n_vox,
+                                             const float* d_noise_var, const vgpr_params* params, float* d_out,
+                                             int8_t* d_axis, uint8_t* d_status, vgpr_graph** out) {
+  using namespace vgpr;
+  if (!ctx || !out) return VGPR_E_INVALID;
+  *out = nullptr;
+  vgpr_status st = check_params(ctx, params);
+  if (st != VGPR_OK) return st;
+  if (ctx->stream == nullptr) return fail(ctx, VGPR_E_INVALID, "graph capture needs a context on a non-default stream");
+  if (n_vox <= 0 || n_vox >= (int64_t(1) << 31) || n_pts <= 0 || n_pts >= (int64_t(1) << 31))
+    return fail(ctx, VGPR_E_INVALID, "graph capture needs 0 < n_vox, n_pts < 2^31");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  st = ensure_aux(ctx);
+  if (st != VGPR_OK) return st;
+  auto* g = new vgpr_graph();
+  g->ctx = ctx;
+  g->bytes = fit_work_bytes(ctx, n_vox, n_pts, params->max_pts);
+  st = alloc_owned(ctx, &g->work, g->bytes);
+  if (st != VGPR_OK) {
+    delete g;
+    return st;
+  }
+  FitArgs a{d_xyz, n_pts, d_keys, d_offsets, d_counts, d_perm, d_noise_var, n_vox, d_out, d_axis, d_status};
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;  // no timing events inside the graph
+  hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = fit_predict_impl(ctx, a, params, 0, static_cast<char*>(g->work));
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->stream, &graph);
+    g->graph = graph;
+    if (st == VGPR_OK && e2 != hipSuccess) st = hip_fail(ctx, e2, "hipStreamEndCapture");
+  } else {
+    st = hip_fail(ctx, e, "hipStreamBeginCapture");
+  }
+  ctx->profiling = prof;
+  if (st == VGPR_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = hip_fail(ctx, e, "hipGraphInstantiate");
+  }
+  if (st != VGPR_OK) {
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    free_owned(ctx, g->work, g->bytes);
+    delete g;
+    return st;
+  }
+  ctx->live_graphs += 1;
+  *out = g;
+  return VGPR_OK;
+}
+
+extern "C" vgpr_status vgpr_graph_launch(vgpr_graph* g) {
+  using namespace vgpr;
+  if (!g) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = g->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  VGPR_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
+  return VGPR_OK;
+}
+
+extern "C" vgpr_status vgpr_graph_destroy(vgpr_graph* g) {
+  using namespace vgpr;
+  if (!g) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = g->ctx;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);  // no replay may still use the scratch
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  free_owned(ctx, g->work, g->bytes);
+  ctx->live_graphs -= 1;
+  delete g;
+  return VGPR_OK;
 }

@@ -50,6 +50,7 @@ struct vgpr_ctx {
   std::string last_error;
   int cu_count = 0;
   int live_maps = 0;          // maps created on this context and not yet destroyed
+  int live_graphs = 0;        // captured graphs created on this context and not yet destroyed
   vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}, 5};
   hipStream_t aux[2] = {nullptr, nullptr};  // side streams the solver buckets fork onto
   hipEvent_t fork_ev = nullptr;
@@ -142,6 +143,9 @@ struct FitArgs {
   uint8_t* status;
 };
 size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts);
-vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset);
+// fixed_work: scratch the caller owns (at least fit_work_bytes); when null the
+// context workspace from work_offset on is used (and grown if needed).
+vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset,
+                             char* fixed_work = nullptr);
 
 }  // namespace vgpr

@@ -23,7 +23,7 @@ SYMBOLS = [
     "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
     "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
-    "vgpr_set_tuning", "vgpr_get_tuning",
+    "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
 ]
 
 
@@ -107,6 +107,9 @@ def load():
         "vgpr_profile_read": (C.c_int, [vp, C.c_char_p, P(C.c_double), P(i64)]),
         "vgpr_set_tuning": (C.c_int, [vp, P(Tuning)]),
         "vgpr_get_tuning": (C.c_int, [vp, P(Tuning)]),
+        "vgpr_fit_graph_create": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp, P(vp)]),
+        "vgpr_graph_launch": (C.c_int, [vp]),
+        "vgpr_graph_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -154,11 +157,14 @@ class Context:
             raise VgprError(st, f"vgpr_create failed: {self.lib.vgpr_status_str(st).decode()}")
         self.h = h
         self._maps = weakref.WeakSet()
+        self._graphs = weakref.WeakSet()
 
     def close(self):
         if getattr(self, "h", None):
             for m in list(self._maps):
                 m.close()
+            for g in list(self._graphs):
+                g.close()
             self._check(self.lib.vgpr_destroy(self.h), "vgpr_destroy")
             self.h = None
 
@@ -220,6 +226,30 @@ class Context:
         self._check(st, "vgpr_fit_predict")
         return o[:v], ax[:v], stt[:v]
 
+    def fit_graph(self, xyz, vox: Voxels, params: Params, noise_var=None, out=None) -> "Graph":
+        """Capture this fit_predict call as a replayable graph (vgpr_fit_graph_create).
+
+        The context must run on a non-default stream. The graph keeps references
+        to every tensor it reads or writes; replays read their current contents.
+        """
+        torch = self.torch
+        m = params.grid_side * params.grid_side
+        dev = xyz.device
+        v = vox.n_vox
+        if out is None:
+            out = (torch.empty((max(v, 1), m, 4), dtype=torch.float32, device=dev),
+                   torch.empty(max(v, 1), dtype=torch.int8, device=dev),
+                   torch.empty(max(v, 1), dtype=torch.uint8, device=dev))
+        o, ax, stt = out
+        h = C.c_void_p()
+        st = self.lib.vgpr_fit_graph_create(self.h, _ptr(xyz), xyz.numel() // 3, _ptr(vox.keys), _ptr(vox.offsets),
+                                            _ptr(vox.counts), _ptr(vox.perm), v, _ptr(noise_var), C.byref(params),
+                                            _ptr(o), _ptr(ax), _ptr(stt), C.byref(h))
+        self._check(st, "vgpr_fit_graph_create")
+        g = Graph(self, h, (xyz, vox, noise_var, out), (o[:v], ax[:v], stt[:v]))
+        self._graphs.add(g)
+        return g
+
     # -- launch tuning ----------------------------------------------------------
     def tuning(self) -> Tuning:
         t = Tuning()
@@ -239,6 +269,31 @@ class Context:
         self._check(self.lib.vgpr_profile_read(self.h, name.encode(), C.byref(ms), C.byref(cnt)),
                     "vgpr_profile_read")
         return ms.value, cnt.value
+
+
+class Graph:
+    """A captured fit_predict (vgpr_graph); `outputs` are views of the buffers it writes."""
+
+    def __init__(self, ctx: Context, h, keep, outputs):
+        self.ctx = ctx
+        self.h = h
+        self._keep = keep
+        self.outputs = outputs
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.vgpr_graph_launch(self.h), "vgpr_graph_launch")
+        return self.outputs
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.vgpr_graph_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Map:

@@ -383,3 +383,51 @@ def test_tuning_choices(env):
     finally:
         ctx.set_tuning(vgpr.Tuning.from_dict(default))
 
+
+
+def test_fit_graph_replays(env):
+    """Captured fit_predict: each replay (with eager work and syncs in between)
+    equals the eager call bit for bit, and a replay after the inputs change
+    computes the new inputs (checked against the oracle)."""
+    torch, vgpr, _ = env
+    st = torch.cuda.Stream()
+    ctx = vgpr.Context(0, stream=st)
+    try:
+        xyz = synth.spin_scan(synth.frame_seed(2, 5), n_beams=32, n_az=1024)
+        w = configs.params_for("spin32")
+        p = parity.gpu_params(vgpr, w)
+        x = dev(torch, xyz)
+        noise = torch.full((len(xyz),), 1e-3, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        say("fit graph: capture", len(xyz))
+        vox = ctx.voxelize(x, p)
+        ref = [t.cpu().numpy() for t in ctx.fit_predict(x, vox, p, noise_var=noise)]
+        g = ctx.fit_graph(x, vox, p, noise_var=noise)
+        for rep in range(3):
+            say("fit graph: replay", rep)
+            eager = ctx.fit_predict(x, vox, p, noise_var=noise)
+            st.synchronize()
+            out = g.launch()
+            st.synchronize()
+            for a, b in zip(out, ref):
+                assert np.array_equal(a.cpu().numpy(), b, equal_nan=True)
+            for a, b in zip(eager, ref):
+                assert np.array_equal(a.cpu().numpy(), b, equal_nan=True)
+        new_noise = rng(16).uniform(2e-4, 5e-3, size=len(xyz)).astype(np.float32)
+        noise.copy_(torch.from_numpy(new_noise))
+        torch.cuda.synchronize()
+        say("fit graph: replay on new noise")
+        out = g.launch()
+        st.synchronize()
+        ov = O.voxelize(xyz, w["voxel_size"])
+        parity.compare_fit(xyz, ov, parity.oracle_params(w), *out, noise=new_noise.astype(np.float64))
+        eager = ctx.fit_predict(x, vox, p, noise_var=noise)
+        st.synchronize()
+        for a, b in zip(out, eager):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy(), equal_nan=True)
+        g.close()
+        with pytest.raises(vgpr.VgprError):
+            vgpr.Context(0, stream=torch.cuda.default_stream()).fit_graph(x, vox, p)
+    finally:
+        st.synchronize()
+        ctx.close()
