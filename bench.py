@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default="fp32")
     ap.add_argument("--latency-frames", type=int, default=60)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -173,7 +173,7 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
         del src, dst
 
-    prec = vgpr.PREC_FP32 if args.precision == "fp32" else vgpr.PREC_FP64
+    prec = {"fp32": vgpr.PREC_FP32, "fp64": vgpr.PREC_FP64, "mixed": vgpr.PREC_MIXED}[args.precision]
     p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
     p.precision = prec
     ctx = vgpr.Context(0)
@@ -356,11 +356,11 @@ def main():
         "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+bf16"}[args.precision], "data": "synthetic",
         "config": {"workload": f"spin32 batch: {args.frames} seeded 32-beam x 1800-azimuth spinning scans "
                                f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step), voxel 0.5 m, "
                                f"cap 128, tau 3, 8x8 grid, l 0.25 m, noise 1e-3",
-                   "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec == 0 else ""),
+                   "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec != 2 else ""),
                    "parallelism": "1 GPU"},
         "dense_pts_per_s": dense,
         "tuning": ctx.tuning().as_dict(),
@@ -406,7 +406,8 @@ def serve_leg(args, vgpr) -> dict:
 
 
 FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
-    [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS]
+    [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS] + \
+    [f"fit_mix_n{c}" for c in BUCKETS]
 
 
 def ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm) -> int:

@@ -77,7 +77,13 @@ enum {
   VGPR_PREC_FP32 = 0,  /* voxels of up to 16 points: FP32 build and LDL^T, and those whose
                           refinement score exceeds refine_threshold are re-solved in FP64;
                           larger voxels run in FP64 directly */
-  VGPR_PREC_MIXED = 1, /* reserved: BF16-MFMA cross-covariance form (returns E_UNSUPPORTED) */
+  VGPR_PREC_MIXED = 1, /* buckets below tile_first_bucket as in FP32 mode; larger voxels: FP32
+                          kernel build and tiled Cholesky on the FP32 matrix cores, the query
+                          (cross-covariance) tile products in split BF16 (hi x hi + hi x lo +
+                          lo x hi) with FP32 accumulation, the mean from K*^T alpha in FP64
+                          with alpha = (K + S)^-1 f~ from the FP32 factor and, when
+                          n s_f^2 / min pivot exceeds cond_threshold, one FP64 residual
+                          refinement step of alpha (status REFINED) */
   VGPR_PREC_FP64 = 2   /* FP64 build and LDL^T for every voxel */
 };
 
@@ -101,6 +107,7 @@ typedef struct {
   int32_t precision;      /* VGPR_PREC_* */
   float refine_threshold; /* FP32 mode: re-solve in FP64 when sum_j |y_j| / d_j exceeds this */
   float converge_var;     /* eta: converged when the max predicted variance <= eta */
+  float cond_threshold;   /* MIXED mode: refine alpha in FP64 when n s_f^2 / min pivot exceeds this */
 } vgpr_params;
 
 /* Fill *p with the paper's defaults (see above), FP32 precision. */
@@ -276,8 +283,9 @@ typedef struct {
   int32_t grid_scale[7];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
                                  workgroups the device holds (1..64; buckets 5 and 6 use at
                                  most 4, one resident wave of workgroups) */
-  int32_t tile_first_bucket;  /* buckets from this one on (3..5) run the tiled FP64 solver on
-                                 the matrix cores; buckets 5 and 6 always do */
+  int32_t tile_first_bucket;  /* buckets from this one on (2..5) run a tiled solver on the
+                                 matrix cores (FP64, or the mixed form in MIXED mode); buckets
+                                 5 and 6 always do */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);

@@ -96,10 +96,11 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
     base = _time_fit(ctx, xyz, vox, params, out, reps)
     best_ms = base
     log(f"[autotune] baseline {base:.3f} ms {cur}")
-    fp32_opts = [-1, 0, 1, 2] if params.precision == vgpr.PREC_FP32 else [cur["fp32_last_bucket"]]
+    fp32_opts = [-1, 0, 1, 2] if params.precision in (vgpr.PREC_FP32, vgpr.PREC_MIXED) else [cur["fp32_last_bucket"]]
     space = [("streams", [1, 3]), ("wave_last_bucket", [0, 1, 2]), ("fp32_last_bucket", fp32_opts)]
-    if params.max_pts > 64:
-        space.append(("tile_first_bucket", [3, 4, 5]))
+    if params.max_pts > 32:
+        space.append(("tile_first_bucket", [b for b in (2, 3, 4, 5) if params.max_pts > (16, 32, 64, 96, 128)[b - 1]]
+                      or [5]))
     caps = (0, 16, 32, 64, 96, 128, 256)  # lower bound of each bucket
     space += [(("grid_scale", b), [2, 4, 8, 16]) for b in range(7) if params.max_pts > caps[b]]
     t0 = time.perf_counter()

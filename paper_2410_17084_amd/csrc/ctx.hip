@@ -118,11 +118,10 @@ vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
     return fail(ctx, VGPR_E_INVALID, "signal_var and length_scale must be > 0, noise_var >= 0");
   if (p->ls_mode != 0 && p->ls_mode != 1) return fail(ctx, VGPR_E_INVALID, "ls_mode must be 0 or 1");
   if (p->frame_mode != 0) return fail(ctx, VGPR_E_UNSUPPORTED, "frame_mode 1 is not supported by this build");
-  if (p->precision != VGPR_PREC_FP32 && p->precision != VGPR_PREC_FP64) {
-    if (p->precision == VGPR_PREC_MIXED)
-      return fail(ctx, VGPR_E_UNSUPPORTED, "VGPR_PREC_MIXED is not supported by this build");
+  if (p->precision != VGPR_PREC_FP32 && p->precision != VGPR_PREC_FP64 && p->precision != VGPR_PREC_MIXED)
     return fail(ctx, VGPR_E_INVALID, "unknown precision");
-  }
+  if (p->precision == VGPR_PREC_MIXED && !(p->cond_threshold > 0.f))
+    return fail(ctx, VGPR_E_INVALID, "cond_threshold must be > 0");
   return VGPR_OK;
 }
 
@@ -147,6 +146,7 @@ void vgpr_params_default(vgpr_params* p) {
   p->precision = VGPR_PREC_FP32;
   p->refine_threshold = 40.0f;
   p->converge_var = 0.3f;
+  p->cond_threshold = 1e4f;
 }
 
 const char* vgpr_status_str(vgpr_status s) {
@@ -229,8 +229,8 @@ vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
   if (t->streams != 1 && t->streams != 3) return fail(ctx, VGPR_E_INVALID, "streams must be 1 or 3");
   for (int b = 0; b < kNumBuckets; ++b)
     if (t->grid_scale[b] < 1 || t->grid_scale[b] > 64) return fail(ctx, VGPR_E_INVALID, "grid_scale must be in [1, 64]");
-  if (t->tile_first_bucket < 3 || t->tile_first_bucket > 5)
-    return fail(ctx, VGPR_E_INVALID, "tile_first_bucket must be in [3, 5]");
+  if (t->tile_first_bucket < 2 || t->tile_first_bucket > 5)
+    return fail(ctx, VGPR_E_INVALID, "tile_first_bucket must be in [2, 5]");
   ctx->tune = *t;
   return VGPR_OK;
 }

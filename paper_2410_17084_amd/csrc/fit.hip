@@ -60,6 +60,7 @@ struct FitParams {
   float noise;
   float eta;
   float refine_thr;
+  float cond_thr;   // mixed mode: FP64 refinement of alpha above this n s_f^2 / min pivot
   double s;         // voxel size (float widened)
   double ell;       // fixed length scale
 };
@@ -952,6 +953,431 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2d. mixed-precision tiled solver (n up to 512): the tiled solver's block
+//     structure with FP32 data tiles and split-BF16 query products
+// ---------------------------------------------------------------------------
+// - K and its Cholesky factor in FP32: tile products on the FP32 matrix cores
+//   (16 x 16 x 4), diagonal tiles by LDL^T on one wavefront.
+// - alpha = L^-T L^-1 f~ by block substitution from the FP32 factor,
+//   accumulated in double; when n s_f^2 / min pivot exceeds cond_threshold,
+//   one refinement step alpha += (K + S)^-1 (f~ - (K + S) alpha) with the
+//   residual in FP64 (kernel entries recomputed in double).
+// - mean_q = mu + sum_c kappa(x*_q, x_c) alpha_c in FP64, so the mean does not
+//   depend on the reduced-precision products below.
+// - z_q = L^-1 k*_q through the same tile recurrences, every query tile
+//   product in BF16 split into high and low parts (hi x hi + hi x lo + lo x hi)
+//   on the 16 x 16 x 32 matrix cores with FP32 accumulation;
+//   var_q = s_f^2 - |z_q|^2.
+// Data tiles, diagonal inverses and their BF16 high/low parts go to the
+// workgroup's scratch area in row-major 32 x 32 tiles.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ flt4 mfma_f32(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma_bf16(bf16x8 a, bf16x8 b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// Accumulator layout of both FP32-accumulating 16 x 16 products: lane l,
+// register k holds element (4 (l / 16) + k, l % 16).
+
+// x = hi + lo with hi the nearest BF16 of x and lo the nearest BF16 of the remainder.
+__device__ __forceinline__ void split_bf16(const float* x, float sign, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = sign * x[e];
+    const __bf16 h = (__bf16)v;
+    hi[e] = h;
+    lo[e] = (__bf16)(v - (float)h);
+  }
+}
+
+__device__ __forceinline__ flt4 mfma_split(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
+                                           flt4 c) {
+  c = mfma_bf16(ah, bh, c);
+  c = mfma_bf16(ah, bl, c);
+  c = mfma_bf16(al, bh, c);
+  return c;
+}
+
+__device__ __forceinline__ float bcastf(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int NPAD>
+__global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams P, FitArgs io,
+                                                                      const SlotRec* __restrict__ recs,
+                                                                      const float4* __restrict__ staged,
+                                                                      const uint32_t* __restrict__ count,
+                                                                      uint32_t* __restrict__ next,
+                                                                      double* __restrict__ scratch) {
+  constexpr int NB = NPAD / kTile;
+  constexpr int NT = NB * (NB + 1) / 2;  // lower data tiles
+  constexpr int LD = NPAD + 4;           // row stride of the row block, in floats
+  __shared__ __attribute__((aligned(16))) float rb[kTile * LD];
+  __shared__ __attribute__((aligned(16))) float xb[kTile * (kTile + 4)];
+  __shared__ double pu[NPAD], pw[NPAD], pf[NPAD];
+  __shared__ float pn[NPAD];
+  __shared__ float sy[NPAD];
+  __shared__ double sal[NPAD], sz[NPAD];
+  __shared__ double sred[16][kTile];
+  __shared__ double smean[kTile];
+  __shared__ float srhs[kTile];
+  __shared__ double squ[kTile], sqw[kTile];
+  __shared__ int s_item;
+  __shared__ int s_fail;
+  __shared__ float s_minpiv;
+  __shared__ unsigned s_maxvar;
+  constexpr int XS = kTile + 4;
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wid = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  // scratch of this workgroup: FP32 tiles, FP32 inverses, then BF16 high / low parts of both
+  float* __restrict__ Lf = reinterpret_cast<float*>(scratch + (size_t)blockIdx.x * tile_scratch_doubles(NPAD));
+  float* __restrict__ Wf = Lf + (size_t)NT * kTileDoubles;
+  __bf16* __restrict__ Lh = reinterpret_cast<__bf16*>(Wf + (size_t)NB * kTileDoubles);
+  __bf16* __restrict__ Ll = Lh + (size_t)NT * kTileDoubles;
+  __bf16* __restrict__ Wh = Ll + (size_t)NT * kTileDoubles;
+  __bf16* __restrict__ Wl = Wh + (size_t)NB * kTileDoubles;
+  const int cnt_items = (int)*count;
+  const double sf2 = (double)P.sf2;
+  const float sf2f = P.sf2;
+
+  for (;;) {
+    if (tid == 0) {
+      s_item = (int)atomicAdd(next, 1u);
+      s_fail = 0;
+      s_minpiv = FLT_MAX;
+      s_maxvar = 0u;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item >= cnt_items) break;
+    const SlotRec r = recs[item];
+    const FrameRec& fr = r.fr;
+    const int n = fr.n;
+    const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
+    const double lam = fr.lam;
+    const float lamf = (float)fr.lam;
+    for (int i = tid; i < NPAD; i += kTileThreads) {
+      double xu = 0, xw = 0, fv = 0;
+      float nz = 0.f;
+      if (i < n) {
+        const float4 pt = staged[r.off + i];
+        xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
+        xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
+        fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
+        nz = pt.w;
+      }
+      pu[i] = xu;
+      pw[i] = xw;
+      pf[i] = fv;
+      pn[i] = nz;
+    }
+    const int nbd = (n + kTile - 1) / kTile;
+    const int nbe = (P.m + kTile - 1) / kTile;
+    __syncthreads();
+
+    // ---- data row blocks: FP32 Cholesky tile by tile ----
+    for (int I = 0; I < nbd; ++I) {
+      const int ncols = (I + 1) * kTile;
+      for (int e = tid; e < kTile * ncols; e += kTileThreads) {
+        const int rr = e / ncols, c = e - rr * ncols;
+        const int i = I * kTile + rr;
+        float val;
+        if (i < n && c < n) {
+          const float du = (float)(pu[i] - pu[c]), dw = (float)(pw[i] - pw[c]);
+          val = sf2f * __expf(-(du * du + dw * dw) * lamf) + (i == c ? pn[i] : 0.f);
+        } else {
+          val = i == c ? 1.f : 0.f;
+        }
+        rb[rr * LD + c] = val;
+      }
+      __syncthreads();
+      for (int J = 0; J < I; ++J) {
+        flt4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int a = (wid >> 1) & 1, b = wid & 1;
+        if (wid < 4) {
+          const float* __restrict__ W = Wf + (size_t)J * kTileDoubles;
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            acc = mfma_f32(rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4], W[(b * 16 + l16) * kTile + 4 * s + l4], acc);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) xb[(a * 16 + 4 * l4 + k) * XS + b * 16 + l16] = acc[k];
+        }
+        __syncthreads();
+        if (wid < 4) {
+          const size_t t = (size_t)(I * (I + 1) / 2 + J) * kTileDoubles;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int row = a * 16 + 4 * l4 + k, col = b * 16 + l16;
+            const float v = acc[k];
+            rb[row * LD + J * kTile + col] = v;
+            const __bf16 h = (__bf16)v;
+            Lf[t + row * kTile + col] = v;
+            Lh[t + row * kTile + col] = h;
+            Ll[t + row * kTile + col] = (__bf16)(v - (float)h);
+          }
+        }
+        const int units = (I - J) * 4;
+        for (int un = wid; un < units; un += kTileWaves) {
+          const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
+          float* __restrict__ cp = rb + Jp * kTile + b2 * 16 + l16;
+          flt4 c4;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c4[k] = cp[(a2 * 16 + 4 * l4 + k) * LD];
+          const float* __restrict__ Bt = Lf + (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles;
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const float bv = Jp == I ? xb[(b2 * 16 + l16) * XS + 4 * s + l4] : Bt[(b2 * 16 + l16) * kTile + 4 * s + l4];
+            c4 = mfma_f32(-xb[(a2 * 16 + l16) * XS + 4 * s + l4], bv, c4);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cp[(a2 * 16 + 4 * l4 + k) * LD] = c4[k];
+        }
+        __syncthreads();
+      }
+      {
+        const int rr = tid >> 4, sub = tid & 15;
+        float t = 0.f;
+        for (int c = sub; c < I * kTile; c += 16) t += rb[rr * LD + c] * sy[c];
+#pragma unroll
+        for (int d = 8; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        if (sub == 0) srhs[rr] = (float)pf[I * kTile + rr] - t;
+      }
+      __syncthreads();
+      if (wid == 0) {
+        float B[kTile];
+        float fy = lane < kTile ? srhs[lane] : 0.f;
+#pragma unroll
+        for (int c = 0; c < kTile; ++c) B[c] = lane < kTile ? rb[lane * LD + I * kTile + c] : 0.f;
+        bool bad = false;
+        float mp = FLT_MAX;
+        for (int j = 0; j < kTile; ++j) {
+          const float cj = B[0];
+          const float d = bcastf(cj, j);
+          const float yj = bcastf(fy, j);
+          const float t = cj / d;
+          const float sd = sqrtf(d);
+          bad |= !(d > 0.f);
+          if (I * kTile + j < n) mp = fminf(mp, d);
+          if (lane == j) {
+            rb[lane * LD + I * kTile + j] = sd;
+            sy[I * kTile + j] = yj / sd;
+          } else if (lane > j && lane < kTile) {
+            rb[lane * LD + I * kTile + j] = cj / sd;
+          }
+          fy -= t * yj;
+#pragma unroll
+          for (int k = 0; k < kTile - 1; ++k) B[k] = B[k + 1] - t * bcastf(cj, (j + 1 + k) & 63);
+          B[kTile - 1] = 0.f;
+        }
+        if (lane == 0) {
+          if (bad) s_fail = 1;
+          s_minpiv = fminf(s_minpiv, mp);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < kTile) {
+          float x[kTile];
+          const float* __restrict__ Ld = rb + I * kTile;
+#pragma unroll
+          for (int i = 0; i < kTile; ++i) {
+            float s = i == lane ? 1.f : 0.f;
+#pragma unroll
+            for (int j = 0; j < i; ++j) s -= Ld[i * LD + j] * x[j];
+            x[i] = s / Ld[i * LD + i];
+          }
+          const size_t t = (size_t)I * kTileDoubles;
+#pragma unroll
+          for (int i = 0; i < kTile; ++i) {
+            const __bf16 h = (__bf16)x[i];
+            Wf[t + i * kTile + lane] = x[i];
+            Wh[t + i * kTile + lane] = h;
+            Wl[t + i * kTile + lane] = (__bf16)(x[i] - (float)h);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- alpha: block back substitution L^T alpha = y, then the optional FP64 refinement ----
+    // back(src, dst): dst = L^-T src (double accumulation, FP32 factor); rows >= n of src are 0
+    auto back = [&](const float* ysrc, const double* dsrc, double* dst) {
+      for (int I = nbd - 1; I >= 0; --I) {
+        const int c = tid & 31, g = tid >> 5;
+        double t = 0.0;
+        for (int J = I + 1; J < nbd; ++J) {
+          const float* __restrict__ T = Lf + (size_t)(J * (J + 1) / 2 + I) * kTileDoubles;
+          for (int rr = g; rr < kTile; rr += 16) t += (double)T[rr * kTile + c] * dst[J * kTile + rr];
+        }
+        sred[g][c] = t;
+        __syncthreads();
+        if (tid < kTile) {
+          double s = ysrc ? (double)ysrc[I * kTile + tid] : dsrc[I * kTile + tid];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) s -= sred[k][tid];
+          sred[0][tid] = s;  // t_I
+        }
+        __syncthreads();
+        if (tid < kTile) {
+          const float* __restrict__ W = Wf + (size_t)I * kTileDoubles;
+          double s = 0.0;
+          for (int cc = tid; cc < kTile; ++cc) s += (double)W[cc * kTile + tid] * sred[0][cc];
+          dst[I * kTile + tid] = s;
+        }
+        __syncthreads();
+      }
+    };
+    back(sy, nullptr, sal);
+    const bool refine = !s_fail && (double)n * sf2 / (double)s_minpiv > (double)P.cond_thr;
+    if (refine) {
+      // residual f~ - (K + S) alpha in FP64, one row per thread
+      for (int i = tid; i < nbd * kTile; i += kTileThreads) {
+        double rsd = 0.0;
+        if (i < n) {
+          rsd = pf[i] - (double)pn[i] * sal[i];
+          for (int c = 0; c < n; ++c) {
+            const double du = pu[i] - pu[c], dw = pw[i] - pw[c];
+            rsd -= sf2 * exp(-(du * du + dw * dw) * lam) * sal[c];
+          }
+        }
+        sz[i] = rsd;
+      }
+      __syncthreads();
+      // forward substitution L w = residual, in place in sz
+      for (int I = 0; I < nbd; ++I) {
+        const int rr = tid & 31, g = tid >> 5;
+        double t = 0.0;
+        for (int J = 0; J < I; ++J) {
+          const float* __restrict__ T = Lf + (size_t)(I * (I + 1) / 2 + J) * kTileDoubles;
+          for (int c = g; c < kTile; c += 16) t += (double)T[rr * kTile + c] * sz[J * kTile + c];
+        }
+        sred[g][rr] = t;
+        __syncthreads();
+        if (tid < kTile) {
+          double s = sz[I * kTile + tid];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) s -= sred[k][tid];
+          sred[0][tid] = s;
+        }
+        __syncthreads();
+        if (tid < kTile) {
+          const float* __restrict__ W = Wf + (size_t)I * kTileDoubles;
+          double s = 0.0;
+          for (int cc = 0; cc <= tid; ++cc) s += (double)W[tid * kTile + cc] * sred[0][cc];
+          sz[I * kTile + tid] = s;
+        }
+        __syncthreads();
+      }
+      // back substitution, in place: delta = L^-T w
+      back(nullptr, sz, sz);
+      for (int i = tid; i < nbd * kTile; i += kTileThreads) sal[i] += sz[i];
+      __syncthreads();
+    }
+
+    // ---- query row blocks: K* in FP32 for z, the mean from alpha in FP64 ----
+    for (int E = 0; E < nbe; ++E) {
+      if (tid < kTile) {
+        const int q = E * kTile + tid;
+        float gu = 0.f, gw = 0.f;
+        if (q < P.m) query_coords(P, fr, q, &gu, &gw);
+        squ[tid] = (double)gu - fr.anc_u;
+        sqw[tid] = (double)gw - fr.anc_w;
+      }
+      __syncthreads();
+      {
+        const int rr = tid >> 4, sub = tid & 15;
+        const int q = E * kTile + rr;
+        double macc = 0.0;
+        for (int c = sub; c < nbd * kTile; c += 16) {
+          float val = 0.f;
+          if (q < P.m && c < n) {
+            const double du = squ[rr] - pu[c], dw = sqw[rr] - pw[c];
+            const double kd = sf2 * exp(-(du * du + dw * dw) * lam);
+            macc += kd * sal[c];
+            val = (float)kd;
+          }
+          rb[rr * LD + c] = val;
+        }
+#pragma unroll
+        for (int d = 8; d >= 1; d >>= 1) macc += __shfl_xor(macc, d, 64);
+        if (sub == 0) smean[rr] = macc;
+      }
+      __syncthreads();
+      for (int J = 0; J < nbd; ++J) {
+        flt4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int a = (wid >> 1) & 1, b = wid & 1;
+        if (wid < 4) {
+          bf16x8 ah, al;
+          split_bf16(rb + (a * 16 + l16) * LD + J * kTile + 8 * l4, 1.f, ah, al);
+          const size_t t = (size_t)J * kTileDoubles + (b * 16 + l16) * kTile + 8 * l4;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Wh + t);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Wl + t);
+          acc = mfma_split(ah, al, bh, bl, acc);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) xb[(a * 16 + 4 * l4 + k) * XS + b * 16 + l16] = acc[k];
+        }
+        __syncthreads();
+        if (wid < 4) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) rb[(a * 16 + 4 * l4 + k) * LD + J * kTile + b * 16 + l16] = acc[k];
+        }
+        const int units = (nbd - 1 - J) * 4;
+        for (int un = wid; un < units; un += kTileWaves) {
+          const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
+          float* __restrict__ cp = rb + Jp * kTile + b2 * 16 + l16;
+          flt4 c4;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c4[k] = cp[(a2 * 16 + 4 * l4 + k) * LD];
+          bf16x8 ah, al;
+          split_bf16(xb + (a2 * 16 + l16) * XS + 8 * l4, -1.f, ah, al);
+          const size_t t = (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles + (b2 * 16 + l16) * kTile + 8 * l4;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Lh + t);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ll + t);
+          c4 = mfma_split(ah, al, bh, bl, c4);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cp[(a2 * 16 + 4 * l4 + k) * LD] = c4[k];
+        }
+        __syncthreads();
+      }
+      {
+        const int rr = tid >> 4, sub = tid & 15;
+        float zz = 0.f;
+        for (int c = sub; c < nbd * kTile; c += 16) {
+          const float z = rb[rr * LD + c];
+          zz += z * z;
+        }
+#pragma unroll
+        for (int d = 8; d >= 1; d >>= 1) zz += __shfl_xor(zz, d, 64);
+        const int q = E * kTile + rr;
+        if (sub == 0 && q < P.m) {
+          float gu, gw;
+          query_coords(P, fr, q, &gu, &gw);
+          const bool failed = s_fail != 0;
+          const double var = sf2 - (double)zz;
+          const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > 0.0 ? var : 0.0);
+          const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + smean[rr]);
+          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = out_row(ax, u, mv, gu, gw, vv);
+          if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
+        }
+        __syncthreads();
+      }
+    }
+    if (tid == 0) {
+      finish_voxel(P, io, r.v, item, r.cnt, fr.axes, s_fail != 0, false, __uint_as_float(s_maxvar), nullptr,
+                   nullptr);
+      if (refine) io.status[r.v] |= (uint8_t)VGPR_ST_REFINED;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename K>
 int occupancy(K kernel, int threads) {
   int nb = 0;
@@ -965,6 +1391,8 @@ const char* const kFam[3][kNumBuckets] = {
     {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n96", "refine_f64_n128", "refine_f64_n256",
      "refine_f64_n512"},
     {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128", "fit_f64_n256", "fit_f64_n512"}};
+const char* const kFamMixed[kNumBuckets] = {"fit_mix_n16", "fit_mix_n32", "fit_mix_n64", "fit_mix_n96",
+                                            "fit_mix_n128", "fit_mix_n256", "fit_mix_n512"};
 
 
 struct Launch {
@@ -1014,57 +1442,69 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
   return VGPR_OK;
 }
 
-template <int NPAD>
+template <int NPAD, bool MIXED>
 int tile_per_cu() {
   static int per_cu = -1;
-  if (per_cu < 0) per_cu = occupancy(fit_tile_kernel<NPAD>, kTileThreads);
+  if (per_cu < 0)
+    per_cu = MIXED ? occupancy(fit_tile_mixed_kernel<NPAD>, kTileThreads) : occupancy(fit_tile_kernel<NPAD>, kTileThreads);
   return per_cu;
 }
 
-int tile_per_cu_of(int b) {
+int tile_per_cu_of(int b, bool mixed) {
   switch (kBucketCap[b]) {
-    case 96: return tile_per_cu<96>();
-    case 128: return tile_per_cu<128>();
-    case 256: return tile_per_cu<256>();
-    default: return tile_per_cu<512>();
+    case 64: return mixed ? tile_per_cu<64, true>() : tile_per_cu<64, false>();
+    case 96: return mixed ? tile_per_cu<96, true>() : tile_per_cu<96, false>();
+    case 128: return mixed ? tile_per_cu<128, true>() : tile_per_cu<128, false>();
+    case 256: return mixed ? tile_per_cu<256, true>() : tile_per_cu<256, false>();
+    default: return mixed ? tile_per_cu<512, true>() : tile_per_cu<512, false>();
   }
 }
 
-// Buckets from this one on run the tiled solver.
+// Buckets from this one on run the tiled solvers.
 int first_tile_bucket(const vgpr_ctx* ctx) { return ctx->tune.tile_first_bucket; }
 
-// Workgroups of the tiled solver for bucket b: at most one resident wave of them,
+// Workgroups of a tiled solver for bucket b: at most one resident wave of them,
 // since each holds a scratch area.
-int tile_grid(const vgpr_ctx* ctx, int b, int grid_scale) {
+int tile_grid(const vgpr_ctx* ctx, int b, bool mixed, int grid_scale) {
   const int gs = grid_scale < 4 ? grid_scale : 4;
-  const int64_t g = (int64_t)tile_per_cu_of(b) * ctx->cu_count * gs / 4;
+  const int64_t g = (int64_t)tile_per_cu_of(b, mixed) * ctx->cu_count * gs / 4;
   return g < 1 ? 1 : (int)g;
 }
 
-size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b) {
-  return (size_t)tile_per_cu_of(b) * ctx->cu_count * tile_scratch_doubles(kBucketCap[b]) * sizeof(double);
+size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b, bool mixed) {
+  return (size_t)tile_per_cu_of(b, mixed) * ctx->cu_count * tile_scratch_doubles(kBucketCap[b]) * sizeof(double);
 }
 
-vgpr_status launch_tile(vgpr_ctx* ctx, int b, const FitParams& P, const FitArgs& io, const float4* staged,
-                        const Launch& l, double* scratch) {
-  int64_t grid = tile_grid(ctx, b, l.grid_scale);
+template <bool MIXED>
+void launch_tile_kernel(int npad, dim3 g, dim3 t, hipStream_t s, const FitParams& P, const FitArgs& io,
+                        const Launch& l, const float4* staged, double* scratch) {
+#define VGPR_TILE_CASE(NP)                                                                                   \
+  case NP:                                                                                                   \
+    if (MIXED)                                                                                               \
+      hipLaunchKernelGGL(fit_tile_mixed_kernel<NP>, g, t, 0, s, P, io, l.recs, staged, l.count, l.next, scratch); \
+    else                                                                                                     \
+      hipLaunchKernelGGL(fit_tile_kernel<NP>, g, t, 0, s, P, io, l.recs, staged, l.count, l.next, scratch);  \
+    break;
+  switch (npad) {
+    VGPR_TILE_CASE(64)
+    VGPR_TILE_CASE(96)
+    VGPR_TILE_CASE(128)
+    VGPR_TILE_CASE(256)
+    default:
+    VGPR_TILE_CASE(512)
+  }
+#undef VGPR_TILE_CASE
+}
+
+vgpr_status launch_tile(vgpr_ctx* ctx, int b, bool mixed, const FitParams& P, const FitArgs& io,
+                        const float4* staged, const Launch& l, double* scratch) {
+  int64_t grid = tile_grid(ctx, b, mixed, l.grid_scale);
   if (grid > l.max_items) grid = l.max_items;
   ProfScope ps(ctx, l.fam, l.stream);
-  const dim3 g((unsigned)grid), t(kTileThreads);
-  switch (kBucketCap[b]) {
-    case 96:
-      hipLaunchKernelGGL(fit_tile_kernel<96>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
-      break;
-    case 128:
-      hipLaunchKernelGGL(fit_tile_kernel<128>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
-      break;
-    case 256:
-      hipLaunchKernelGGL(fit_tile_kernel<256>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
-      break;
-    default:
-      hipLaunchKernelGGL(fit_tile_kernel<512>, g, t, 0, l.stream, P, io, l.recs, staged, l.count, l.next, scratch);
-      break;
-  }
+  if (mixed)
+    launch_tile_kernel<true>(kBucketCap[b], dim3((unsigned)grid), dim3(kTileThreads), l.stream, P, io, l, staged, scratch);
+  else
+    launch_tile_kernel<false>(kBucketCap[b], dim3((unsigned)grid), dim3(kTileThreads), l.stream, P, io, l, staged, scratch);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -1091,10 +1531,11 @@ vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, c
 
 }  // namespace
 
-size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts) {
+size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const vgpr_params* p) {
   size_t tiles = 0;
+  const bool mixed = p->precision == VGPR_PREC_MIXED;
   for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
-    if (max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b));
+    if (p->max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b, mixed));
   return Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
          Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
          Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
@@ -1111,7 +1552,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   const int m = p->grid_side * p->grid_side;
   vgpr_status st = VGPR_OK;
   if (!fixed_work) {
-    st = reserve_work(ctx, work_offset + fit_work_bytes(ctx, a.n_vox, a.n_pts, p->max_pts));
+    st = reserve_work(ctx, work_offset + fit_work_bytes(ctx, a.n_vox, a.n_pts, p));
     if (st != VGPR_OK) return st;
   }
   Carver cv(fixed_work ? fixed_work : static_cast<char*>(ctx->work.ptr) + work_offset);
@@ -1121,8 +1562,10 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   uint32_t* ctr = cv.take<uint32_t>(64);  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch
   double* tile_scratch[kNumBuckets] = {};
+  const bool mixed = p->precision == VGPR_PREC_MIXED;
   for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
-    if (p->max_pts > kBucketCap[b - 1]) tile_scratch[b] = cv.take<double>(tile_bucket_bytes(ctx, b) / sizeof(double));
+    if (p->max_pts > kBucketCap[b - 1])
+      tile_scratch[b] = cv.take<double>(tile_bucket_bytes(ctx, b, mixed) / sizeof(double));
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
 
   // the wave solver holds one query row per lane: grids up to 64 points
@@ -1138,9 +1581,10 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   P.noise = p->noise_var;
   P.eta = p->converge_var;
   P.refine_thr = p->refine_threshold;
+  P.cond_thr = p->cond_threshold;
   P.s = (double)p->voxel_size;
   P.ell = (double)p->length_scale;
-  const bool fp32 = p->precision == VGPR_PREC_FP32;
+  const bool fp32 = p->precision == VGPR_PREC_FP32 || p->precision == VGPR_PREC_MIXED;
   P.mode = 2;
 
   Lists L{recs, nan_list, ctr, a.n_vox};
@@ -1176,7 +1620,8 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     Launch l{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b,
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     if (tiled) {
-      st = launch_tile(ctx, b, Pb, a, staged, l, tile_scratch[b]);
+      if (mixed) l.fam = kFamMixed[b];
+      st = launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
       if (st != VGPR_OK) return st;
       continue;
     }
@@ -1245,7 +1690,7 @@ extern "C" vgpr_status vgpr_fit_graph_create(vgpr_ctx* ctx, const float* d_xyz, 
   if (st != VGPR_OK) return st;
   auto* g = new vgpr_graph();
   g->ctx = ctx;
-  g->bytes = fit_work_bytes(ctx, n_vox, n_pts, params->max_pts);
+  g->bytes = fit_work_bytes(ctx, n_vox, n_pts, params);
   st = alloc_owned(ctx, &g->work, g->bytes);
   if (st != VGPR_OK) {
     delete g;

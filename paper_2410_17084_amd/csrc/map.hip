@@ -312,7 +312,7 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
                o_id = sub(4 * n), o_bs = sub(4 * nblk + 64), o_uk = sub(8 * n), o_uo = sub(4 * n), o_uc = sub(4 * n),
                o_ui = sub(4 * n), o_tot = sub(64);
   head = (head + 255) & ~size_t(255);
-  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_work_bytes(ctx, n, M->max_voxels * (int64_t)p.max_pts, p.max_pts) + (1 << 20));
+  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_work_bytes(ctx, n, M->max_voxels * (int64_t)p.max_pts, &p) + (1 << 20));
   if (st != VGPR_OK) return st;
   char* w = static_cast<char*>(ctx->work.ptr);
   uint64_t* fkeys = reinterpret_cast<uint64_t*>(w + o_k);

@@ -142,7 +142,7 @@ struct FitArgs {
   int8_t* axis;
   uint8_t* status;
 };
-size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, int max_pts);
+size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const vgpr_params* p);
 // fixed_work: scratch the caller owns (at least fit_work_bytes); when null the
 // context workspace from work_offset on is used (and grown if needed).
 vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params* p, size_t work_offset,

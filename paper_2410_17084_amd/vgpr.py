@@ -32,7 +32,7 @@ class Params(C.Structure):
         ("voxel_size", C.c_float), ("max_pts", C.c_int32), ("min_pts", C.c_int32), ("grid_side", C.c_int32),
         ("signal_var", C.c_float), ("length_scale", C.c_float), ("noise_var", C.c_float),
         ("ls_mode", C.c_int32), ("frame_mode", C.c_int32), ("precision", C.c_int32),
-        ("refine_threshold", C.c_float), ("converge_var", C.c_float),
+        ("refine_threshold", C.c_float), ("converge_var", C.c_float), ("cond_threshold", C.c_float),
     ]
 
     def replace(self, **kw) -> "Params":

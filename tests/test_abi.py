@@ -46,8 +46,8 @@ def test_params_default_are_the_papers():
 
 
 def test_params_struct_layout_matches_header():
-    # 12 four-byte fields, no padding
-    assert C.sizeof(vgpr.Params) == 48
+    # 13 four-byte fields, no padding
+    assert C.sizeof(vgpr.Params) == 52
 
 
 def test_status_strings():

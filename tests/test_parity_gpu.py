@@ -188,6 +188,36 @@ def test_fit_large_voxels(env, nq, ls_mode):
         print(stats)
 
 
+@pytest.mark.parametrize("tile_first", [2, 5])
+def test_fit_mixed_precision(env, tile_first):
+    """MIXED mode (FP32 tiles, split-BF16 query products, FP64 mean and refinement)
+    on every size class, two grid sizes, and the 1 m batched scan: within the tolerances."""
+    torch, vgpr, ctx = env
+    default = ctx.tuning().as_dict()
+    t = dict(default)
+    t["tile_first_bucket"] = tile_first
+    ctx.set_tuning(vgpr.Tuning.from_dict(t))
+    try:
+        for nq, ls_mode in ((8, 0), (16, 1)):
+            xyz = _ragged_voxels(31 + nq, LARGE_SIZES)
+            w = dict(configs.params_for("spin32"), max_pts=512, min_pts=3, grid_side=nq, ls_mode=ls_mode)
+            say("fit mixed", tile_first, nq, ls_mode, len(xyz))
+            gv, (out, axis, status) = run_fit(env, xyz, w, precision=vgpr.PREC_MIXED)
+            ov = O.voxelize(xyz, w["voxel_size"])
+            stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status)
+            assert stats["solved"] == len(LARGE_SIZES)
+            print("mixed", tile_first, nq, stats)
+        xyz = synth.spin_scan(synth.frame_seed(3, 0), n_beams=128, n_az=1024)
+        w = configs.params_for("batched")
+        say("fit mixed batched", tile_first, len(xyz))
+        gv, (out, axis, status) = run_fit(env, xyz, w, precision=vgpr.PREC_MIXED)
+        ov = O.voxelize(xyz, w["voxel_size"])
+        stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status)
+        print("mixed batched", tile_first, stats)
+    finally:
+        ctx.set_tuning(vgpr.Tuning.from_dict(default))
+
+
 @pytest.mark.parametrize("scan", ["spin128", "rosette"])
 def test_fit_batched_workload(env, scan):
     """128-beam spinning scan and rosette scan at 1 m voxels, cap 256: every voxel against the oracle."""
@@ -368,14 +398,15 @@ def test_tuning_choices(env):
                 assert np.array_equal(g, r, equal_nan=True)
         for change, prec in [(dict(wave_last_bucket=-1), vgpr.PREC_FP64), (dict(wave_last_bucket=0), vgpr.PREC_FP64),
                              (dict(fp32_last_bucket=2), vgpr.PREC_FP32), (dict(fp32_last_bucket=-1), vgpr.PREC_FP32),
-                             (dict(tile_first_bucket=3), vgpr.PREC_FP64), (dict(tile_first_bucket=4), vgpr.PREC_FP32)]:
+                             (dict(tile_first_bucket=3), vgpr.PREC_FP64), (dict(tile_first_bucket=4), vgpr.PREC_FP32),
+                             (dict(tile_first_bucket=2), vgpr.PREC_FP64), (dict(tile_first_bucket=2), vgpr.PREC_MIXED)]:
             say("tuning (within tolerance)", change, prec)
             t = dict(default)
             t.update(change)
             ctx.set_tuning(vgpr.Tuning.from_dict(t))
             out = ctx.fit_predict(x, gv, p.replace(precision=prec))
             parity.compare_fit(xyz, ov, prm, *out)
-        for key, val in (("streams", 2), ("tile_first_bucket", 2), ("wave_last_bucket", 3)):
+        for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3)):
             with pytest.raises(vgpr.VgprError):
                 bad = dict(default)
                 bad[key] = val
