@@ -23,6 +23,10 @@ What it computes, in the paper's order (Sec. 3.1, Alg. 1; supplementary Alg. S1)
 5. ``fit_predict_voxel`` / ``fit_predict`` - Alg. 1 end to end for one voxel /
    for every voxel of a frame: predicted points (f*, x*) plus their variances.
 6. ``map_update`` - the voxel state machine of Sec. 3.3 (types (a)-(d)).
+7. ``gauss_init`` - Sec. 3.2: one 3D Gaussian per n_r x n_r subgrid of a
+   voxel's predicted points, position = inverse-variance weighted mean,
+   covariance = weighted scatter about it, scale = its diagonal, rotation =
+   identity.
 
 Precision: all arithmetic is float64 on the float32 inputs converted exactly.
 Library primitives used as single steps: ``numpy.argsort`` (stable sort),
@@ -438,3 +442,40 @@ class VoxelMap:
 
 def with_params(p: Params, **kw) -> Params:
     return replace(p, **kw)
+
+
+def gauss_init(out: np.ndarray, status: np.ndarray, grid_side: int, n_r: int, var_floor: float) -> np.ndarray:
+    """Initial 3D Gaussians of Sec. 3.2 from predicted grids.
+
+    out: (V, m, 4) predicted points (x, y, z) and variances, m = grid_side^2,
+    row q = i * grid_side + j. The grid splits into n_s x n_s subgrids of
+    n_r x n_r points (n_s = grid_side / n_r); subgrid beta = bi * n_s + bj
+    holds rows i in [bi n_r, (bi + 1) n_r), columns j in [bj n_r, (bj + 1) n_r).
+    Each point gets the weight w = 1 / var (var raised to var_floor first, so a
+    zero variance gives a finite weight); the Gaussian's position is the
+    weighted mean p = sum w P / sum w, its covariance Phi = Q^T diag(w) Q / sum w
+    with Q = P - p, its scale S = diag(Phi) and its rotation the identity.
+
+    Returns (V, n_s^2, 8): (p_x, p_y, p_z, sum w, S_x, S_y, S_z, 0); voxels
+    whose status lacks SOLVED get NaN rows.
+    """
+    out = np.asarray(out, dtype=np.float64)
+    V, m = out.shape[0], out.shape[1]
+    assert m == grid_side * grid_side and grid_side % n_r == 0
+    n_s = grid_side // n_r
+    res = np.full((V, n_s * n_s, 8), np.nan)
+    for v in range(V):
+        if not int(status[v]) & ST_SOLVED:
+            continue
+        g = out[v].reshape(grid_side, grid_side, 4)
+        for bi in range(n_s):
+            for bj in range(n_s):
+                blk = g[bi * n_r:(bi + 1) * n_r, bj * n_r:(bj + 1) * n_r].reshape(-1, 4)
+                P = blk[:, :3]
+                w = 1.0 / np.maximum(blk[:, 3], var_floor)
+                sw = w.sum()
+                p = (P * w[:, None]).sum(axis=0) / sw
+                Q = P - p
+                phi = Q.T @ np.diag(w) @ Q / sw
+                res[v, bi * n_s + bj] = [p[0], p[1], p[2], sw, phi[0, 0], phi[1, 1], phi[2, 2], 0.0]
+    return res

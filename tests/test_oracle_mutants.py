@@ -146,3 +146,66 @@ def test_pins_green_on_unmodified_oracle():
 def test_pins_catch_mutant(monkeypatch, name, target, mutant):
     monkeypatch.setattr(O, target, mutant)
     assert _caught(), f"no pin caught the mutant: {name}"
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.2 Gaussian initialisation: mutants of gauss_init
+# ---------------------------------------------------------------------------
+def _gauss_variant(weight="inv", transpose=False, std=False, norm="sum"):
+    def f(out, status, grid_side, n_r, var_floor):
+        out = np.asarray(out, dtype=np.float64)
+        V = out.shape[0]
+        ns = grid_side // n_r
+        res = np.full((V, ns * ns, 8), np.nan)
+        for v in range(V):
+            if not int(status[v]) & O.ST_SOLVED:
+                continue
+            g = out[v].reshape(grid_side, grid_side, 4)
+            for bi in range(ns):
+                for bj in range(ns):
+                    a, b = (bj, bi) if transpose else (bi, bj)
+                    blk = g[a * n_r:(a + 1) * n_r, b * n_r:(b + 1) * n_r].reshape(-1, 4)
+                    var = np.maximum(blk[:, 3], var_floor)
+                    w = var if weight == "var" else (np.ones_like(var) if weight == "one" else 1.0 / var)
+                    p = (blk[:, :3] * w[:, None]).sum(0) / w.sum()
+                    Q = blk[:, :3] - p
+                    den = w.sum() if norm == "sum" else len(w)
+                    phi = np.diag(Q.T @ np.diag(w) @ Q) / den
+                    if std:
+                        phi = np.sqrt(phi)
+                    res[v, bi * ns + bj] = [*p, w.sum(), *phi, 0.0]
+        return res
+    return f
+
+
+GAUSS_PINS = [
+    lambda: pins.test_gauss_uniform_weights_regular_grid_closed_form(),
+    lambda: pins.test_gauss_matches_numpy_weighted_covariance(),
+    lambda: pins.test_gauss_dominant_weight_and_invariances(),
+    lambda: pins.test_gauss_floor_unsolved_and_single_point_subgrids(),
+]
+
+
+def _gauss_caught():
+    for t in GAUSS_PINS:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError, FloatingPointError):
+            return True
+    return False
+
+
+def test_gauss_pins_green_on_unmodified_oracle():
+    assert not _gauss_caught()
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("weight = variance", _gauss_variant(weight="var")),
+    ("unweighted", _gauss_variant(weight="one")),
+    ("subgrids transposed", _gauss_variant(transpose=True)),
+    ("scale as standard deviation", _gauss_variant(std=True)),
+    ("scatter divided by the point count", _gauss_variant(norm="count")),
+])
+def test_gauss_pins_catch_mutant(monkeypatch, name, mutant):
+    monkeypatch.setattr(O, "gauss_init", mutant)
+    assert _gauss_caught(), f"no pin caught the mutant: {name}"

@@ -494,3 +494,106 @@ def test_map_state_machine_types():
     m.converged[kB] = True
     u4 = m.update(pts(5, B))                                          # type (d): skipped
     assert kB not in u4["keys"].tolist()
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.2: initial 3D Gaussians from the predicted grid
+# ---------------------------------------------------------------------------
+def _grid_rows(gs, h, z, var):
+    rows = np.zeros((1, gs * gs, 4))
+    for i in range(gs):
+        for j in range(gs):
+            rows[0, i * gs + j] = [i * h, j * h, z(i, j), var(i, j)]
+    return rows
+
+
+def test_gauss_uniform_weights_regular_grid_closed_form():
+    """Equal variances: position = centroid of the block, parameter-axis scales =
+    h^2 (n_r^2 - 1) / 12 (population variance of n_r equally spaced values),
+    value-axis scale = exact rational variance of the block's values."""
+    gs, nr = 6, 3
+    h = Fraction(1, 10)
+    zf = lambda i, j: Fraction(1, 2) + Fraction(1, 100) * i * i + Fraction(1, 1000) * j  # noqa: E731
+    rows = _grid_rows(gs, float(h), lambda i, j: float(zf(i, j)), lambda i, j: 0.04)
+    g = O.gauss_init(rows, np.array([O.ST_SOLVED]), gs, nr, 1e-12)
+    ns = gs // nr
+    assert g.shape == (1, ns * ns, 8)
+    for bi in range(ns):
+        for bj in range(ns):
+            pts = [(i, j) for i in range(bi * nr, bi * nr + nr) for j in range(bj * nr, bj * nr + nr)]
+            zs = [zf(i, j) for i, j in pts]
+            zm = sum(zs) / len(zs)
+            zv = sum((z - zm) ** 2 for z in zs) / len(zs)
+            e = g[0, bi * ns + bj]
+            assert e[0] == pytest.approx(float(h * (bi * nr + Fraction(nr - 1, 2))), abs=1e-15)
+            assert e[1] == pytest.approx(float(h * (bj * nr + Fraction(nr - 1, 2))), abs=1e-15)
+            assert e[2] == pytest.approx(float(zm), abs=1e-15)
+            assert e[3] == pytest.approx(nr * nr / 0.04, rel=1e-15)
+            assert e[4] == pytest.approx(float(h * h * (nr * nr - 1) / 12), rel=1e-12)
+            assert e[5] == pytest.approx(float(h * h * (nr * nr - 1) / 12), rel=1e-12)
+            assert e[6] == pytest.approx(float(zv), rel=1e-10, abs=1e-18)
+
+
+def test_gauss_matches_numpy_weighted_covariance():
+    """Brute force: numpy.average and numpy.cov(aweights=1/var, bias=True) per subgrid."""
+    r = rng(40)
+    gs, nr = 8, 4
+    rows = np.concatenate([r.normal(size=(3, gs * gs, 3)), r.uniform(1e-3, 0.5, size=(3, gs * gs, 1))], axis=2)
+    g = O.gauss_init(rows, np.array([O.ST_SOLVED] * 3), gs, nr, 1e-12)
+    ns = gs // nr
+    for v in range(3):
+        grid = rows[v].reshape(gs, gs, 4)
+        for bi in range(ns):
+            for bj in range(ns):
+                blk = grid[bi * nr:(bi + 1) * nr, bj * nr:(bj + 1) * nr].reshape(-1, 4)
+                w = 1.0 / blk[:, 3]
+                p = np.average(blk[:, :3], axis=0, weights=w)
+                C = np.cov(blk[:, :3].T, aweights=w, bias=True)
+                e = g[v, bi * ns + bj]
+                assert np.allclose(e[:3], p, rtol=0, atol=1e-13)
+                assert np.allclose(e[4:7], np.diag(C), rtol=1e-11, atol=1e-15)
+                assert e[7] == 0.0
+
+
+def test_gauss_dominant_weight_and_invariances():
+    r = rng(41)
+    gs, nr = 6, 3
+    rows = np.concatenate([r.normal(size=(1, gs * gs, 3)), np.ones((1, gs * gs, 1))], axis=2)
+    st = np.array([O.ST_SOLVED])
+    base = O.gauss_init(rows, st, gs, nr, 1e-30)
+    # one point with a tiny variance pulls its Gaussian onto itself and shrinks the scales
+    q = 1 * gs + 4  # (i, j) = (1, 4): subgrid (0, 1)
+    r2 = rows.copy()
+    r2[0, q, 3] = 1e-14
+    g = O.gauss_init(r2, st, gs, nr, 1e-30)
+    assert np.allclose(g[0, 1, :3], rows[0, q, :3], atol=1e-12)
+    assert np.all(g[0, 1, 4:7] < 1e-12)
+    assert np.array_equal(g[0, [0, 2, 3]], base[0, [0, 2, 3]])
+    # scaling every variance leaves position and scale unchanged and divides sum w
+    r3 = rows.copy()
+    r3[..., 3] *= 7.5
+    g3 = O.gauss_init(r3, st, gs, nr, 1e-30)
+    assert np.allclose(g3[..., [0, 1, 2, 4, 5, 6]], base[..., [0, 1, 2, 4, 5, 6]], rtol=1e-12, atol=1e-14)
+    assert np.allclose(g3[..., 3] * 7.5, base[..., 3], rtol=1e-12)
+    # translation moves positions only
+    r4 = rows.copy()
+    r4[..., :3] += np.array([3.0, -2.0, 0.5])
+    g4 = O.gauss_init(r4, st, gs, nr, 1e-30)
+    assert np.allclose(g4[..., :3] - base[..., :3], [3.0, -2.0, 0.5], atol=1e-12)
+    assert np.allclose(g4[..., 4:7], base[..., 4:7], rtol=1e-9, atol=1e-14)
+
+
+def test_gauss_floor_unsolved_and_single_point_subgrids():
+    r = rng(42)
+    gs = 4
+    rows = np.concatenate([r.normal(size=(2, gs * gs, 3)), r.uniform(0.1, 1, size=(2, gs * gs, 1))], axis=2)
+    rows[0, 5, 3] = 0.0  # a zero variance takes the floor: finite weight 1 / floor
+    g = O.gauss_init(rows, np.array([O.ST_SOLVED, O.ST_BELOW_TAU]), gs, 2, 1e-6)
+    assert np.isfinite(g[0]).all() and np.isnan(g[1]).all()
+    q = 5  # (1, 1): subgrid (0, 0)
+    assert g[0, 0, 3] == pytest.approx(1e6 + sum(1.0 / rows[0, k, 3] for k in (0, 1, 4)), rel=1e-12)
+    # n_r = 1: every point is its own Gaussian with zero scale
+    g1 = O.gauss_init(rows, np.array([O.ST_SOLVED, O.ST_SOLVED]), gs, 1, 1e-6)
+    assert np.allclose(g1[:, :, :3], rows[:, :, :3], rtol=1e-15, atol=1e-15)
+    assert np.all(np.abs(g1[:, :, 4:7]) <= 1e-28)  # zero up to the rounding of w P / w
+    assert q == 5
