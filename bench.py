@@ -142,6 +142,8 @@ def main():
                     help="length of the 8-stream 10 Hz serving run (0 skips it)")
     ap.add_argument("--serve-frames", type=int, default=10, help="distinct frames generated per stream (cycled)")
     ap.add_argument("--autotune", action="store_true", help="search launch choices first and cache them")
+    ap.add_argument("--gauss-launches", type=int, default=20,
+                    help="timed launches of the 3D-Gaussian initialisation on the batch's grids (0 skips)")
     ap.add_argument("--graph-steps", type=int, default=20,
                     help="steps of the captured-graph form of the batch (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -320,6 +322,28 @@ def main():
         gctx.close()
         log(f"graph: {graph}")
 
+    # initial 3D Gaussians (Sec. 3.2) from the batch's grids: 8x8 grid as 4x4
+    # subgrids of 2x2 points; HBM-bound (rows read once, 32 B per Gaussian written)
+    gauss = None
+    if args.gauss_launches > 0:
+        nr = 2
+        ns = w["grid_side"] // nr
+        gbuf = torch.empty((V, ns * ns, 8), dtype=torch.float32, device="cuda")
+        ctx.gauss_init(out[0], out[2], w["grid_side"], nr, gauss=gbuf)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read("gauss_init")
+        for _ in range(args.gauss_launches):
+            ctx.gauss_init(out[0], out[2], w["grid_side"], nr, gauss=gbuf)
+        gms, gcnt = ctx.profile_read("gauss_init")
+        ctx.profile(False)
+        per = gms / gcnt / 1e3
+        gbytes = V * m * 16 + V + n_solved * ns * ns * 32 + (V - n_solved) * ns * ns * 32
+        gauss = {"ms_per_launch": per * 1e3, "gaussians_per_launch": int(V * ns * ns), "n_r": nr,
+                 "bytes_per_launch": gbytes, "achieved_GBps": gbytes / per / 1e9,
+                 "hbm_frac": gbytes / per / 1e9 / HBM_PEAK, "bound": "hbm"}
+        log(f"gauss_init: {gauss}")
+
     # single-frame latency (voxelize + fit of one scan, host clock, synchronised)
     lat = []
     lat_solved = []
@@ -372,6 +396,7 @@ def main():
                                "what": "one scan per call, synchronised (the unbatched path)"}
                               if len(lat) else None),
         "batched_graph": graph,
+        "gauss_init": gauss,
         "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(rec), flush=True)
@@ -407,7 +432,7 @@ def serve_leg(args, vgpr) -> dict:
 
 FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
     [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS] + \
-    [f"fit_mix_n{c}" for c in BUCKETS]
+    [f"fit_mix_n{c}" for c in BUCKETS] + ["gauss_init"]
 
 
 def ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm) -> int:

@@ -235,6 +235,27 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
                            int64_t* h_n_converged);
 
 /*
+ * vgpr_gauss_init - initial 3D Gaussians from the predicted grids (Sec. 3.2).
+ *
+ * d_out / d_status: n_vox voxels as written by vgpr_fit_predict (or
+ * vgpr_map_update) with grid side grid_side (m = grid_side^2 float4 rows per
+ * voxel, row q = i grid_side + j). The grid splits into n_s x n_s subgrids of
+ * n_r x n_r points, n_s = grid_side / n_r (the paper's n_s intervals with n_r
+ * neighbours each); subgrid beta = bi n_s + bj holds rows i in [bi n_r,
+ * (bi + 1) n_r) and columns j in [bj n_r, (bj + 1) n_r). Each point's weight
+ * is 1 / max(var, var_floor). Per subgrid, d_gauss receives 8 floats:
+ * (p_x, p_y, p_z, sum of weights, S_x, S_y, S_z, 0) with p the weighted mean
+ * position and S the diagonal of the weighted scatter sum w (P - p)(P - p)^T
+ * / sum w; the rotation is the identity. d_gauss: n_vox * n_s^2 * 8 floats,
+ * caller-owned, 16-byte aligned. Voxels without the SOLVED bit get NaN.
+ * Enqueued on the context's stream. Errors: E_INVALID (n_r does not divide
+ * grid_side, grid_side outside 1..16, var_floor <= 0, null or misaligned
+ * pointers).
+ */
+VGPR_API vgpr_status vgpr_gauss_init(vgpr_ctx* ctx, const float* d_out, const uint8_t* d_status, int64_t n_vox,
+                                     int32_t grid_side, int32_t n_r, float var_floor, float* d_gauss);
+
+/*
  * Captured form of vgpr_fit_predict (the batching form: every size bucket's
  * persistent launch, the side-stream fork and join, recorded once as a HIP
  * graph and replayed with one launch).
@@ -298,7 +319,8 @@ VGPR_API vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t);
  * family `name`, the summed duration in milliseconds and the number of
  * launches since the last read of that family, then resets it. Families:
  * "voxelize_key", "voxelize_sort" (all radix passes of a call),
- * "voxelize_segment", "classify", "fit_f32_n<C>" / "fit_f64_n<C>" (the
+ * "voxelize_segment", "classify", "gauss_init", "fit_mix_n<C>" (MIXED mode tiled
+ * solver), "fit_f32_n<C>" / "fit_f64_n<C>" (the
  * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 96, 128, 256, 512) and
  * "refine_f64_n<C>" (the FP64 re-solve of flagged voxels of that bucket).
  */

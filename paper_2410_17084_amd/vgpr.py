@@ -24,6 +24,7 @@ SYMBOLS = [
     "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
     "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
+    "vgpr_gauss_init",
 ]
 
 
@@ -110,6 +111,7 @@ def load():
         "vgpr_fit_graph_create": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp, P(vp)]),
         "vgpr_graph_launch": (C.c_int, [vp]),
         "vgpr_graph_destroy": (C.c_int, [vp]),
+        "vgpr_gauss_init": (C.c_int, [vp, vp, vp, i64, i32, i32, C.c_float, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -249,6 +251,19 @@ class Context:
         g = Graph(self, h, (xyz, vox, noise_var, out), (o[:v], ax[:v], stt[:v]))
         self._graphs.add(g)
         return g
+
+    # -- vgpr_gauss_init -----------------------------------------------------
+    def gauss_init(self, out, status, grid_side: int, n_r: int, var_floor: float = 1e-8, gauss=None):
+        """Initial 3D Gaussians of each n_r x n_r subgrid: (V, n_s^2, 8) float32."""
+        torch = self.torch
+        v = int(status.shape[0])
+        ns = grid_side // n_r if n_r > 0 else 0
+        if gauss is None:
+            gauss = torch.empty((max(v, 1), max(ns * ns, 1), 8), dtype=torch.float32, device=out.device)
+        st = self.lib.vgpr_gauss_init(self.h, _ptr(out), _ptr(status), v, int(grid_side), int(n_r),
+                                      float(var_floor), _ptr(gauss))
+        self._check(st, "vgpr_gauss_init")
+        return gauss[:v]
 
     # -- launch tuning ----------------------------------------------------------
     def tuning(self) -> Tuning:

@@ -1,0 +1,99 @@
+"""GPU parity of vgpr_gauss_init (initial 3D Gaussians, Sec. 3.2) against the oracle.
+
+Two comparisons:
+- same inputs: the oracle's gauss_init evaluated on the GPU's own predicted
+  rows; both sides accumulate in double from the same float32 rows, so the
+  float32 outputs agree to a few ulps (rtol 4e-7, atol 1e-12);
+- end to end (FP64 mode): the oracle's full fit_predict + gauss_init against
+  the GPU's. The GPU's FP64 rows differ from the oracle's by at most ~1e-6 m
+  in the mean and ~3e-8 in the variance, which moves a weighted position by
+  well under 1e-4 m and a scale by under 1e-3 relative (+1e-9 m^2).
+"""
+import numpy as np
+import pytest
+
+from oracle import vgpr_oracle as O
+from paper_2410_17084_amd import configs, synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2410_17084_amd import vgpr
+    ctx = vgpr.Context(0)
+    yield torch, vgpr, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _fit(env, xyz, w, prec):
+    torch, vgpr, ctx = env
+    p = parity.gpu_params(vgpr, w, precision=prec)
+    x = torch.from_numpy(np.ascontiguousarray(xyz, dtype=np.float32)).cuda()
+    gv = ctx.voxelize(x, p)
+    out, axis, status = ctx.fit_predict(x, gv, p)
+    torch.cuda.synchronize()
+    return gv, out, axis, status
+
+
+def _same_inputs(ctx, out, status, gs, nr, floor):
+    g = ctx.gauss_init(out, status, gs, nr, floor).cpu().numpy().astype(np.float64)
+    ref = O.gauss_init(out.cpu().numpy().astype(np.float64), status.cpu().numpy(), gs, nr,
+                       float(np.float32(floor)))
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(g), nan)
+    assert np.allclose(g[~nan], ref[~nan], rtol=4e-7, atol=1e-12)
+    return g, ref
+
+
+@pytest.mark.parametrize("nr", [1, 2, 4, 8])
+def test_gauss_same_inputs_spin32(env, nr):
+    torch, vgpr, ctx = env
+    xyz = synth.spin_scan(synth.frame_seed(2, 6), n_beams=32, n_az=1024)
+    w = configs.params_for("spin32")
+    say("gauss same inputs spin32", nr, len(xyz))
+    gv, out, axis, status = _fit(env, xyz, w, vgpr.PREC_FP32)
+    g, ref = _same_inputs(ctx, out, status, 8, nr, 1e-8)
+    assert g.shape == (gv.n_vox, (8 // nr) ** 2, 8)
+    solved = (status.cpu().numpy() & vgpr.ST_SOLVED) != 0
+    assert np.isnan(g[~solved]).all() and np.isfinite(g[solved]).all()
+
+
+def test_gauss_paper_grid_end_to_end(env):
+    """Paper-shaped grid (n_s = n_r = 3, 9x9) on a serving-stream frame, FP64 mode."""
+    torch, vgpr, ctx = env
+    xyz = synth.stream_frames(2, 1)[0]
+    w = configs.params_for("paper_stream")
+    say("gauss end to end, 9x9 grid, n_r 3", len(xyz))
+    gv, out, axis, status = _fit(env, xyz, w, vgpr.PREC_FP64)
+    g, _ = _same_inputs(ctx, out, status, 9, 3, 1e-8)
+    ov = O.voxelize(xyz, w["voxel_size"])
+    prm = parity.oracle_params(w)
+    of = O.fit_predict(xyz, ov, prm, axes=axis.cpu().numpy())
+    ref = O.gauss_init(of["out"], of["status"], 9, 3, float(np.float32(1e-8)))
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(g), nan)
+    assert int((~nan).sum()) > 1000
+    assert np.abs(g[..., :3] - ref[..., :3])[~nan[..., :3]].max() <= 1e-4
+    sg, sr = g[..., 4:7][~nan[..., 4:7]], ref[..., 4:7][~nan[..., 4:7]]
+    assert np.all(np.abs(sg - sr) <= 1e-3 * np.abs(sr) + 1e-9)
+
+
+def test_gauss_argument_errors(env):
+    torch, vgpr, ctx = env
+    out = torch.zeros((4, 64, 4), device="cuda")
+    st = torch.ones(4, dtype=torch.uint8, device="cuda")
+    say("gauss argument errors")
+    for gs, nr, fl in ((8, 3, 1e-8), (8, 0, 1e-8), (8, 2, 0.0), (17, 1, 1e-8)):
+        with pytest.raises(vgpr.VgprError) as ei:
+            ctx.gauss_init(out, st, gs, nr, fl)
+        assert ei.value.status == vgpr.E_INVALID
+    empty = ctx.gauss_init(out[:0], st[:0], 8, 2)
+    assert empty.shape[0] == 0
