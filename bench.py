@@ -427,6 +427,20 @@ def serve_leg(args, vgpr) -> dict:
     out["points_per_tick"] = int(sum(s[0] for s in sizes))
     out["config"] = "voxel 0.2 m, tau 10, cap 64, 9x9 grid, eta 0.3; 10 frames per stream cycled"
     be.close()
+    # throughput of the served form: the same frames as a backlog (all queued at
+    # t = 0), continuous batching over 8 worker slots vs one frame at a time,
+    # each on fresh maps
+    backlog = {}
+    for workers in (8, 1):
+        be = serve.GpuBackend(p, frames, max_voxels=250000)
+        be.warmup()
+        sb = serve.serve(be, sizes, rate_hz=10.0, duration_s=1.0, workers=workers, budget_bytes=8 << 30,
+                         m=p.grid_side ** 2, realtime=False).summary()
+        be.close()
+        backlog[f"workers{workers}"] = {k: sb[k] for k in ("frames", "failed", "solves", "solves_per_s", "wall_s",
+                                                           "max_inflight")}
+    backlog["speedup"] = backlog["workers8"]["solves_per_s"] / backlog["workers1"]["solves_per_s"]
+    out["backlog"] = backlog
     return out
 
 

@@ -346,7 +346,7 @@ __device__ __forceinline__ float4 out_row(int ax, int u, float mv, float gu, flo
 // ---------------------------------------------------------------------------
 // 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
 // ---------------------------------------------------------------------------
-template <typename T, int NMAX>
+template <typename T, int NMAX, int QR>
 __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
                                                                 const float4* __restrict__ staged,
@@ -356,8 +356,9 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
                                                                 uint32_t* __restrict__ rcount) {
   constexpr bool kKInLds = NMAX <= 32;       // K from its upper triangle through LDS
   constexpr int kWaves = kWaveThreads / 64;
-  __shared__ T s_xu[kWaves][NMAX + 8], s_xw[kWaves][NMAX + 8];
-  __shared__ T s_tab[kWaves][2 * 8 * NMAX];
+  constexpr int NQ = QR == 1 ? 8 : (QR == 2 ? 12 : 16);  // largest grid side for QR query rows per lane
+  __shared__ T s_xu[kWaves][NMAX + NQ], s_xw[kWaves][NMAX + NQ];
+  __shared__ T s_tab[kWaves][2 * NQ * NMAX];
   __shared__ T s_K[kWaves][kKInLds ? NMAX * NMAX : 1];
   const int wid = threadIdx.x >> 6;
   const int lane = lane_id();
@@ -399,11 +400,16 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       fv = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
       nz = (T)pt.w;
     }
-    // this lane's query point (lanes < m): row i, column j of the grid
-    float gu = 0.f, gwv = 0.f;
-    const int q = lane < P.m ? lane : 0;
-    query_coords(P, fr, q, &gu, &gwv);
-    const int qi = q / P.nq, qj = q - qi * P.nq;
+    // this lane's query points q = lane + 64 r (r < QR, q < m): row i, column j of the grid
+    float gu[QR], gwv[QR];
+    int qi[QR], qj[QR];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const int q = lane + 64 * r < P.m ? lane + 64 * r : 0;
+      query_coords(P, fr, q, &gu[r], &gwv[r]);
+      qi[r] = q / P.nq;
+      qj[r] = q - qi[r] * P.nq;
+    }
     const bool dlane = lane < n;
 
     // Kernel entries with few exponentials. The query entries factor as
@@ -414,7 +420,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     T* __restrict__ su = s_xu[wid];
     T* __restrict__ sw = s_xw[wid];
     T* __restrict__ tu = s_tab[wid];
-    T* __restrict__ tw = s_tab[wid] + 8 * NMAX;
+    T* __restrict__ tw = s_tab[wid] + NQ * NMAX;
     if (dlane) {
       su[lane] = xu;
       sw[lane] = xw;
@@ -464,13 +470,14 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // rows: A = query row (lanes < m), B = data row (lanes < n) with its right-hand side fy
-    T A[NMAX], B[NMAX];
+    // rows: A = query rows (q = lane + 64 r < m), B = data row (lanes < n) with its right-hand side fy
+    T A[QR][NMAX], B[NMAX];
     T fy = fv;
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) {
       if (c < n) {
-        A[c] = sf2 * tu[c * nq + qi] * tw[c * nq + qj];
+#pragma unroll
+        for (int r = 0; r < QR; ++r) A[r][c] = sf2 * tu[c * nq + qi[r]] * tw[c * nq + qj[r]];
         T kb;
         if constexpr (kKInLds) {
           kb = s_K[wid][c * NMAX + lane];
@@ -480,7 +487,8 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
         }
         B[c] = dlane ? kb + (c == lane ? nz : (T)0) : (T)0;
       } else {
-        A[c] = 0;
+#pragma unroll
+        for (int r = 0; r < QR; ++r) A[r][c] = 0;
         B[c] = 0;
       }
       // keep the table loads of later columns from being hoisted (register pressure)
@@ -488,15 +496,26 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     }
     // the LDS region is rewritten for the next voxel only after every lane has read it
     __builtin_amdgcn_wave_barrier();
-    T var = sf2, mean = 0, minpiv = (T)FLT_MAX, score = 0;
+    T var[QR], mean[QR], tA[QR];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      var[r] = sf2;
+      mean[r] = 0;
+    }
+    T minpiv = (T)FLT_MAX, score = 0;
     for (int j = 0; j < n; ++j) {
-      const T cjA = A[0], cjB = B[0];
+      const T cjB = B[0];
       const T d = bcast(cjB, j);
       const T y = bcast(fy, j);  // y_j = (L^-1 f~)_j, final once step j is reached
       const T inv = (T)1 / d;
-      const T tA = cjA * inv, tB = cjB * inv;
-      var -= tA * cjA;
-      mean += tA * y;
+      const T tB = cjB * inv;
+#pragma unroll
+      for (int r = 0; r < QR; ++r) {
+        const T cjA = A[r][0];
+        tA[r] = cjA * inv;
+        var[r] -= tA[r] * cjA;
+        mean[r] += tA[r] * y;
+      }
       fy -= tB * y;
       minpiv = d < minpiv ? d : minpiv;
       score += (y < 0 ? -y : y) * inv;
@@ -509,7 +528,8 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
             if (k < NMAX - 1) {
               // lane j+1+k holds data row j+1+k; past row n-1 the value is unused
               const T col = bcast(cjB, (j + 1 + k) & 63);
-              A[k] = A[k + 1] - tA * col;
+#pragma unroll
+              for (int r = 0; r < QR; ++r) A[r][k] = A[r][k + 1] - tA[r] * col;
               B[k] = B[k + 1] - tB * col;
             }
           }
@@ -519,11 +539,15 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     const bool failed = !(minpiv > (T)0) || !isfinite((double)score);
     const bool flag = P.mode == 0 && (failed || score > (T)P.refine_thr);
     float mv_lane = 0.f;
-    if (!flag && lane < P.m) {
-      const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > (T)0 ? var : (T)0);
-      const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean);
-      reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + lane] = out_row(ax, u, mv, gu, gwv, vv);
-      mv_lane = failed ? 0.f : vv;
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const int q = lane + 64 * r;
+      if (!flag && q < P.m) {
+        const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var[r] > (T)0 ? var[r] : (T)0);
+        const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean[r]);
+        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = out_row(ax, u, mv, gu[r], gwv[r], vv);
+        mv_lane = fmaxf(mv_lane, failed ? 0.f : vv);
+      }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mv_lane = fmaxf(mv_lane, __shfl_xor(mv_lane, d, 64));
@@ -1408,17 +1432,17 @@ struct Launch {
   const char* fam;
 };
 
-template <typename T, int NMAX>
+template <typename T, int NMAX, int QR>
 vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const float4* staged,
                         const Launch& l) {
   static int per_cu = -1;
-  if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX>, kWaveThreads);
+  if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX, QR>, kWaveThreads);
   int64_t grid = (int64_t)per_cu * ctx->cu_count * l.grid_scale / 4;
   const int64_t need = (l.max_items + kWaveThreads / 64 - 1) / (kWaveThreads / 64);
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam, l.stream);
-  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P, io,
+  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX, QR>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P, io,
                      l.recs, staged, l.slots, l.count, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
@@ -1514,11 +1538,19 @@ template <typename T>
 vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, const FitArgs& io,
                           const float4* staged, const Launch& l) {
   if (wave) {
-    switch (b) {
-      case 0: return launch_wave<T, 16>(ctx, P, io, staged, l);
-      case 1: return launch_wave<T, 32>(ctx, P, io, staged, l);
-      default: return launch_wave<T, 64>(ctx, P, io, staged, l);
+    // query rows per lane; combinations that do not fit the register file fall back to the block solver
+    const int qr = P.m <= 64 ? 1 : (P.m <= 128 ? 2 : 4);
+    if (b == 0) {
+      if (qr == 1) return launch_wave<T, 16, 1>(ctx, P, io, staged, l);
+      if (qr == 2) return launch_wave<T, 16, 2>(ctx, P, io, staged, l);
+      return launch_wave<T, 16, 4>(ctx, P, io, staged, l);
     }
+    if (b == 1) {
+      if (qr == 1) return launch_wave<T, 32, 1>(ctx, P, io, staged, l);
+      if (qr == 2) return launch_wave<T, 32, 2>(ctx, P, io, staged, l);
+      if constexpr (sizeof(T) == 4) return launch_wave<T, 32, 4>(ctx, P, io, staged, l);
+    }
+    if (b == 2 && qr == 1) return launch_wave<T, 64, 1>(ctx, P, io, staged, l);
   }
   switch (b) {
     case 0: return launch_block<T, 16>(ctx, P, io, staged, l);
@@ -1568,8 +1600,9 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
       tile_scratch[b] = cv.take<double>(tile_bucket_bytes(ctx, b, mixed) / sizeof(double));
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, ctx->stream, ctr, 64);
 
-  // the wave solver holds one query row per lane: grids up to 64 points
-  const bool wave_ok = m <= 64;
+  // the wave solver holds up to four query rows per lane (grids up to 256 points) for voxels of up
+  // to 32 points, one row per lane (grids up to 64 points) for voxels of up to 64 points
+  auto wave_ok = [&](int b) { return b <= 1 ? m <= 256 : m <= 64; };
   FitParams P;
   P.cap = p->max_pts;
   P.tau = p->min_pts;
@@ -1613,7 +1646,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
     const bool tiled = b >= first_tile_bucket(ctx);
-    const bool wave = wave_ok && b <= tu.wave_last_bucket;
+    const bool wave = wave_ok(b) && b <= tu.wave_last_bucket;
     const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket && !tiled;
     FitParams Pb = P;
     Pb.mode = in_fp32 ? 0 : 2;
