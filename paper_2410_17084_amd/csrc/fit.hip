@@ -608,6 +608,8 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
     const int qchunk = NT - n;
     bool failed = false;
     for (int q0 = 0; q0 < P.m; q0 += qchunk) {
+      // the previous chunk's last step may still be reading the pivot slots
+      if (q0 > 0) __syncthreads();
       const bool is_data = tid < n;
       const int q = q0 + tid - n;
       const bool is_query = tid >= n && q < P.m;
@@ -704,6 +706,13 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
 //     var_q = s_f^2 - |z_q|^2,   mean_q = mu + z_q . y      (Eq. (3)).
 // Padding rows and columns of the last data block are identity rows, so they
 // leave the factor of the real block unchanged.
+// Order LDS writes of one wavefront before its later reads (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kTile = 32;
 constexpr int kTileThreads = 512;
@@ -750,6 +759,9 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
   __shared__ float pn[NPAD];
   __shared__ double sy[NPAD];
   __shared__ double srhs[kTile], squ[kTile], sqw[kTile];
+  __shared__ double sdc[2 * kTile + 8];  // diagonal-tile column broadcast (lanes >= 32 hold zeros)
+  __shared__ double srd[kTile];          // 1 / L_jj of the diagonal tile
+  __shared__ double sdy;
   __shared__ int s_item, s_fail;
   __shared__ unsigned s_maxvar;
 
@@ -908,37 +920,71 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
           for (int c = 0; c < kTile; ++c) B[c] = lane < kTile ? rb[lane * LD + I * kTile + c] : 0.0;
           bool bad = false;
           for (int j = 0; j < kTile; ++j) {
+            // column j of the remaining rows through LDS (one wavefront: no workgroup barrier)
             const double cj = B[0];
-            const double d = bcast(cj, j);
-            const double yj = bcast(fy, j);
-            const double t = cj / d;
-            const double sd = sqrt(d);
+            sdc[lane] = cj;
+            if (lane == j) sdy = fy;
+            wave_sync();
+            // first half of the column before the reciprocal, so the LDS reads overlap it
+            constexpr int H = kTile / 2;
+            double colv[H];
+#pragma unroll
+            for (int k = 0; k < H; ++k) colv[k] = sdc[j + 1 + k];
+            const double d = sdc[j];
+            const double yj = sdy;
+            // 1/sqrt(d) from the hardware estimate and two Newton steps (each doubles the
+            // correct bits), then 1/d = rs^2 and sqrt(d) = d rs
+            double rs = __builtin_amdgcn_rsq(d);
+            rs = rs * (1.5 - 0.5 * d * rs * rs);
+            rs = rs * (1.5 - 0.5 * d * rs * rs);
+            const double inv = rs * rs;
+            const double t = cj * inv;
             bad |= !(d > 0.0);
             if (lane == j) {
-              rb[lane * LD + I * kTile + j] = sd;
-              sy[I * kTile + j] = yj / sd;
+              rb[lane * LD + I * kTile + j] = d * rs;  // sqrt(d)
+              srd[j] = rs;
+              sy[I * kTile + j] = yj * rs;
             } else if (lane > j && lane < kTile) {
-              rb[lane * LD + I * kTile + j] = cj / sd;
+              rb[lane * LD + I * kTile + j] = cj * rs;
             }
             fy -= t * yj;
+            double colw[kTile - 1 - H];
 #pragma unroll
-            for (int k = 0; k < kTile - 1; ++k) B[k] = B[k + 1] - t * bcast(cj, (j + 1 + k) & 63);
+            for (int k = 0; k < kTile - 1 - H; ++k) colw[k] = sdc[j + 1 + H + k];
+#pragma unroll
+            for (int k = 0; k < H; ++k) B[k] = B[k + 1] - t * colv[k];
+#pragma unroll
+            for (int k = 0; k < kTile - 1 - H; ++k) B[H + k] = B[H + k + 1] - t * colw[k];
             B[kTile - 1] = 0.0;
+            wave_sync();  // every lane has read column j before it is overwritten
           }
           if (bad && lane == 0) s_fail = 1;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // L(I,I)^-1 by forward substitution, lane k computing column k
+          // L(I,I)^-1 by forward substitution, lane k computing column k; the sums
+          // run as four independent chains and the division is by the stored 1/L_ii
           if (lane < kTile) {
             double x[kTile];
             const double* __restrict__ Ld = rb + I * kTile;
 #pragma unroll
             for (int i = 0; i < kTile; ++i) {
-              double s = i == lane ? 1.0 : 0.0;
+              double s0 = i == lane ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-              for (int j = 0; j < i; ++j) s -= Ld[i * LD + j] * x[j];
-              x[i] = s / Ld[i * LD + i];
+              for (int j0 = 0; j0 < i; j0 += 8) {
+                // eight entries of row i read together, then four independent chains
+                double lr[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) lr[e] = j0 + e < i ? Ld[i * LD + j0 + e] : 0.0;
+#pragma unroll
+                for (int e = 0; e < 8; e += 4) {
+                  if (j0 + e < i) s0 -= lr[e] * x[j0 + e];
+                  if (j0 + e + 1 < i) s1 -= lr[e + 1] * x[j0 + e + 1];
+                  if (j0 + e + 2 < i) s2 -= lr[e + 2] * x[j0 + e + 2];
+                  if (j0 + e + 3 < i) s3 -= lr[e + 3] * x[j0 + e + 3];
+                }
+              }
+              x[i] = ((s0 + s1) + (s2 + s3)) * srd[i];
             }
             double* __restrict__ Wi = Wt + (size_t)I * kTileDoubles;
 #pragma unroll
@@ -1026,10 +1072,6 @@ __device__ __forceinline__ flt4 mfma_split(const bf16x8& ah, const bf16x8& al, c
   return c;
 }
 
-__device__ __forceinline__ float bcastf(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
 template <int NPAD>
 __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams P, FitArgs io,
                                                                       const SlotRec* __restrict__ recs,
@@ -1050,6 +1092,9 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
   __shared__ double smean[kTile];
   __shared__ float srhs[kTile];
   __shared__ double squ[kTile], sqw[kTile];
+  __shared__ float sdcf[2 * kTile + 8];
+  __shared__ float srdf[kTile];
+  __shared__ float sdyf;
   __shared__ int s_item;
   __shared__ int s_fail;
   __shared__ float s_minpiv;
@@ -1183,22 +1228,31 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
         float mp = FLT_MAX;
         for (int j = 0; j < kTile; ++j) {
           const float cj = B[0];
-          const float d = bcastf(cj, j);
-          const float yj = bcastf(fy, j);
-          const float t = cj / d;
-          const float sd = sqrtf(d);
+          sdcf[lane] = cj;
+          if (lane == j) sdyf = fy;
+          wave_sync();
+          float colv[kTile - 1];  // the column up front: the LDS reads overlap the reciprocal
+#pragma unroll
+          for (int k = 0; k < kTile - 1; ++k) colv[k] = sdcf[j + 1 + k];
+          const float d = sdcf[j];
+          const float yj = sdyf;
+          const float inv = 1.f / d;
+          const float rs = sqrtf(inv);
+          const float t = cj * inv;
           bad |= !(d > 0.f);
           if (I * kTile + j < n) mp = fminf(mp, d);
           if (lane == j) {
-            rb[lane * LD + I * kTile + j] = sd;
-            sy[I * kTile + j] = yj / sd;
+            rb[lane * LD + I * kTile + j] = d * rs;
+            srdf[j] = rs;
+            sy[I * kTile + j] = yj * rs;
           } else if (lane > j && lane < kTile) {
-            rb[lane * LD + I * kTile + j] = cj / sd;
+            rb[lane * LD + I * kTile + j] = cj * rs;
           }
           fy -= t * yj;
 #pragma unroll
-          for (int k = 0; k < kTile - 1; ++k) B[k] = B[k + 1] - t * bcastf(cj, (j + 1 + k) & 63);
+          for (int k = 0; k < kTile - 1; ++k) B[k] = B[k + 1] - t * colv[k];
           B[kTile - 1] = 0.f;
+          wave_sync();
         }
         if (lane == 0) {
           if (bad) s_fail = 1;
@@ -1212,10 +1266,14 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
           const float* __restrict__ Ld = rb + I * kTile;
 #pragma unroll
           for (int i = 0; i < kTile; ++i) {
-            float s = i == lane ? 1.f : 0.f;
+            float s0 = i == lane ? 1.f : 0.f, s1 = 0.f;
 #pragma unroll
-            for (int j = 0; j < i; ++j) s -= Ld[i * LD + j] * x[j];
-            x[i] = s / Ld[i * LD + i];
+            for (int j = 0; j + 1 < i; j += 2) {
+              s0 -= Ld[i * LD + j] * x[j];
+              s1 -= Ld[i * LD + j + 1] * x[j + 1];
+            }
+            if (i & 1) s0 -= Ld[i * LD + i - 1] * x[i - 1];
+            x[i] = (s0 + s1) * srdf[i];
           }
           const size_t t = (size_t)I * kTileDoubles;
 #pragma unroll
