@@ -3,8 +3,10 @@
 A step is one pass of the whole path over one batch of synthetic scans that
 are already resident in HBM: vgpr_voxelize over the batch (frames voxelized
 independently) followed by vgpr_fit_predict over every voxel of the batch.
-The batch is `--frames` seeded 32-beam x 1800-azimuth spinning scans of the
-box scene (voxel 0.5 m, cap 128, tau 3, 8x8 query grid).
+By default the batch is 64 seeded 32-beam x 1800-azimuth spinning scans of the
+box scene (voxel 0.5 m, cap 128, tau 3, 8x8 query grid); `--workload batched`
+and `--workload aggregated` run the 1 m / cap 256 and 0.1 m / cap 512 / 16x16
+workloads instead.
 
 Prints one JSON line: solved voxels per second (plus dense points per second),
 the per-kernel roofline of the dominant kernel from HIP events on the
@@ -132,7 +134,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--workload", choices=["spin32", "batched", "aggregated"], default="spin32",
+                    help="spin32: 32-beam scans (the default step); batched: 128-beam and rosette scans at 1 m "
+                         "voxels, cap 256; aggregated: 10-scan 128-beam map updates at 0.1 m voxels, cap 512, 16x16")
+    ap.add_argument("--frames", type=int, default=None, help="frames per step (default 64 / 16 / 1 by workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default="fp32")
     ap.add_argument("--latency-frames", type=int, default=60)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -159,12 +164,13 @@ def main():
 
     from paper_2410_17084_amd import vgpr
 
-    w = configs.params_for("spin32")
-    wl = configs.WORKLOADS["spin32"]
+    w = configs.params_for(args.workload)
+    if args.frames is None:
+        args.frames = {"spin32": 64, "batched": 16, "aggregated": 1}[args.workload]
     m = w["grid_side"] ** 2
     t0 = time.perf_counter()
-    xyz_np, fo = synth.scan_batch(2, args.frames, n_beams=wl["n_beams"], n_az=wl["n_az"])
-    log(f"generated {args.frames} scans, {len(xyz_np)} points in {time.perf_counter() - t0:.1f} s")
+    xyz_np, fo = workload_frames(args.workload, args.frames)
+    log(f"generated {args.frames} {args.workload} frames, {len(xyz_np)} points in {time.perf_counter() - t0:.1f} s")
 
     if args.copy_probe:
         src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -275,7 +281,8 @@ def main():
                     "voxels_per_launch": int(sel.sum() / launches_per_step),
                     "algorithmic_bytes_per_launch": float(by[sel].sum() / launches_per_step),
                     "hbm_frac": float(by[sel].sum() / launches_per_step) / per_launch_s / 1e9 / HBM_PEAK}
-            roof["traffic"] = measured_traffic(dom, ctx.tuning().as_dict(), args.precision)
+            roof["traffic"] = (measured_traffic(dom, ctx.tuning().as_dict(), args.precision)
+                               if args.workload == "spin32" and args.frames == 64 else None)
         tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
@@ -326,7 +333,7 @@ def main():
     # subgrids of 2x2 points; HBM-bound (rows read once, 32 B per Gaussian written)
     gauss = None
     if args.gauss_launches > 0:
-        nr = 2
+        nr = max(1, w["grid_side"] // 4)
         ns = w["grid_side"] // nr
         gbuf = torch.empty((V, ns * ns, 8), dtype=torch.float32, device="cuda")
         ctx.gauss_init(out[0], out[2], w["grid_side"], nr, gauss=gbuf)
@@ -381,9 +388,8 @@ def main():
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+bf16"}[args.precision], "data": "synthetic",
-        "config": {"workload": f"spin32 batch: {args.frames} seeded 32-beam x 1800-azimuth spinning scans "
-                               f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step), voxel 0.5 m, "
-                               f"cap 128, tau 3, 8x8 grid, l 0.25 m, noise 1e-3",
+        "config": {"workload": f"{args.workload} batch: {args.frames} frames, {WORKLOAD_DESC[args.workload]} "
+                               f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step)",
                    "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec != 2 else ""),
                    "parallelism": "1 GPU"},
         "dense_pts_per_s": dense,
@@ -447,6 +453,34 @@ def serve_leg(args, vgpr) -> dict:
 FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
     [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS] + \
     [f"fit_mix_n{c}" for c in BUCKETS] + ["gauss_init"]
+
+
+WORKLOAD_DESC = {
+    "spin32": "seeded 32-beam x 1800-azimuth spinning scans, voxel 0.5 m, cap 128, tau 3, 8x8 grid, l 0.25 m, "
+              "noise 1e-3",
+    "batched": "alternating seeded 128-beam x 1024-azimuth spinning scans and 100k-ray rosette scans (17/23 Hz "
+               "petals), voxel 1 m, cap 256, tau 3, 8x8 grid, l 0.5 m, noise 1e-3",
+    "aggregated": "each 10 seeded 128-beam x 1024-azimuth scans along a path with N(0, 0.01 m) pose noise, voxel "
+                  "0.1 m, cap 512, tau 3, 16x16 grid, length scale from PCA, noise 1e-3",
+}
+
+
+def workload_frames(name: str, n_frames: int):
+    """Seeded frames of a workload, concatenated, with their frame offsets."""
+    if name == "spin32":
+        wl = configs.WORKLOADS["spin32"]
+        return synth.scan_batch(2, n_frames, n_beams=wl["n_beams"], n_az=wl["n_az"])
+    scene = synth.box_scene()
+    frames = []
+    for k in range(n_frames):
+        if name == "batched":
+            frames.append(synth.spin_scan(synth.frame_seed(3, k), n_beams=128, n_az=1024, scene=scene) if k % 2 == 0
+                          else synth.rosette_scan(synth.frame_seed(3, k), n_pts=100000, frame_index=k, scene=scene))
+        else:
+            frames.append(synth.aggregated_scans(synth.frame_seed(5, k), scene=scene))
+    offs = np.zeros(n_frames + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(f) for f in frames])
+    return np.ascontiguousarray(np.concatenate(frames)), offs
 
 
 def ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm) -> int:
