@@ -753,6 +753,9 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
                                                                 double* __restrict__ scratch) {
   constexpr int NB = NPAD / kTile;
   constexpr int LD = NPAD + 2;  // row stride of the row block, in doubles
+  // up to 128 points every finished tile and diagonal inverse stays in LDS (no scratch traffic)
+  constexpr bool kLdsTiles = NPAD <= 128;
+  __shared__ double s_tiles[kLdsTiles ? (NB * (NB + 1) / 2 + NB) * kTileDoubles : 1];
   __shared__ double rb[kTile * LD];
   __shared__ double xb[kTile * kXS];  // the tile finished in the current step
   __shared__ double pu[NPAD], pw[NPAD], pf[NPAD];
@@ -769,7 +772,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
   const int lane = lane_id();
   const int wid = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
-  double* __restrict__ Lt = scratch + (size_t)blockIdx.x * tile_scratch_doubles(NPAD);
+  double* __restrict__ Lt = kLdsTiles ? s_tiles : scratch + (size_t)blockIdx.x * tile_scratch_doubles(NPAD);
   double* __restrict__ Wt = Lt + (size_t)(NB * (NB + 1) / 2) * kTileDoubles;
   const int cnt_items = (int)*count;
   const double sf2 = (double)P.sf2;
@@ -1554,6 +1557,7 @@ int tile_grid(const vgpr_ctx* ctx, int b, bool mixed, int grid_scale) {
 }
 
 size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b, bool mixed) {
+  if (!mixed && kBucketCap[b] <= 128) return 0;  // the FP64 tiled solver keeps these tiles in LDS
   return (size_t)tile_per_cu_of(b, mixed) * ctx->cu_count * tile_scratch_doubles(kBucketCap[b]) * sizeof(double);
 }
 
