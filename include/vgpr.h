@@ -299,8 +299,9 @@ typedef struct {
   int32_t fp32_last_bucket;   /* FP32 mode: buckets 0..this run in float first (-1: none) */
   int32_t wave_last_bucket;   /* grids of up to 64 points: buckets 0..this use the one-voxel-per-
                                  wavefront solver (max 2), the others one voxel per workgroup */
-  int32_t streams;            /* 1: every bucket on the context's stream; 3: the two largest
-                                 buckets and the next two fork onto two side streams */
+  int32_t streams;            /* 1: every bucket on the context's stream; 3: buckets fork onto
+                                 side streams (96/128 points, 32/64 points, 256/512 points each
+                                 on one, 16 points on the context's stream) and join back */
   int32_t grid_scale[7];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
                                  workgroups the device holds (1..64; buckets 5 and 6 use at
                                  most 4, one resident wave of workgroups) */

@@ -95,7 +95,7 @@ void prof_end(vgpr_ctx* ctx, const char* family, hipStream_t stream, hipEvent_t 
 vgpr_status ensure_aux(vgpr_ctx* ctx) {
   if (ctx->aux[0]) return VGPR_OK;
   // default priority on purpose: every stream of the library runs at the same priority
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < vgpr_ctx::kAux; ++i) {
     VGPR_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
     VGPR_HIP(ctx, hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming));
   }
@@ -198,7 +198,7 @@ vgpr_status vgpr_destroy(vgpr_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < vgpr_ctx::kAux; ++i) {
     if (ctx->aux[i]) {
       (void)hipStreamSynchronize(ctx->aux[i]);
       (void)hipStreamDestroy(ctx->aux[i]);
@@ -251,7 +251,7 @@ vgpr_status vgpr_profile_read(vgpr_ctx* ctx, const char* name, double* h_total_m
   if (!ctx || !name) return VGPR_E_INVALID;
   (void)hipSetDevice(ctx->device);
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < vgpr_ctx::kAux; ++i)
     if (ctx->aux[i]) VGPR_HIP(ctx, hipStreamSynchronize(ctx->aux[i]));
   double total = 0.0;
   int64_t count = 0;

@@ -1699,11 +1699,13 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   st = ensure_aux(ctx);
   if (st != VGPR_OK) return st;
   VGPR_HIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
-  for (int i = 0; i < 2; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+  for (int i = 0; i < vgpr_ctx::kAux; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
   const vgpr_tuning& tu = ctx->tune;
   auto stream_of = [&](int b) {
     if (tu.streams == 1) return ctx->stream;
-    return b >= 3 ? ctx->aux[0] : (b >= 1 ? ctx->aux[1] : ctx->stream);
+    // 256/512-point buckets on their own stream: their workgroups need whole CUs of LDS, so even an
+    // empty launch waits for CUs to drain and would hold back the buckets queued behind it
+    return b >= 5 ? ctx->aux[2] : (b >= 3 ? ctx->aux[0] : (b >= 1 ? ctx->aux[1] : ctx->stream));
   };
   for (int b = kNumBuckets - 1; b >= 0; --b) {
     if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
@@ -1733,7 +1735,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
       if (st != VGPR_OK) return st;
     }
   }
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < vgpr_ctx::kAux; ++i) {
     VGPR_HIP(ctx, hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
     VGPR_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0));
   }

@@ -52,9 +52,10 @@ struct vgpr_ctx {
   int live_maps = 0;          // maps created on this context and not yet destroyed
   int live_graphs = 0;        // captured graphs created on this context and not yet destroyed
   vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}, 5};
-  hipStream_t aux[2] = {nullptr, nullptr};  // side streams the solver buckets fork onto
+  static constexpr int kAux = 3;
+  hipStream_t aux[kAux] = {nullptr, nullptr, nullptr};  // side streams the solver buckets fork onto
   hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[2] = {nullptr, nullptr};
+  hipEvent_t join_ev[kAux] = {nullptr, nullptr, nullptr};
   bool profiling = false;
   std::map<std::string, vgpr::ProfFamily> prof;
   std::vector<hipEvent_t> event_pool;
