@@ -103,6 +103,7 @@ class Params:
     noise_var: float = 1e-3
     ls_mode: int = 0          # 0 fixed l, 1 per-voxel l from PCA eigenvalues
     converge_var: float = 0.3
+    frame_mode: int = 0       # 0 world value axis (Alg. 1), 1 PCA-rotated local frame
 
 
 # ----------------------------------------------------------------------------
@@ -239,6 +240,38 @@ def local_frame(P: np.ndarray) -> Frame:
     return Frame(axis=a, params=PARAM_AXES[a], centroid=c, eigvals=w, normal=v, ambiguous=amb)
 
 
+def rotated_frame(fr: Frame) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Orthonormal local frame (e1, e2, v) of the PCA-rotated variant (frame_mode 1).
+
+    v is the surface normal of `local_frame` with its largest component made
+    positive (the sign of an eigenvector is arbitrary). The in-plane axes are
+    not the other two eigenvectors, whose directions are undefined when their
+    eigenvalues coincide (a roughly isotropic patch); instead e1 is the unit
+    vector along e_k x v, e_k the world axis least aligned with v (smallest
+    |v_k|, ties to the lower index), and e2 = v x e1, a right-handed frame
+    that depends continuously on v.
+    """
+    v = np.asarray(fr.normal, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    if v[fr.axis] < 0:
+        v = -v
+    k = int(np.argmin(np.abs(v)))
+    ek = np.zeros(3)
+    ek[k] = 1.0
+    e1 = np.cross(ek, v)
+    e1 = e1 / np.linalg.norm(e1)
+    e2 = np.cross(v, e1)
+    return e1, e2, v
+
+
+def rotated_grid(voxel_size: float, n_q: int) -> np.ndarray:
+    """Query grid of frame_mode 1: interval centres of an s x s square centred
+    on the voxel's centroid in its (e1, e2) plane; row q = i n_q + j, i along e1."""
+    s = float(np.float32(voxel_size))
+    t = np.array([((i + 0.5) / n_q - 0.5) * s for i in range(n_q)])
+    return np.stack([np.repeat(t, n_q), np.tile(t, n_q)], axis=1)
+
+
 def pca_length_scale(eigvals: np.ndarray, voxel_size: float) -> float:
     """Per-voxel length scale for the aggregated-map workload (ls_mode 1).
 
@@ -346,6 +379,8 @@ def fit_predict_voxel(P: np.ndarray, key, params: Params, axis: int | None = Non
         res["status"] |= ST_BELOW_TAU
         return res
     fr = local_frame(P)
+    if params.frame_mode == 1:
+        return _fit_predict_rotated(P, fr, params, noise_var, n, res)
     a = fr.axis if axis is None else int(axis)
     u, w = PARAM_AXES[a]
     k = unpack_key(key)
@@ -363,6 +398,32 @@ def fit_predict_voxel(P: np.ndarray, key, params: Params, axis: int | None = Non
     if fr.ambiguous:
         res["status"] |= ST_AXIS_TIE
     res.update(axis=a, ambiguous=fr.ambiguous, length_scale=ell, frame=fr)
+    return res
+
+
+def _fit_predict_rotated(P, fr, params, noise_var, n, res):
+    """frame_mode 1: Alg. 1 in the PCA-rotated frame. With c the centroid,
+    x = ((p - c).e1, (p - c).e2) and f = (p - c).v; the predicted world point
+    of query x*_q is c + x*_q,1 e1 + x*_q,2 e2 + mu*_q v. Points of a noiseless
+    plane have f = 0, so every prediction lies on that plane exactly."""
+    e1, e2, v = rotated_frame(fr)
+    c = fr.centroid
+    D = P - c
+    x = np.stack([D @ e1, D @ e2], axis=1)
+    f = D @ v
+    xq = rotated_grid(params.voxel_size, params.grid_side)
+    ell = params.length_scale if params.ls_mode == 0 else pca_length_scale(fr.eigvals, params.voxel_size)
+    nv = params.noise_var if noise_var is None else np.asarray(noise_var, dtype=np.float64)[:n]
+    mean, var = gp_posterior(x, f, xq, params.signal_var, ell, nv)
+    out = res["out"]
+    out[:, :3] = c + xq[:, :1] * e1 + xq[:, 1:] * e2 + mean[:, None] * v
+    out[:, 3] = var
+    res["status"] |= ST_SOLVED
+    if var.max() <= params.converge_var:
+        res["status"] |= ST_CONVERGED
+    if fr.ambiguous:
+        res["status"] |= ST_AXIS_TIE
+    res.update(axis=fr.axis, ambiguous=fr.ambiguous, length_scale=ell, frame=fr, rotation=(e1, e2, v))
     return res
 
 

@@ -209,3 +209,70 @@ def test_gauss_pins_green_on_unmodified_oracle():
 def test_gauss_pins_catch_mutant(monkeypatch, name, mutant):
     monkeypatch.setattr(O, "gauss_init", mutant)
     assert _gauss_caught(), f"no pin caught the mutant: {name}"
+
+
+# ---------------------------------------------------------------------------
+# PCA-rotated frame (frame_mode 1): mutants
+# ---------------------------------------------------------------------------
+_orig_rot_frame = O.rotated_frame
+_orig_rot_grid = O.rotated_grid
+
+
+def _rot_frame_swapped(fr):
+    e1, e2, v = _orig_rot_frame(fr)
+    return e2, -e1, v  # still right-handed, but the grid's i axis runs along e2
+
+
+def _rot_frame_fixed_axis(fr):
+    # e1 from a fixed world axis (x) instead of the one least aligned with the normal
+    v = _orig_rot_frame(fr)[2]
+    e1 = np.cross([1.0, 0.0, 0.0], v)
+    e1 = e1 / np.linalg.norm(e1)
+    return e1, np.cross(v, e1), v
+
+
+def _rot_frame_world_axis(fr):
+    # value along the world axis of Alg. 1 instead of the normal
+    a = fr.axis
+    v = np.zeros(3)
+    v[a] = 1.0
+    u, w = O.PARAM_AXES[a]
+    e1 = np.zeros(3)
+    e1[u] = 1.0
+    return e1, np.cross(v, e1), v
+
+
+def _rot_grid_uncentred(s, nq):
+    return _orig_rot_grid(s, nq) + 0.5 * float(np.float32(s))
+
+
+ROT_PINS = [
+    lambda: [pins.test_rotated_frame_recovers_noiseless_tilted_planes_exactly(c) for c in
+             [(0.5, 0.25, 0.125, [0, 1, 2]), (1.5, -0.25, 0.0, [1, 2, 0])]],
+    lambda: pins.test_rotated_frame_closed_form_and_grid_geometry(),
+    lambda: pins.test_rotated_frame_orthonormal_and_continuous(),
+]
+
+
+def _rot_caught():
+    for t in ROT_PINS:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def test_rotated_pins_green_on_unmodified_oracle():
+    assert not _rot_caught()
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("in-plane axes swapped", "rotated_frame", _rot_frame_swapped),
+    ("in-plane axis from a fixed world axis", "rotated_frame", _rot_frame_fixed_axis),
+    ("value along the world axis", "rotated_frame", _rot_frame_world_axis),
+    ("grid not centred on the centroid", "rotated_grid", _rot_grid_uncentred),
+])
+def test_rotated_pins_catch_mutant(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(O, target, mutant)
+    assert _rot_caught(), f"no pin caught the mutant: {name}"

@@ -597,3 +597,76 @@ def test_gauss_floor_unsolved_and_single_point_subgrids():
     assert np.allclose(g1[:, :, :3], rows[:, :, :3], rtol=1e-15, atol=1e-15)
     assert np.all(np.abs(g1[:, :, 4:7]) <= 1e-28)  # zero up to the rounding of w P / w
     assert q == 5
+
+
+# ---------------------------------------------------------------------------
+# PCA-rotated local frame (frame_mode 1)
+# ---------------------------------------------------------------------------
+def _dyadic_plane_points(coef, n=40, seed=0):
+    """Points with dyadic coordinates on z = a x + b y + c (exact in float32),
+    or on the same plane with the axes cyclically relabelled."""
+    r = rng(seed)
+    a, b, c, perm = coef
+    xy = r.integers(0, 32, size=(n, 2)) / 64.0
+    z = a * xy[:, 0] + b * xy[:, 1] + c
+    P = np.stack([xy[:, 0], xy[:, 1], z], axis=1)[:, perm]
+    assert np.array_equal(P.astype(np.float32).astype(np.float64), P)
+    return P
+
+
+@pytest.mark.parametrize("coef", [(0.5, 0.25, 0.125, [0, 1, 2]), (-0.75, 0.5, 0.25, [0, 1, 2]),
+                                  (1.5, -0.25, 0.0, [1, 2, 0]), (0.25, 2.0, 0.5, [2, 0, 1]),
+                                  (-3.0, 0.5, 0.75, [0, 2, 1])])
+def test_rotated_frame_recovers_noiseless_tilted_planes_exactly(coef):
+    """Every prediction lies on the plane of the data, for any tilt (the value
+    coordinate of coplanar points is zero in the rotated frame)."""
+    P = _dyadic_plane_points(coef)
+    a, b, c, perm = coef
+    nrm = np.array([-a, -b, 1.0])[perm]  # normal in the relabelled axes: column j is axis perm[j]
+    key = O.pack_keys(O.voxel_coords(P[:1], 1.0)[0])[0]
+    for nq in (3, 8):
+        prm = O.Params(voxel_size=1.0, min_pts=3, grid_side=nq, frame_mode=1, length_scale=0.3)
+        r = O.fit_predict_voxel(P, key, prm)
+        assert r["status"] & O.ST_SOLVED
+        out = r["out"][:, :3]
+        # distance of every predicted point to the plane through the data
+        off = (out - P[0]) @ nrm / np.linalg.norm(nrm)
+        assert np.abs(off).max() <= 1e-12, np.abs(off).max()
+
+
+def test_rotated_frame_closed_form_and_grid_geometry():
+    """Plane z = x / 2: normal (-1, 0, 2)/sqrt(5) with its z component positive,
+    e1 = e_y x v = (2, 0, 1)/sqrt(5), e2 = v x e1 = (0, 1, 0); the predicted points
+    project onto (e1, e2) about the centroid as the interval centres of an s x s square."""
+    P = _dyadic_plane_points((0.5, 0.0, 0.25, [0, 1, 2]), n=30, seed=3)
+    prm = O.Params(voxel_size=0.5, min_pts=3, grid_side=4, frame_mode=1, length_scale=0.2)
+    key = O.pack_keys(O.voxel_coords(P[:1], 0.5)[0])[0]
+    r = O.fit_predict_voxel(P, key, prm)
+    e1, e2, v = r["rotation"]
+    s5 = math.sqrt(5.0)
+    assert np.allclose(v, [-1 / s5, 0, 2 / s5], atol=1e-14)
+    assert np.allclose(e1, [2 / s5, 0, 1 / s5], atol=1e-14)
+    assert np.allclose(e2, [0, 1, 0], atol=1e-14)
+    assert np.allclose(np.cross(e1, e2), v, atol=1e-14)
+    c = P.mean(axis=0)
+    d = r["out"][:, :3] - c
+    t = [((i + 0.5) / 4 - 0.5) * 0.5 for i in range(4)]
+    assert np.allclose(d @ e1, np.repeat(t, 4), atol=1e-12)
+    assert np.allclose(d @ e2, np.tile(t, 4), atol=1e-12)
+
+
+def test_rotated_frame_orthonormal_and_continuous():
+    r0 = rng(50)
+    for _ in range(20):
+        P = r0.normal(size=(30, 3)) * [1.0, 0.7, 0.05]
+        Q, _ = np.linalg.qr(r0.normal(size=(3, 3)))
+        P = P @ Q.T
+        fr = O.local_frame(P)
+        e1, e2, v = O.rotated_frame(fr)
+        M = np.stack([e1, e2, v])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-13)
+        assert np.linalg.det(M) > 0 and v[fr.axis] > 0
+        # a tiny perturbation of the points moves the frame only a little
+        e1b, e2b, vb = O.rotated_frame(O.local_frame(P + 1e-9 * r0.normal(size=P.shape)))
+        if np.argmin(np.abs(v)) == np.argmin(np.abs(vb)):
+            assert np.abs(np.stack([e1b, e2b, vb]) - M).max() < 1e-6
