@@ -82,7 +82,8 @@ enum {
                           (cross-covariance) tile products in split BF16 (hi x hi + hi x lo +
                           lo x hi) with FP32 accumulation, the mean from K*^T alpha in FP64
                           with alpha = (K + S)^-1 f~ from the FP32 factor and, when
-                          n s_f^2 / min pivot exceeds cond_threshold, one FP64 residual
+                          n s_f^2 / min pivot exceeds cond_threshold or the refinement score
+                          sum_j |y_j| / d_j exceeds refine_threshold, one FP64 residual
                           refinement step of alpha (status REFINED) */
   VGPR_PREC_FP64 = 2   /* FP64 build and LDL^T for every voxel */
 };
@@ -103,7 +104,14 @@ typedef struct {
   float noise_var;        /* sigma_n^2, the sensor noise variance added to K's diagonal, >= 0 */
   int32_t ls_mode;        /* 0: fixed length_scale; 1: per voxel from PCA eigenvalues,
                              l = sqrt(3 (lambda_mid + lambda_max) / 2) clamped to [0.05 s, 2 s] */
-  int32_t frame_mode;     /* 0: world value axis of Alg. 1 (the only mode in this build) */
+  int32_t frame_mode;     /* 0: world value axis of Alg. 1 (value = world coordinate a, grid on
+                             the voxel face); 1: PCA-rotated frame: value along the normal v
+                             (largest component positive), parameters along e1 = unit(e_k x v),
+                             e_k the world axis least aligned with v, and e2 = v x e1, about the
+                             centroid; grid = interval centres of an s x s square centred on the
+                             centroid in the (e1, e2) plane; output rows are world points
+                             centroid + u e1 + w e2 + mean v (noiseless planes are reproduced
+                             exactly in any orientation) */
   int32_t precision;      /* VGPR_PREC_* */
   float refine_threshold; /* FP32 mode: re-solve in FP64 when sum_j |y_j| / d_j exceeds this */
   float converge_var;     /* eta: converged when the max predicted variance <= eta */

@@ -117,7 +117,7 @@ vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
   if (!(p->signal_var > 0.f) || !(p->length_scale > 0.f) || !(p->noise_var >= 0.f))
     return fail(ctx, VGPR_E_INVALID, "signal_var and length_scale must be > 0, noise_var >= 0");
   if (p->ls_mode != 0 && p->ls_mode != 1) return fail(ctx, VGPR_E_INVALID, "ls_mode must be 0 or 1");
-  if (p->frame_mode != 0) return fail(ctx, VGPR_E_UNSUPPORTED, "frame_mode 1 is not supported by this build");
+  if (p->frame_mode != 0 && p->frame_mode != 1) return fail(ctx, VGPR_E_INVALID, "frame_mode must be 0 or 1");
   if (p->precision != VGPR_PREC_FP32 && p->precision != VGPR_PREC_FP64 && p->precision != VGPR_PREC_MIXED)
     return fail(ctx, VGPR_E_INVALID, "unknown precision");
   if (p->precision == VGPR_PREC_MIXED && !(p->cond_threshold > 0.f))

@@ -54,6 +54,7 @@ struct FitParams {
   int nq;           // grid side
   int m;            // nq * nq
   int ls_mode;
+  int frame_mode;   // 0 world value axis, 1 PCA-rotated frame
   int mode;         // 0 = FP32 first pass (flags), 1 = FP64 re-solve pass, 2 = FP64 only
   int bcap[kNumBuckets];  // bucket capacities
   float sf2;
@@ -85,11 +86,18 @@ struct SlotRec {
   int pad;
 };
 
+// Rotated local frame of one slot (frame_mode 1): centroid and the axes (e1, e2, v).
+struct RotRec {
+  double c[3];
+  double e1[3], e2[3], v[3];
+};
+
 struct Lists {
   SlotRec* recs;         // kNumBuckets lists of `stride` slot records
   int32_t* nan_list;     // voxels below tau
   uint32_t* count;       // kLists counters
   int64_t stride;
+  RotRec* rots;          // frame_mode 1: one rotated frame per slot record, else null
 };
 
 __device__ __forceinline__ float k_exp(float x) { return __expf(x); }
@@ -280,6 +288,41 @@ __global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, floa
   r.off = off;
   r.cnt = c;
   r.pad = 0;
+  if (P.frame_mode == 1) {
+    // rotated frame: the normal with its largest component positive, e1 along e_k x v for the
+    // world axis k least aligned with v (ties to the lower index), e2 = v x e1; local
+    // coordinates are taken about the centroid, so the value's mean and the anchors are 0
+    const double nv = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    const double sg = (ax == 0 ? v0 : (ax == 1 ? v1 : v2)) < 0.0 ? -1.0 : 1.0;
+    const double n0 = sg * v0 / nv, n1 = sg * v1 / nv, n2 = sg * v2 / nv;
+    const double c0 = fabs(n0), c1 = fabs(n1), c2 = fabs(n2);
+    const int k = (c1 < c0) ? ((c2 < c1) ? 2 : 1) : ((c2 < c0) ? 2 : 0);
+    // e_k x n
+    double a0 = k == 0 ? 0.0 : (k == 1 ? n2 : -n1);
+    double a1 = k == 0 ? -n2 : (k == 1 ? 0.0 : n0);
+    double a2 = k == 0 ? n1 : (k == 1 ? -n0 : 0.0);
+    const double an = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+    a0 /= an;
+    a1 /= an;
+    a2 /= an;
+    RotRec rr;
+    rr.c[0] = p0x + m0;
+    rr.c[1] = p0y + m1;
+    rr.c[2] = p0z + m2;
+    rr.e1[0] = a0;
+    rr.e1[1] = a1;
+    rr.e1[2] = a2;
+    rr.e2[0] = n1 * a2 - n2 * a1;  // n x e1
+    rr.e2[1] = n2 * a0 - n0 * a2;
+    rr.e2[2] = n0 * a1 - n1 * a0;
+    rr.v[0] = n0;
+    rr.v[1] = n1;
+    rr.v[2] = n2;
+    L.rots[lst * L.stride + slot] = rr;
+    r.fr.mu = 0.0;
+    r.fr.anc_u = 0.0;
+    r.fr.anc_w = 0.0;
+  }
   L.recs[lst * L.stride + slot] = r;
 }
 
@@ -328,6 +371,12 @@ __device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& 
 
 __device__ __forceinline__ void query_coords(const FitParams& P, const FrameRec& fr, int q, float* gu, float* gw) {
   const int i = q / P.nq, j = q - (q / P.nq) * P.nq;
+  if (P.frame_mode == 1) {
+    // interval centres of an s x s square centred on the centroid, in the (e1, e2) plane
+    *gu = (float)__dmul_rn(__dadd_rn(__ddiv_rn((double)i + 0.5, (double)P.nq), -0.5), P.s);
+    *gw = (float)__dmul_rn(__dadd_rn(__ddiv_rn((double)j + 0.5, (double)P.nq), -0.5), P.s);
+    return;
+  }
   const double ti = __ddiv_rn((double)i + 0.5, (double)P.nq);
   const double tj = __ddiv_rn((double)j + 0.5, (double)P.nq);
   *gu = (float)__dmul_rn(__dadd_rn((double)fr.ku, ti), P.s);
@@ -343,12 +392,41 @@ __device__ __forceinline__ float4 out_row(int ax, int u, float mv, float gu, flo
   return o;
 }
 
+// Local coordinates of a staged point: (u, w) on the parameter plane and the centred value f.
+__device__ __forceinline__ void local_point(const FitParams& P, const FrameRec& fr, const RotRec* __restrict__ rot,
+                                            float4 pt, double* xu, double* xw, double* fv) {
+  if (P.frame_mode == 1) {
+    const double dx = (double)pt.x - rot->c[0], dy = (double)pt.y - rot->c[1], dz = (double)pt.z - rot->c[2];
+    *xu = dx * rot->e1[0] + dy * rot->e1[1] + dz * rot->e1[2];
+    *xw = dx * rot->e2[0] + dy * rot->e2[1] + dz * rot->e2[2];
+    *fv = dx * rot->v[0] + dy * rot->v[1] + dz * rot->v[2] - fr.mu;
+  } else {
+    const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
+    *xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
+    *xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
+    *fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
+  }
+}
+
+// Output row of query (gu, gw) with predicted value fhat and variance vv, in world coordinates.
+__device__ __forceinline__ float4 make_row(const FitParams& P, const FrameRec& fr, const RotRec* __restrict__ rot,
+                                           double fhat, float gu, float gw, float vv) {
+  if (P.frame_mode == 1) {
+    const double a = gu, b = gw;
+    return make_float4((float)(rot->c[0] + a * rot->e1[0] + b * rot->e2[0] + fhat * rot->v[0]),
+                       (float)(rot->c[1] + a * rot->e1[1] + b * rot->e2[1] + fhat * rot->v[1]),
+                       (float)(rot->c[2] + a * rot->e1[2] + b * rot->e2[2] + fhat * rot->v[2]), vv);
+  }
+  return out_row(fr.axes & 3, (fr.axes >> 2) & 3, (float)fhat, gu, gw, vv);
+}
+
 // ---------------------------------------------------------------------------
 // 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
 // ---------------------------------------------------------------------------
 template <typename T, int NMAX, int QR>
 __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
+                                                                const RotRec* __restrict__ rots,
                                                                 const float4* __restrict__ staged,
                                                                 const int32_t* __restrict__ slots,
                                                                 const uint32_t* __restrict__ count,
@@ -387,6 +465,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     }
     if (it + 2 * nw < cnt_items) rnn = recs[slots ? slots[it + 2 * nw] : it + 2 * nw];
     const FrameRec& fr = r.fr;
+    const RotRec* rot = rots ? rots + (slots ? slots[it] : it) : nullptr;
     const int v = r.v;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
@@ -395,9 +474,11 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     // this lane's data point (lanes < n)
     T xu = 0, xw = 0, fv = 0, nz = 0;
     if (lane < n) {
-      xu = (T)((double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u);
-      xw = (T)((double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w);
-      fv = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
+      double du, dw, df;
+      local_point(P, fr, rot, pt, &du, &dw, &df);
+      xu = (T)du;
+      xw = (T)dw;
+      fv = (T)df;
       nz = (T)pt.w;
     }
     // this lane's query points q = lane + 64 r (r < QR, q < m): row i, column j of the grid
@@ -544,8 +625,8 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       const int q = lane + 64 * r;
       if (!flag && q < P.m) {
         const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var[r] > (T)0 ? var[r] : (T)0);
-        const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean[r]);
-        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = out_row(ax, u, mv, gu[r], gwv[r], vv);
+        const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + (double)mean[r];
+        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = make_row(P, fr, rot, fh, gu[r], gwv[r], vv);
         mv_lane = fmaxf(mv_lane, failed ? 0.f : vv);
       }
     }
@@ -561,6 +642,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, FitArgs io,
                                                                   const SlotRec* __restrict__ recs,
+                                                                  const RotRec* __restrict__ rots,
                                                                   const float4* __restrict__ staged,
                                                                   const int32_t* __restrict__ slots,
                                                                   const uint32_t* __restrict__ count,
@@ -591,15 +673,18 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
     const int slot = slots ? slots[item] : item;
     const SlotRec r = recs[slot];
     const FrameRec& fr = r.fr;
+    const RotRec* rot = rots ? rots + slot : nullptr;
     const int v = r.v;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
     const int cnt = r.cnt;
     for (int i = tid; i < n; i += NT) {
       const float4 pt = staged[r.off + i];
-      su[i] = (T)((double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u);
-      sw[i] = (T)((double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w);
-      sf[i] = (T)((double)pick(ax, pt.x, pt.y, pt.z) - fr.mu);
+      double du, dw, df;
+      local_point(P, fr, rot, pt, &du, &dw, &df);
+      su[i] = (T)du;
+      sw[i] = (T)dw;
+      sf[i] = (T)df;
       sn[i] = (T)pt.w;
     }
     __syncthreads();
@@ -672,8 +757,8 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
       const bool flag = P.mode == 0 && (failed || score > (T)P.refine_thr);
       if (is_query && !flag) {
         const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > (T)0 ? var : (T)0);
-        const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + (double)mean);
-        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = out_row(ax, u, mv, gu, gwv, vv);
+        const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + (double)mean;
+        reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = make_row(P, fr, rot, fh, gu, gwv, vv);
         if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
       }
       if (flag) {
@@ -747,6 +832,7 @@ __device__ __forceinline__ double sum16(double v) {
 template <int NPAD>
 __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
+                                                                const RotRec* __restrict__ rots,
                                                                 const float4* __restrict__ staged,
                                                                 const uint32_t* __restrict__ count,
                                                                 uint32_t* __restrict__ next,
@@ -788,6 +874,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
     if (item >= cnt_items) break;
     const SlotRec r = recs[item];
     const FrameRec& fr = r.fr;
+    const RotRec* rot = rots ? rots + item : nullptr;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
     const double lam = fr.lam;
@@ -796,9 +883,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
       float nz = 0.f;
       if (i < n) {
         const float4 pt = staged[r.off + i];
-        xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
-        xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
-        fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
+        local_point(P, fr, rot, pt, &xu, &xw, &fv);
         nz = pt.w;
       }
       pu[i] = xu;
@@ -1013,8 +1098,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
           const bool failed = s_fail != 0;
           const double var = sf2 - zz;
           const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > 0.0 ? var : 0.0);
-          const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + zy);
-          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = out_row(ax, u, mv, gu, gw, vv);
+          const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + zy;
+          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = make_row(P, fr, rot, fh, gu, gw, vv);
           if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
         }
         __syncthreads();
@@ -1033,9 +1118,10 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
 // - K and its Cholesky factor in FP32: tile products on the FP32 matrix cores
 //   (16 x 16 x 4), diagonal tiles by LDL^T on one wavefront.
 // - alpha = L^-T L^-1 f~ by block substitution from the FP32 factor,
-//   accumulated in double; when n s_f^2 / min pivot exceeds cond_threshold,
-//   one refinement step alpha += (K + S)^-1 (f~ - (K + S) alpha) with the
-//   residual in FP64 (kernel entries recomputed in double).
+//   accumulated in double; when n s_f^2 / min pivot exceeds cond_threshold
+//   (small pivots) or the amplification score sum_j |y_j| / d_j exceeds
+//   refine_threshold, one refinement step alpha += (K + S)^-1 (f~ - (K + S) alpha)
+//   with the residual in FP64 (kernel entries recomputed in double).
 // - mean_q = mu + sum_c kappa(x*_q, x_c) alpha_c in FP64, so the mean does not
 //   depend on the reduced-precision products below.
 // - z_q = L^-1 k*_q through the same tile recurrences, every query tile
@@ -1078,6 +1164,7 @@ __device__ __forceinline__ flt4 mfma_split(const bf16x8& ah, const bf16x8& al, c
 template <int NPAD>
 __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams P, FitArgs io,
                                                                       const SlotRec* __restrict__ recs,
+                                                                      const RotRec* __restrict__ rots,
                                                                       const float4* __restrict__ staged,
                                                                       const uint32_t* __restrict__ count,
                                                                       uint32_t* __restrict__ next,
@@ -1101,6 +1188,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
   __shared__ int s_item;
   __shared__ int s_fail;
   __shared__ float s_minpiv;
+  __shared__ float s_score;
   __shared__ unsigned s_maxvar;
   constexpr int XS = kTile + 4;
 
@@ -1124,6 +1212,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
       s_item = (int)atomicAdd(next, 1u);
       s_fail = 0;
       s_minpiv = FLT_MAX;
+      s_score = 0.f;
       s_maxvar = 0u;
     }
     __syncthreads();
@@ -1131,6 +1220,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
     if (item >= cnt_items) break;
     const SlotRec r = recs[item];
     const FrameRec& fr = r.fr;
+    const RotRec* rot = rots ? rots + item : nullptr;
     const int n = fr.n;
     const int ax = fr.axes & 3, u = (fr.axes >> 2) & 3, wax = (fr.axes >> 4) & 3;
     const double lam = fr.lam;
@@ -1140,9 +1230,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
       float nz = 0.f;
       if (i < n) {
         const float4 pt = staged[r.off + i];
-        xu = (double)pick(u, pt.x, pt.y, pt.z) - fr.anc_u;
-        xw = (double)pick(wax, pt.x, pt.y, pt.z) - fr.anc_w;
-        fv = (double)pick(ax, pt.x, pt.y, pt.z) - fr.mu;
+        local_point(P, fr, rot, pt, &xu, &xw, &fv);
         nz = pt.w;
       }
       pu[i] = xu;
@@ -1229,6 +1317,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
         for (int c = 0; c < kTile; ++c) B[c] = lane < kTile ? rb[lane * LD + I * kTile + c] : 0.f;
         bool bad = false;
         float mp = FLT_MAX;
+        float sc = 0.f;  // sum_j |y_j| / d_j of the unit-diagonal factor (the FP32 amplification score)
         for (int j = 0; j < kTile; ++j) {
           const float cj = B[0];
           sdcf[lane] = cj;
@@ -1243,7 +1332,10 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
           const float rs = sqrtf(inv);
           const float t = cj * inv;
           bad |= !(d > 0.f);
-          if (I * kTile + j < n) mp = fminf(mp, d);
+          if (I * kTile + j < n) {
+            mp = fminf(mp, d);
+            sc += fabsf(yj) * inv;
+          }
           if (lane == j) {
             rb[lane * LD + I * kTile + j] = d * rs;
             srdf[j] = rs;
@@ -1260,6 +1352,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
         if (lane == 0) {
           if (bad) s_fail = 1;
           s_minpiv = fminf(s_minpiv, mp);
+          s_score += sc;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1320,7 +1413,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
       }
     };
     back(sy, nullptr, sal);
-    const bool refine = !s_fail && (double)n * sf2 / (double)s_minpiv > (double)P.cond_thr;
+    const bool refine = !s_fail && ((double)n * sf2 / (double)s_minpiv > (double)P.cond_thr ||
+                                    !(s_score <= P.refine_thr));
     if (refine) {
       // residual f~ - (K + S) alpha in FP64, one row per thread
       for (int i = tid; i < nbd * kTile; i += kTileThreads) {
@@ -1447,8 +1541,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
           const bool failed = s_fail != 0;
           const double var = sf2 - (double)zz;
           const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > 0.0 ? var : 0.0);
-          const float mv = failed ? __int_as_float(0x7fc00000) : (float)(fr.mu + smean[rr]);
-          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = out_row(ax, u, mv, gu, gw, vv);
+          const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + smean[rr];
+          reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = make_row(P, fr, rot, fh, gu, gw, vv);
           if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
         }
         __syncthreads();
@@ -1484,6 +1578,7 @@ struct Launch {
   hipStream_t stream;
   int grid_scale;            // x 1/4 of the resident workgroups
   const SlotRec* recs;
+  const RotRec* rots;        // frame_mode 1: rotated frames parallel to recs, else null
   const int32_t* slots;      // nullable: item -> slot indirection (re-solve lists)
   const uint32_t* count;
   uint32_t* next;
@@ -1504,7 +1599,7 @@ vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, co
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam, l.stream);
   hipLaunchKernelGGL((fit_wave_kernel<T, NMAX, QR>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P, io,
-                     l.recs, staged, l.slots, l.count, l.rlist, l.rcount);
+                     l.recs, l.rots, staged, l.slots, l.count, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -1522,7 +1617,7 @@ vgpr_status launch_block(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, c
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam, l.stream);
   hipLaunchKernelGGL((fit_block_kernel<T, NMAX>), dim3((unsigned)grid), dim3(threads), 0, l.stream, P, io,
-                     l.recs, staged, l.slots, l.count, l.next, l.rlist, l.rcount);
+                     l.recs, l.rots, staged, l.slots, l.count, l.next, l.rlist, l.rcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -1567,9 +1662,10 @@ void launch_tile_kernel(int npad, dim3 g, dim3 t, hipStream_t s, const FitParams
 #define VGPR_TILE_CASE(NP)                                                                                   \
   case NP:                                                                                                   \
     if (MIXED)                                                                                               \
-      hipLaunchKernelGGL(fit_tile_mixed_kernel<NP>, g, t, 0, s, P, io, l.recs, staged, l.count, l.next, scratch); \
+      hipLaunchKernelGGL(fit_tile_mixed_kernel<NP>, g, t, 0, s, P, io, l.recs, l.rots, staged, l.count, l.next,     \
+                         scratch);                                                                            \
     else                                                                                                     \
-      hipLaunchKernelGGL(fit_tile_kernel<NP>, g, t, 0, s, P, io, l.recs, staged, l.count, l.next, scratch);  \
+      hipLaunchKernelGGL(fit_tile_kernel<NP>, g, t, 0, s, P, io, l.recs, l.rots, staged, l.count, l.next, scratch); \
     break;
   switch (npad) {
     VGPR_TILE_CASE(64)
@@ -1630,7 +1726,8 @@ size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const v
   const bool mixed = p->precision == VGPR_PREC_MIXED;
   for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
     if (p->max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b, mixed));
-  return Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
+  const size_t rot_bytes = p->frame_mode == 1 ? Carver::round(sizeof(RotRec) * (size_t)n_vox * kNumBuckets) : 0;
+  return rot_bytes + Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
          Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
          Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
 }
@@ -1650,6 +1747,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     if (st != VGPR_OK) return st;
   }
   Carver cv(fixed_work ? fixed_work : static_cast<char*>(ctx->work.ptr) + work_offset);
+  RotRec* rots = p->frame_mode == 1 ? cv.take<RotRec>((size_t)a.n_vox * kNumBuckets) : nullptr;
   SlotRec* recs = cv.take<SlotRec>((size_t)a.n_vox * kNumBuckets);
   float4* staged = cv.take<float4>((size_t)a.n_pts);
   int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
@@ -1671,6 +1769,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   P.nq = p->grid_side;
   P.m = m;
   P.ls_mode = p->ls_mode;
+  P.frame_mode = p->frame_mode;
   for (int b = 0; b < kNumBuckets; ++b) P.bcap[b] = kBucketCap[b];
   P.sf2 = p->signal_var;
   P.noise = p->noise_var;
@@ -1682,7 +1781,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   const bool fp32 = p->precision == VGPR_PREC_FP32 || p->precision == VGPR_PREC_MIXED;
   P.mode = 2;
 
-  Lists L{recs, nan_list, ctr, a.n_vox};
+  Lists L{recs, nan_list, ctr, a.n_vox, rots};
   {
     ProfScope ps(ctx, "classify");
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((a.n_vox + 255) / 256)), dim3(256), 0, ctx->stream, P, a,
@@ -1714,7 +1813,8 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket && !tiled;
     FitParams Pb = P;
     Pb.mode = in_fp32 ? 0 : 2;
-    Launch l{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, nullptr, ctr + b, ctr + 8 + b,
+    const RotRec* rb_ = rots ? rots + (size_t)b * a.n_vox : nullptr;
+    Launch l{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rb_, nullptr, ctr + b, ctr + 8 + b,
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     if (tiled) {
       if (mixed) l.fam = kFamMixed[b];
@@ -1729,7 +1829,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
       // FP64 re-solve of this bucket's flagged voxels, on the same stream right after it
       FitParams R = P;
       R.mode = 1;
-      Launch lr{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rlists + (size_t)b * a.n_vox,
+      Launch lr{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rb_, rlists + (size_t)b * a.n_vox,
                 ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
       st = launch_bucket<double>(ctx, b, wave, R, a, staged, lr);
       if (st != VGPR_OK) return st;

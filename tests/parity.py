@@ -100,3 +100,36 @@ def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, vox
             assert bool(st & O.ST_CONVERGED) == bool(mv <= prm.converge_var), (v, mv)
     return {"max_mean_err": max_mean, "max_var_err": max_var, "solved": n_solved, "refined": n_refined,
             "axis_ties": n_tie}
+
+
+def compare_fit_rotated(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, voxels=None) -> dict:
+    """frame_mode 1: every output coordinate carries the predicted value (along
+    the normal), so all three are compared within MEAN_TOL (the grid offsets
+    themselves agree to float rounding, ~1e-8 m); variance as in compare_fit.
+    Voxels whose normal is a near-tie, or whose least-aligned world axis is a
+    near-tie (either side may then take the other frame), are counted and skipped."""
+    out = out.cpu().numpy().astype(np.float64)
+    status = status.cpu().numpy().astype(np.int64)
+    idx = range(len(ov["keys"])) if voxels is None else voxels
+    max_mean = max_var = 0.0
+    n_solved = n_skip = 0
+    for v in idx:
+        P = O.voxel_points(xyz, ov, v)
+        r = O.fit_predict_voxel(P, ov["keys"][v], prm)
+        st = status[v]
+        for bit in (O.ST_SOLVED, O.ST_BELOW_TAU, O.ST_CAPPED):
+            assert bool(st & bit) == bool(r["status"] & bit), (v, st, r["status"])
+        if not r["status"] & O.ST_SOLVED:
+            continue
+        n_solved += 1
+        nv = np.sort(np.abs(r["rotation"][2]))
+        if r["ambiguous"] or (st & O.ST_AXIS_TIE) or nv[1] - nv[0] < 1e-9:
+            n_skip += 1
+            continue
+        g, e = out[v], r["out"]
+        em = np.abs(g[:, :3] - e[:, :3]).max()
+        ev = np.abs(g[:, 3] - e[:, 3]).max()
+        max_mean, max_var = max(max_mean, em), max(max_var, ev)
+        assert em <= MEAN_TOL, (v, em, r["n"])
+        assert ev <= VAR_TOL_REL * prm.signal_var, (v, ev, r["n"])
+    return {"max_xyz_err": max_mean, "max_var_err": max_var, "solved": n_solved, "skipped_ties": n_skip}
