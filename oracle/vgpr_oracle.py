@@ -468,24 +468,43 @@ class VoxelMap:
     voxels it touched that hold at least tau points and are not converged
     (types (b) and (c)); types (a) (too few points) and (d) (converged) are
     skipped. A solved voxel becomes converged when its max variance <= eta.
+
+    feedback=True takes the covariance-centred update of type (c) voxels
+    (Sec. 3.3, Fig. 4): once a voxel has been solved (it is in the map) it
+    keeps its predicted grid rows, stored as float32 like the output rows, and
+    the pool is no longer extended. A later frame that touches it re-solves
+    Alg. 1 on those rows, each carrying its posterior variance as its noise
+    variance, stacked with the frame's new points (the first max_pts of them in
+    arrival order, sensor noise), and the new prediction replaces the old one;
+    this repeats until the max variance reaches eta (type (d)). Voxels not yet
+    in the map accumulate points and take their first solve as without feedback.
     """
     params: Params
+    feedback: bool = False
     points: dict = field(default_factory=dict)
     converged: dict = field(default_factory=dict)
     total: dict = field(default_factory=dict)
+    pred: dict = field(default_factory=dict)
 
     def update(self, xyz: np.ndarray) -> dict:
         vox = voxelize(xyz, self.params.voxel_size)
         keys_upd, outs, axes, stats = [], [], [], []
         for v, key in enumerate(vox["keys"].tolist()):
             P = voxel_points(xyz, vox, v)
-            have = self.points.get(key)
-            stored = P if have is None else np.concatenate([have, P])
             self.total[key] = self.total.get(key, 0) + len(P)
-            self.points[key] = stored[: self.params.max_pts]
-            if self.converged.get(key, False) or len(self.points[key]) < self.params.min_pts:
-                continue
-            r = fit_predict_voxel(self.points[key], key, self.params, n_total=self.total[key])
+            if self.feedback and key in self.pred:
+                if self.converged.get(key, False):
+                    continue
+                r = self._feedback_solve(key, P)
+            else:
+                have = self.points.get(key)
+                stored = P if have is None else np.concatenate([have, P])
+                self.points[key] = stored[: self.params.max_pts]
+                if self.converged.get(key, False) or len(self.points[key]) < self.params.min_pts:
+                    continue
+                r = fit_predict_voxel(self.points[key], key, self.params, n_total=self.total[key])
+                if self.feedback and r["status"] & ST_SOLVED:
+                    self.pred[key] = r["out"].astype(np.float32)
             if r["status"] & ST_CONVERGED:
                 self.converged[key] = True
             keys_upd.append(key)
@@ -499,6 +518,38 @@ class VoxelMap:
             "axis": np.asarray(axes, dtype=np.int64),
             "status": np.asarray(stats, dtype=np.int64),
         }
+
+    def _feedback_solve(self, key, P: np.ndarray) -> dict:
+        """Type (c) re-solve: Alg. 1 on the carried rows stacked with the new
+        points; the cap applies to the new points, so the stacked set holds up
+        to m + max_pts points. CAPPED reports that the frame brought more than
+        max_pts new points; the prediction is kept only when SOLVED."""
+        prm = self.params
+        X, nz = feedback_inputs(self.pred[key], P, prm)
+        m = prm.grid_side ** 2
+        r = fit_predict_voxel(X, key, with_params(prm, max_pts=m + prm.max_pts), noise_var=nz)
+        r["status"] = (r["status"] & ~ST_CAPPED) | (ST_CAPPED if len(P) > prm.max_pts else 0)
+        if r["status"] & ST_SOLVED:
+            self.pred[key] = r["out"].astype(np.float32)
+        return r
+
+
+# Smallest noise variance, relative to s_f^2, that a carried prediction takes
+# into a type (c) re-solve (a posterior variance can round to 0).
+PRED_NOISE_FLOOR = 1e-6
+
+
+def feedback_inputs(prev: np.ndarray, P: np.ndarray, params: Params):
+    """Stacked training set of a type (c) re-solve (Sec. 3.3, Fig. 4): the
+    previous prediction's m rows (x, y, z) first, with their posterior
+    variances (raised to PRED_NOISE_FLOOR s_f^2) as noise variances, then the
+    first max_pts new points in arrival order with the sensor noise variance."""
+    prev = np.asarray(prev, dtype=np.float32)
+    new = np.asarray(P, dtype=np.float32)[: params.max_pts]
+    X = np.concatenate([prev[:, :3], new])
+    carried = np.maximum(prev[:, 3].astype(np.float64), PRED_NOISE_FLOOR * params.signal_var)
+    nz = np.concatenate([carried, np.full(len(new), params.noise_var)])
+    return X, nz
 
 
 def with_params(p: Params, **kw) -> Params:

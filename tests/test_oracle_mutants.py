@@ -276,3 +276,84 @@ def test_rotated_pins_green_on_unmodified_oracle():
 def test_rotated_pins_catch_mutant(monkeypatch, name, target, mutant):
     monkeypatch.setattr(O, target, mutant)
     assert _rot_caught(), f"no pin caught the mutant: {name}"
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.3 covariance-centred update (VoxelMap(feedback=True))
+# ---------------------------------------------------------------------------
+_orig_fb_inputs = O.feedback_inputs
+
+
+def _fb_sensor_noise(prev, P, params):
+    X, nz = _orig_fb_inputs(prev, P, params)
+    return X, np.full(len(X), params.noise_var)  # carried rows keep the sensor variance
+
+
+def _fb_dropped(prev, P, params):
+    X, nz = _orig_fb_inputs(prev, P, params)
+    m = len(prev)
+    return X[m:], nz[m:]  # re-solve on the new points only
+
+
+def _fb_uncapped(prev, P, params):
+    prev = np.asarray(prev, np.float32)
+    new = np.asarray(P, np.float32)  # every new point, past max_pts
+    X = np.concatenate([prev[:, :3], new])
+    nz = np.concatenate([np.maximum(prev[:, 3].astype(np.float64), 1e-6), np.full(len(new), params.noise_var)])
+    return X, nz
+
+
+def _fb_std_dev(prev, P, params):
+    X, nz = _orig_fb_inputs(prev, P, params)
+    m = len(prev)
+    nz = nz.copy()
+    nz[:m] = np.sqrt(nz[:m])  # standard deviation where a variance belongs
+    return X, nz
+
+
+def _fb_pool_grows(self, xyz):
+    # the pool keeps growing after the voxel entered the map
+    vox = O.voxelize(xyz, self.params.voxel_size)
+    for v, key in enumerate(vox["keys"].tolist()):
+        if key in self.pred:
+            P = O.voxel_points(xyz, vox, v)
+            self.points[key] = np.concatenate([self.points[key], P])[: self.params.max_pts]
+    return _orig_map_update(self, xyz)
+
+
+_orig_map_update = O.VoxelMap.update
+
+FB_PINS = [
+    lambda: pins.test_feedback_update_closed_form_sequence(),
+    lambda: pins.test_feedback_variance_never_exceeds_single_pseudo_observation(),
+    lambda: pins.test_feedback_state_machine(),
+]
+
+
+def _fb_caught():
+    for t in FB_PINS:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def test_feedback_pins_green_on_unmodified_oracle():
+    assert not _fb_caught()
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("carried rows keep the sensor variance", _fb_sensor_noise),
+    ("carried rows dropped", _fb_dropped),
+    ("new points not capped", _fb_uncapped),
+    ("standard deviation as the carried noise", _fb_std_dev),
+])
+def test_feedback_pins_catch_input_mutant(monkeypatch, name, mutant):
+    monkeypatch.setattr(O, "feedback_inputs", mutant)
+    assert _fb_caught(), f"no pin caught the mutant: {name}"
+
+
+def test_feedback_pins_catch_growing_pool(monkeypatch):
+    monkeypatch.setattr(O.VoxelMap, "update", _fb_pool_grows)
+    assert _fb_caught()

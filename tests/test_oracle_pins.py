@@ -497,6 +497,130 @@ def test_map_state_machine_types():
 
 
 # ---------------------------------------------------------------------------
+# Sec. 3.3 / Fig. 4: covariance-centred update of type (c) voxels
+# ---------------------------------------------------------------------------
+# Lattice sites at >= 0.1 from the interval centres 0.25 / 0.75 of a 2x2 grid on
+# the unit voxel's face; with l = 1e-3 every kernel entry between distinct sites
+# or between a site and a grid point underflows to 0, so the posterior at a grid
+# point sees only the carried prediction at that point: with prior s_f^2 and a
+# pseudo-observation c of noise variance v at the point itself,
+#   var = s_f^2 v / (s_f^2 + v),  mean = mu + s_f^2 / (s_f^2 + v) (c - mu),
+# mu being the mean value of the stacked set (Eq. (3) for one observation).
+_FB_SITES = [0.05, 0.15, 0.35, 0.45, 0.55, 0.65, 0.85, 0.95]
+
+
+def _fb_frame(r, n, z):
+    idx = r.choice(64, n, replace=False)
+    x = np.array([_FB_SITES[i // 8] for i in idx])
+    y = np.array([_FB_SITES[i % 8] for i in idx])
+    return np.stack([x, y, np.asarray(z, float)], 1).astype(np.float32)
+
+
+def test_feedback_update_closed_form_sequence():
+    prm = _params(voxel_size=1.0, grid_side=2, min_pts=3, max_pts=8, length_scale=1e-3, converge_var=0.3)
+    m = O.VoxelMap(prm, feedback=True)
+    r = rng(90)
+    key = int(O.pack_keys(np.array([[0, 0, 0]]))[0])
+    frames = [_fb_frame(r, 5, 0.5 + r.uniform(-0.01, 0.01, 5)),
+              _fb_frame(r, 4, 0.5 + r.uniform(-0.01, 0.01, 4)),
+              _fb_frame(r, 3, 0.5 + r.uniform(-0.01, 0.01, 3)),
+              _fb_frame(r, 11, np.concatenate([0.5 + r.uniform(-0.01, 0.01, 8), [0.56] * 3])),
+              _fb_frame(r, 2, [0.5, 0.5])]
+    sf2 = prm.signal_var
+    grid = np.array([[0.25, 0.25], [0.25, 0.75], [0.75, 0.25], [0.75, 0.75]])
+    c = v = None
+    for k, F in enumerate(frames):
+        u = m.update(F)
+        if k == 4:  # converged at the fourth solve: type (d), skipped
+            assert u["keys"].tolist() == []
+            break
+        assert u["keys"].tolist() == [key] and u["axis"].tolist() == [2]
+        z = F[:, 2].astype(np.float64)
+        if k == 0:  # type (b): no grid point sees a data point
+            mean = np.full(4, z.mean())
+            var = np.full(4, sf2)
+        else:
+            zn = z[: prm.max_pts]
+            mu = (4 * c + zn.sum()) / (4 + len(zn))
+            mean = np.full(4, mu + sf2 / (sf2 + v) * (c - mu))
+            var = np.full(4, sf2 * v / (sf2 + v))
+        out = u["out"][0]
+        assert np.allclose(out[:, :2], grid, atol=0)
+        assert np.allclose(out[:, 2], mean, rtol=0, atol=1e-12), (k, out[:, 2], mean)
+        assert np.allclose(out[:, 3], var, rtol=0, atol=1e-12), (k, out[:, 3], var)
+        st = int(u["status"][0])
+        assert bool(st & O.ST_CAPPED) == (len(F) > prm.max_pts)
+        assert bool(st & O.ST_CONVERGED) == (k == 3), (k, var)
+        c = float(np.float32(mean[0]))
+        v = float(np.float32(var[0]))
+
+
+def test_feedback_variance_never_exceeds_single_pseudo_observation():
+    """Posterior variance with more observations is no larger than with a subset:
+    at a grid point that carries a prediction of variance v, a type (c) re-solve
+    (same value axis, hence the same grid) gives var <= s_f^2 v / (s_f^2 + v) < v."""
+    prm = _params(voxel_size=0.5, grid_side=4, min_pts=3, max_pts=24, length_scale=0.25, converge_var=1e-4)
+    m = O.VoxelMap(prm, feedback=True)
+    r = rng(91)
+    n_checked = 0
+    axes = {}
+    for f in range(5):
+        pts = []
+        for b in range(6):
+            o = np.array([0.5 * (b % 3), 0.5 * (b // 3), 0.0])
+            n = int(r.integers(2, 30))
+            xy = r.uniform(0.02, 0.48, (n, 2))
+            z = 0.2 + 0.3 * xy[:, 0] - 0.2 * xy[:, 1] + r.normal(0, 0.01, n)
+            pts.append(o + np.stack([xy[:, 0], xy[:, 1], z], 1))
+        F = np.concatenate(pts).astype(np.float32)
+        prev = {k: v.copy() for k, v in m.pred.items()}
+        pool = {k: len(v) for k, v in m.points.items()}
+        u = m.update(F)
+        for i, key in enumerate(u["keys"].tolist()):
+            st = int(u["status"][i])
+            if key in prev:
+                assert len(m.points[key]) == pool[key]  # the pool stops growing once in the map
+                if st & O.ST_SOLVED and axes.get(key) == int(u["axis"][i]):
+                    vq = np.maximum(prev[key][:, 3].astype(np.float64), O.PRED_NOISE_FLOOR * prm.signal_var)
+                    bound = prm.signal_var * vq / (prm.signal_var + vq)
+                    assert (u["out"][i][:, 3] <= bound * (1 + 1e-9) + 1e-12).all(), (f, key)
+                    n_checked += 1
+            if st & O.ST_SOLVED:
+                axes[key] = int(u["axis"][i])
+    assert n_checked >= 10
+
+
+def test_feedback_state_machine():
+    """Types (a)-(d) with feedback: points pool until tau, the first solve puts the
+    voxel in the map, a later frame re-solves on the m carried rows plus the new
+    points (capped), converged voxels are skipped."""
+    prm = _params(min_pts=10, max_pts=12, grid_side=3, converge_var=1e-6)
+    m = O.VoxelMap(prm, feedback=True)
+    r = rng(92)
+
+    def pts(n, base):
+        return np.stack([base[0] + r.uniform(0.01, 0.49, n), base[1] + r.uniform(0.01, 0.49, n),
+                         base[2] + 0.25 + r.normal(0, 0.005, n)], 1).astype(np.float32)
+    A, B = (0.0, 0.0, 0.0), (1.0, 0.0, 0.0)
+    kA = int(O.pack_keys(np.array([[0, 0, 0]]))[0])
+    kB = int(O.pack_keys(np.array([[2, 0, 0]]))[0])
+    u1 = m.update(np.concatenate([pts(6, A), pts(12, B)]))   # A: (a); B: (b) -> in the map
+    assert u1["keys"].tolist() == [kB] and kB in m.pred and kA not in m.pred
+    u2 = m.update(np.concatenate([pts(5, A), pts(3, B)]))    # A: (b) on 11 pooled points; B: (c) on 9 + 3
+    assert u2["keys"].tolist() == [kA, kB]
+    assert len(m.points[kA]) == 11 and len(m.points[kB]) == 12
+    assert not u2["status"][1] & O.ST_CAPPED
+    u3 = m.update(pts(20, B))                                 # (c) with 20 new points: 12 taken, CAPPED
+    assert u3["keys"].tolist() == [kB] and u3["status"][0] & O.ST_CAPPED
+    assert len(m.points[kB]) == 12
+    m.converged[kB] = True
+    assert m.update(pts(4, B))["keys"].tolist() == []         # (d): skipped
+    # the re-solve sees exactly the carried rows and the capped new points
+    X, nz = O.feedback_inputs(m.pred[kA], pts(15, A), prm)
+    assert X.shape == (9 + 12, 3) and np.all(nz[9:] == prm.noise_var)
+
+
+# ---------------------------------------------------------------------------
 # Sec. 3.2: initial 3D Gaussians from the predicted grid
 # ---------------------------------------------------------------------------
 def _grid_rows(gs, h, z, var):
