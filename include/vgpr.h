@@ -217,6 +217,27 @@ VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t
  */
 VGPR_API vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels,
                             vgpr_map** out);
+
+/*
+ * vgpr_map_create_ex - as vgpr_map_create with an update mode.
+ * update_mode 0: the map above (type (c) voxels re-solved on their stored
+ * points). update_mode 1: the covariance-centred update of Sec. 3.3 (Fig. 4).
+ * A voxel's first solve (type (b), on its pooled points) puts it in the map
+ * with its m = grid_side^2 predicted rows (x, y, z, var), kept as float32;
+ * its pool then stops growing. A later frame that touches it (type (c))
+ * re-solves Alg. 1 on the m carried rows, each with its posterior variance
+ * (raised to 1e-6 signal_var) as its noise variance, stacked with the
+ * frame's first max_pts points in that voxel (sensor noise_var); the new
+ * rows replace the carried ones, and the voxel is converged (type (d)) once
+ * their max variance <= converge_var. CAPPED then reports that the frame
+ * brought more than max_pts points to the voxel. Needs grid_side^2 + max_pts
+ * <= 512 and max_voxels * grid_side^2 < 2^31; the map owns an extra
+ * max_voxels * (16 m + 1) bytes and a staging area of about
+ * 48 (m + max_pts) bytes per re-solved voxel of the largest frame so far.
+ * Errors: E_INVALID for another update_mode or those limits.
+ */
+VGPR_API vgpr_status vgpr_map_create_ex(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels,
+                               int update_mode, vgpr_map** out);
 VGPR_API vgpr_status vgpr_map_destroy(vgpr_map* map);
 
 /*

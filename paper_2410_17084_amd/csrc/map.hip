@@ -12,6 +12,14 @@
 // hold >= tau points and are not converged (types (b), (c)) in ascending key
 // order -> solve them from the pool with the per-voxel solver -> mark those
 // whose max variance <= eta as converged (type (d)).
+//
+// Feedback maps (update mode 1, the covariance-centred update of Sec. 3.3 and
+// Fig. 4) also keep each solved voxel's predicted grid (m float4 rows). Once a
+// voxel holds a prediction its pool stops growing: a frame that touches it
+// stacks the m carried rows (noise variance = their posterior variance,
+// raised to kPredNoiseFloor s_f^2) with the frame's first max_pts new points
+// (sensor noise) in a staging area of m + max_pts slots per voxel, re-solves
+// Alg. 1 on that set, and the new rows replace the carried ones.
 #include "scan.cuh"
 #include "vgpr_internal.h"
 
@@ -30,10 +38,19 @@ struct vgpr_map {
   unsigned long long* counters = nullptr;  // [0] voxels, [1] new this frame, [2] updates
   size_t bytes = 0;
   void* block = nullptr;
+  int mode = 0;              // 0: re-solve on the stored points; 1: covariance feedback
+  float4* pred = nullptr;    // mode 1: m predicted rows (x, y, z, var) per voxel
+  uint8_t* vpred = nullptr;  // mode 1: the voxel holds a prediction (it is in the map)
+  void* stage = nullptr;     // mode 1: stacked points, noise, per-update records, fit scratch
+  size_t stage_bytes = 0;
 };
 
 namespace vgpr {
 namespace {
+
+// Smallest noise variance, relative to s_f^2, that a carried prediction takes
+// into a re-solve (a posterior variance can round to 0).
+constexpr float kPredNoiseFloor = 1e-6f;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   // splitmix64 finaliser (a published 64-bit mixing function)
@@ -83,6 +100,7 @@ __global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __
   const uint64_t key = keys[v];
   int id = -1;
   int stored = 0;
+  int inmap = 0;
   if (lane == 0) {
     int64_t s = (int64_t)(mix64(key) & (uint64_t)(M.nslots - 1));
     for (int64_t probe = 0; probe < M.nslots; ++probe) {
@@ -102,11 +120,15 @@ __global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __
         M.vstored[id] = 0;
         M.vtotal[id] = 0;
         M.vconv[id] = 0;
+        if (M.vpred) M.vpred[id] = 0;
         break;
       }
       if (prev == key) {
         id = M.slot_id[s];
-        if (id >= 0) stored = M.vstored[id];
+        if (id >= 0) {
+          stored = M.vstored[id];
+          inmap = M.vpred ? M.vpred[id] : 0;
+        }
         break;
       }
       s = (s + 1) & (M.nslots - 1);
@@ -115,6 +137,7 @@ __global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __
   // the record is read and written by lane 0 only; other lanes get it by shuffle
   id = __shfl(id, 0, 64);
   stored = __shfl(stored, 0, 64);
+  inmap = __shfl(inmap, 0, 64);
   if (id < 0) {
     if (lane == 0) {
       flag[v] = 0u;
@@ -123,6 +146,14 @@ __global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __
     return;
   }
   const int c = cnts[v];
+  if (inmap) {  // feedback map, voxel already solved: its new points go to the re-solve, not the pool
+    if (lane == 0) {
+      M.vtotal[id] += c;
+      ids[v] = id;
+      flag[v] = M.vconv[id] ? 0u : 1u;
+    }
+    return;
+  }
   const int take = min(c, cap - stored);
   const int o = offs[v];
   for (int i = lane; i < take; i += 64) {
@@ -176,7 +207,8 @@ __global__ void __launch_bounds__(1024) compact_scatter(vgpr_map M, const uint32
                                                         const int32_t* __restrict__ ids, int64_t n,
                                                         const uint32_t* __restrict__ block_base,
                                                         uint64_t* __restrict__ ukey, int32_t* __restrict__ uoff,
-                                                        int32_t* __restrict__ ucnt, int32_t* __restrict__ uid) {
+                                                        int32_t* __restrict__ ucnt, int32_t* __restrict__ uid,
+                                                        int32_t* __restrict__ ufv) {
   __shared__ uint32_t smem[17];
   const int64_t i = (int64_t)blockIdx.x * kCompactTile + threadIdx.x;
   const uint32_t f = i < n ? flag[i] : 0u;
@@ -189,6 +221,7 @@ __global__ void __launch_bounds__(1024) compact_scatter(vgpr_map M, const uint32
     uoff[slot] = id * M.params.max_pts;
     ucnt[slot] = M.vtotal[id];
     uid[slot] = id;
+    ufv[slot] = (int32_t)i;
   }
 }
 
@@ -196,6 +229,95 @@ __global__ void __launch_bounds__(256) state_kernel(vgpr_map M, const int32_t* _
                                                     const uint8_t* __restrict__ status, int64_t nu) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u < nu && (status[u] & VGPR_ST_CONVERGED)) M.vconv[uid[u]] = 1;
+}
+
+// Feedback maps: one wavefront per re-solved voxel u writes its training set to
+// slots [u * per, u * per + n) of the staging area. A voxel in the map: the m
+// carried rows, then the frame's first max_pts new points; otherwise (first
+// solve): its pooled points. CAPPED is decided here (frame points beyond
+// max_pts, or pooled arrivals beyond max_pts) since the solve sees only the
+// kept points.
+__global__ void __launch_bounds__(256) stack_kernel(vgpr_map M, const float* __restrict__ xyz,
+                                                    const int32_t* __restrict__ foff, const int32_t* __restrict__ fcnt,
+                                                    const int32_t* __restrict__ fperm, const int32_t* __restrict__ uid,
+                                                    const int32_t* __restrict__ ufv, int64_t nu, int m, int per,
+                                                    float* __restrict__ sxyz, float* __restrict__ snoise,
+                                                    int32_t* __restrict__ soff, int32_t* __restrict__ scnt,
+                                                    uint8_t* __restrict__ scap) {
+  const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = lane_id();
+  if (u >= nu) return;
+  const int id = uid[u];
+  const int cap = M.params.max_pts;
+  const float sn = M.params.noise_var;
+  const int64_t base = u * (int64_t)per;
+  int n;
+  bool capped;
+  if (M.vpred[id]) {
+    const float floor_var = kPredNoiseFloor * M.params.signal_var;
+    const float4* rows = M.pred + (size_t)id * m;
+    for (int q = lane; q < m; q += 64) {
+      const float4 r = rows[q];
+      float* d = sxyz + 3 * (base + q);
+      d[0] = r.x;
+      d[1] = r.y;
+      d[2] = r.z;
+      snoise[base + q] = fmaxf(r.w, floor_var);
+    }
+    const int fv = ufv[u];
+    const int c = fcnt[fv];
+    const int take = min(c, cap);
+    const int o = foff[fv];
+    for (int k = lane; k < take; k += 64) {
+      const int src = fperm[o + k];
+      float* d = sxyz + 3 * (base + m + k);
+      d[0] = xyz[3 * (size_t)src + 0];
+      d[1] = xyz[3 * (size_t)src + 1];
+      d[2] = xyz[3 * (size_t)src + 2];
+      snoise[base + m + k] = sn;
+    }
+    n = m + take;
+    capped = c > cap;
+  } else {
+    const int st = M.vstored[id];
+    const float* src = M.pool + (size_t)id * cap * 3;
+    for (int k = lane; k < st; k += 64) {
+      float* d = sxyz + 3 * (base + k);
+      d[0] = src[3 * k + 0];
+      d[1] = src[3 * k + 1];
+      d[2] = src[3 * k + 2];
+      snoise[base + k] = sn;
+    }
+    n = st;
+    capped = M.vtotal[id] > cap;
+  }
+  if (lane == 0) {
+    soff[u] = (int32_t)base;
+    scnt[u] = n;
+    scap[u] = capped ? 1 : 0;
+  }
+}
+
+// Feedback maps: one thread per predicted row; a solved voxel's rows replace
+// its carried prediction; the row-0 thread sets the voxel's flags and adds
+// CAPPED to its status (the SOLVED and CONVERGED bits it reads are not
+// changed by that write).
+__global__ void __launch_bounds__(256) feedback_state_kernel(vgpr_map M, const int32_t* __restrict__ uid,
+                                                             const uint8_t* __restrict__ scap,
+                                                             const float4* __restrict__ out,
+                                                             uint8_t* __restrict__ status, int64_t nu, int m) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nu * m) return;
+  const int64_t u = t / m;
+  const int q = (int)(t - u * m);
+  const int id = uid[u];
+  const uint8_t st = status[u];
+  if (st & VGPR_ST_SOLVED) M.pred[(size_t)id * m + q] = out[t];
+  if (q == 0) {
+    if (st & VGPR_ST_SOLVED) M.vpred[id] = 1;
+    if (st & VGPR_ST_CONVERGED) M.vconv[id] = 1;
+    if (scap[u]) status[u] = st | VGPR_ST_CAPPED;
+  }
 }
 
 __global__ void __launch_bounds__(256) stats_kernel(vgpr_map M, unsigned long long* __restrict__ out) {
@@ -216,13 +338,20 @@ using namespace vgpr;
 
 extern "C" {
 
-vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels, vgpr_map** out) {
+vgpr_status vgpr_map_create_ex(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels, int update_mode,
+                               vgpr_map** out) {
   if (!ctx || !out) return VGPR_E_INVALID;
   *out = nullptr;
   vgpr_status st = check_params(ctx, params);
   if (st != VGPR_OK) return st;
+  if (update_mode != 0 && update_mode != 1) return fail(ctx, VGPR_E_INVALID, "update_mode must be 0 or 1");
+  const int64_t m = (int64_t)params->grid_side * params->grid_side;
   if (max_voxels < 1 || max_voxels * (int64_t)params->max_pts >= (int64_t(1) << 31))
     return fail(ctx, VGPR_E_INVALID, "max_voxels * max_pts must be in [1, 2^31)");
+  if (update_mode == 1 && m + params->max_pts > kMaxPtsLimit)
+    return fail(ctx, VGPR_E_INVALID, "update_mode 1 needs grid_side^2 + max_pts <= 512");
+  if (update_mode == 1 && max_voxels * m >= (int64_t(1) << 31))
+    return fail(ctx, VGPR_E_INVALID, "max_voxels * grid_side^2 must be below 2^31");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
   vgpr_map* M = new (std::nothrow) vgpr_map();
   if (!M) return VGPR_E_NOMEM;
@@ -244,6 +373,8 @@ vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t ma
   const size_t o_vk = sub(sizeof(uint64_t) * max_voxels), o_vs = sub(sizeof(int32_t) * max_voxels);
   const size_t o_vt = sub(sizeof(int32_t) * max_voxels), o_vc = sub(max_voxels);
   const size_t o_pool = sub(sizeof(float) * 3 * cap * max_voxels), o_ctr = sub(sizeof(unsigned long long) * 8);
+  const size_t o_pred = update_mode == 1 ? sub(sizeof(float4) * (size_t)m * max_voxels) : 0;
+  const size_t o_vp = update_mode == 1 ? sub(max_voxels) : 0;
   const size_t total = (off + 255) & ~size_t(255);
   void* blk = nullptr;
   st = alloc_owned(ctx, &blk, total);
@@ -262,6 +393,11 @@ vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t ma
   M->vconv = reinterpret_cast<uint8_t*>(b + o_vc);
   M->pool = reinterpret_cast<float*>(b + o_pool);
   M->counters = reinterpret_cast<unsigned long long*>(b + o_ctr);
+  M->mode = update_mode;
+  if (update_mode == 1) {
+    M->pred = reinterpret_cast<float4*>(b + o_pred);
+    M->vpred = reinterpret_cast<uint8_t*>(b + o_vp);
+  }
   if (hipMemsetAsync(M->slot_key, 0xFF, sizeof(uint64_t) * ns, ctx->stream) != hipSuccess ||
       hipMemsetAsync(M->counters, 0, sizeof(unsigned long long) * 8, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -274,11 +410,16 @@ vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t ma
   return VGPR_OK;
 }
 
+vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels, vgpr_map** out) {
+  return vgpr_map_create_ex(ctx, params, max_voxels, 0, out);
+}
+
 vgpr_status vgpr_map_destroy(vgpr_map* M) {
   if (!M) return VGPR_E_INVALID;
   vgpr_ctx* ctx = M->ctx;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
   free_owned(ctx, M->block, M->bytes);
   ctx->live_maps -= 1;
   delete M;
@@ -310,9 +451,11 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   };
   const size_t o_k = sub(8 * n), o_o = sub(4 * n), o_c = sub(4 * n), o_p = sub(4 * n), o_f = sub(4 * n),
                o_id = sub(4 * n), o_bs = sub(4 * nblk + 64), o_uk = sub(8 * n), o_uo = sub(4 * n), o_uc = sub(4 * n),
-               o_ui = sub(4 * n), o_tot = sub(64);
+               o_ui = sub(4 * n), o_fv = sub(4 * n), o_tot = sub(64);
   head = (head + 255) & ~size_t(255);
-  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_work_bytes(ctx, n, M->max_voxels * (int64_t)p.max_pts, &p) + (1 << 20));
+  // update mode 1 solves from the map's own staging area (sized once the update count is known)
+  const size_t fit_bytes = M->mode == 1 ? 0 : fit_work_bytes(ctx, n, M->max_voxels * (int64_t)p.max_pts, &p);
+  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_bytes + (1 << 20));
   if (st != VGPR_OK) return st;
   char* w = static_cast<char*>(ctx->work.ptr);
   uint64_t* fkeys = reinterpret_cast<uint64_t*>(w + o_k);
@@ -326,6 +469,7 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   int32_t* uoff = reinterpret_cast<int32_t*>(w + o_uo);
   int32_t* ucnt = reinterpret_cast<int32_t*>(w + o_uc);
   int32_t* uid = reinterpret_cast<int32_t*>(w + o_ui);
+  int32_t* ufv = reinterpret_cast<int32_t*>(w + o_fv);
   unsigned long long* dtot = reinterpret_cast<unsigned long long*>(w + o_tot);
 
   int64_t nv = 0;
@@ -354,7 +498,7 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   hipLaunchKernelGGL(compact_reduce, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, flag, nv, bsum);
   hipLaunchKernelGGL(compact_scan, dim3(1), dim3(1024), 0, ctx->stream, bsum, (int)nvb, dtot);
   hipLaunchKernelGGL(compact_scatter, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, *M, flag, ids, nv, bsum, ukey,
-                     uoff, ucnt, uid);
+                     uoff, ucnt, uid, ufv);
   VGPR_HIP(ctx, hipGetLastError());
   VGPR_HIP(ctx, hipMemcpyAsync(hc, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -362,7 +506,49 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   *h_n_upd = nu;
   if (nu == 0) return VGPR_OK;
   const int64_t nout = nu < cap_upd ? nu : cap_upd;
-  if (nout > 0) {
+  if (nout > 0 && M->mode == 1) {
+    VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
+    const int m = p.grid_side * p.grid_side;
+    const int per = m + p.max_pts;
+    const int64_t npts = nout * (int64_t)per;
+    if (npts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_CAPACITY, "too many re-solved voxels in one frame");
+    vgpr_params pf = p;  // the stacked set holds up to m + max_pts points; CAPPED is set by stack_kernel
+    pf.max_pts = per;
+    size_t so = 0;
+    auto take = [&](size_t bytes) {
+      so = (so + 255) & ~size_t(255);
+      size_t r = so;
+      so += bytes;
+      return r;
+    };
+    const size_t s_xyz = take(12 * (size_t)npts), s_nz = take(4 * (size_t)npts), s_off = take(4 * (size_t)nout),
+                 s_cnt = take(4 * (size_t)nout), s_cap = take((size_t)nout), s_fit = take(fit_work_bytes(ctx, nout, npts, &pf));
+    const size_t need = (so + 255) & ~size_t(255);
+    if (need > M->stage_bytes) {
+      VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the previous frame's solve may still read it
+      if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
+      M->stage = nullptr;
+      M->stage_bytes = 0;
+      st = alloc_owned(ctx, &M->stage, need + need / 4);
+      if (st != VGPR_OK) return st;
+      M->stage_bytes = need + need / 4;
+    }
+    char* sb = static_cast<char*>(M->stage);
+    float* sxyz = reinterpret_cast<float*>(sb + s_xyz);
+    float* snz = reinterpret_cast<float*>(sb + s_nz);
+    int32_t* soff = reinterpret_cast<int32_t*>(sb + s_off);
+    int32_t* scnt = reinterpret_cast<int32_t*>(sb + s_cnt);
+    uint8_t* scap = reinterpret_cast<uint8_t*>(sb + s_cap);
+    hipLaunchKernelGGL(stack_kernel, dim3((unsigned)((nout + 3) / 4)), dim3(256), 0, ctx->stream, *M, d_xyz, foff,
+                       fcnt, fperm, uid, ufv, nout, m, per, sxyz, snz, soff, scnt, scap);
+    VGPR_HIP(ctx, hipGetLastError());
+    FitArgs a{sxyz, npts, ukey, soff, scnt, nullptr, snz, nout, d_out, d_axis, d_status};
+    st = fit_predict_impl(ctx, a, &pf, 0, sb + s_fit);
+    if (st != VGPR_OK) return st;
+    hipLaunchKernelGGL(feedback_state_kernel, dim3((unsigned)((nout * m + 255) / 256)), dim3(256), 0, ctx->stream,
+                       *M, uid, scap, reinterpret_cast<const float4*>(d_out), d_status, nout, m);
+    VGPR_HIP(ctx, hipGetLastError());
+  } else if (nout > 0) {
     VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
     FitArgs a{M->pool, M->max_voxels * (int64_t)p.max_pts, ukey, uoff, ucnt, nullptr, nullptr, nout, d_out, d_axis,
               d_status};

@@ -21,7 +21,7 @@ PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
 # every entry point include/vgpr.h declares
 SYMBOLS = [
     "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
-    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create",
+    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create", "vgpr_map_create_ex",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
     "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
     "vgpr_gauss_init",
@@ -101,6 +101,7 @@ def load():
                                     P(i64)]),
         "vgpr_fit_predict": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
         "vgpr_map_create": (C.c_int, [vp, P(Params), i64, P(vp)]),
+        "vgpr_map_create_ex": (C.c_int, [vp, P(Params), i64, C.c_int, P(vp)]),
         "vgpr_map_destroy": (C.c_int, [vp]),
         "vgpr_map_update": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, P(i64)]),
         "vgpr_map_stats": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
@@ -312,13 +313,16 @@ class Graph:
 
 
 class Map:
-    """A device-resident voxel map (vgpr_map) bound to a Context."""
+    """A device-resident voxel map (vgpr_map) bound to a Context; feedback=True
+    selects update mode 1 (the covariance-centred update of type (c) voxels)."""
 
-    def __init__(self, ctx: Context, params: Params, max_voxels: int):
+    def __init__(self, ctx: Context, params: Params, max_voxels: int, feedback: bool = False):
         self.ctx = ctx
         self.params = params
+        self.feedback = bool(feedback)
         h = C.c_void_p()
-        ctx._check(ctx.lib.vgpr_map_create(ctx.h, C.byref(params), int(max_voxels), C.byref(h)), "vgpr_map_create")
+        ctx._check(ctx.lib.vgpr_map_create_ex(ctx.h, C.byref(params), int(max_voxels), int(self.feedback),
+                                              C.byref(h)), "vgpr_map_create_ex")
         self.h = h
         ctx._maps.add(self)
 

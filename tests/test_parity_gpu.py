@@ -352,6 +352,116 @@ def test_map_update_matches_oracle_state_machine(env):
         assert st["points"] == sum(len(v) for v in om.points.values())
 
 
+def _compare_map_frame(o_ref, keys, out, axis, status, sf2, eta):
+    """One frame of map updates: keys exact, SOLVED / CAPPED / BELOW_TAU equal,
+    CONVERGED equal unless the oracle's max variance is within tolerance of eta,
+    rows within the fit tolerances where both took the same value axis."""
+    assert np.array_equal(parity.as_u64(keys), o_ref["keys"])
+    o = out.cpu().numpy().astype(np.float64)
+    ax = axis.cpu().numpy()
+    stt = status.cpu().numpy()
+    n_cmp = 0
+    for i in range(len(o_ref["keys"])):
+        for bit in (O.ST_SOLVED, O.ST_CAPPED, O.ST_BELOW_TAU):
+            assert bool(stt[i] & bit) == bool(o_ref["status"][i] & bit), (i, stt[i], o_ref["status"][i])
+        if not o_ref["status"][i] & O.ST_SOLVED:
+            continue
+        a = o_ref["axis"][i]
+        if ax[i] != a:
+            assert (stt[i] & O.ST_AXIS_TIE) or (o_ref["status"][i] & O.ST_AXIS_TIE), i
+            continue
+        u, wv = O.PARAM_AXES[a]
+        assert np.array_equal(o[i][:, u].astype(np.float32), o_ref["out"][i][:, u].astype(np.float32))
+        assert np.array_equal(o[i][:, wv].astype(np.float32), o_ref["out"][i][:, wv].astype(np.float32))
+        assert np.abs(o[i][:, a] - o_ref["out"][i][:, a]).max() <= parity.MEAN_TOL, i
+        assert np.abs(o[i][:, 3] - o_ref["out"][i][:, 3]).max() <= parity.VAR_TOL_REL * sf2, i
+        mv = o_ref["out"][i][:, 3].max()
+        if abs(mv - eta) > parity.VAR_TOL_REL * sf2:
+            assert bool(stt[i] & O.ST_CONVERGED) == bool(mv <= eta), (i, mv)
+        n_cmp += 1
+    return o, stt, n_cmp
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_map_feedback_matches_oracle(env, prec):
+    """Update mode 1 (covariance-centred update of type (c) voxels): each frame is
+    compared with the oracle's feedback map on the same carried state (after a
+    frame the oracle takes the GPU's float32 rows and converged flags, so every
+    re-solve of the next frame starts from identical inputs)."""
+    torch, vgpr, ctx = env
+    w = dict(configs.params_for("paper_stream"), max_pts=48, converge_var=2e-4)
+    prm = parity.oracle_params(w)
+    p = parity.gpu_params(vgpr, w, precision=vgpr.PREC_FP32 if prec == "fp32" else vgpr.PREC_FP64)
+    om = O.VoxelMap(prm, feedback=True)
+    gm = vgpr.Map(ctx, p, max_voxels=200000, feedback=True)
+    n_resolved = n_cmp_total = 0
+    for k in range(5):
+        xyz = synth.spin_scan(synth.frame_seed(5, k), n_beams=32, n_az=1024, position=(0.05 * k, 0.02 * k),
+                              yaw=0.05 * k)
+        say("feedback map", prec, "frame", k, len(xyz))
+        before = set(om.pred)
+        keys, out, axis, status = gm.update(dev(torch, xyz))
+        ref = om.update(xyz)
+        o, stt, n_cmp = _compare_map_frame(ref, keys, out, axis, status, prm.signal_var, prm.converge_var)
+        n_cmp_total += n_cmp
+        for i, key in enumerate(ref["keys"].tolist()):
+            n_resolved += key in before
+            if stt[i] & O.ST_SOLVED:
+                om.pred[key] = o[i].astype(np.float32)
+            om.converged[key] = bool(stt[i] & O.ST_CONVERGED)
+        st = gm.stats()
+        assert st["voxels"] == len(om.points)
+        assert st["points"] == sum(len(v) for v in om.points.values())
+        assert st["converged"] == sum(om.converged.values())
+    say("feedback map", prec, "compared", n_cmp_total, "type (c) re-solves", n_resolved)
+    assert n_resolved >= 200
+
+
+def test_map_feedback_closed_form_frames(env):
+    """The l -> 0 frames of the oracle's closed-form pin through the GPU map, compared
+    with the oracle without any re-synchronisation: four solves, variance 1, 1/2,
+    1/3, 1/4 (converged), CAPPED on the fourth frame, then skipped."""
+    torch, vgpr, ctx = env
+    w = dict(voxel_size=1.0, grid_side=2, min_pts=3, max_pts=8, signal_var=1.0, length_scale=1e-3,
+             noise_var=1e-3, converge_var=0.3)
+    prm = parity.oracle_params(w)
+    r = rng(90)
+    sites = [0.05, 0.15, 0.35, 0.45, 0.55, 0.65, 0.85, 0.95]
+
+    def frame(n, z):
+        idx = r.choice(64, n, replace=False)
+        return np.stack([[sites[i // 8] for i in idx], [sites[i % 8] for i in idx], z], 1).astype(np.float32)
+    frames = [frame(5, 0.5 + r.uniform(-0.01, 0.01, 5)), frame(4, 0.5 + r.uniform(-0.01, 0.01, 4)),
+              frame(3, 0.5 + r.uniform(-0.01, 0.01, 3)),
+              frame(11, np.concatenate([0.5 + r.uniform(-0.01, 0.01, 8), [0.56] * 3])), frame(2, [0.5, 0.5])]
+    for prec in (vgpr.PREC_FP32, vgpr.PREC_FP64):
+        om = O.VoxelMap(prm, feedback=True)
+        gm = vgpr.Map(ctx, parity.gpu_params(vgpr, w, precision=prec), max_voxels=16, feedback=True)
+        for k, F in enumerate(frames):
+            say("feedback closed form", prec, k)
+            keys, out, axis, status = gm.update(dev(torch, F))
+            ref = om.update(F)
+            _, stt, _ = _compare_map_frame(ref, keys, out, axis, status, 1.0, 0.3)
+            if k < 4:
+                assert abs(out.cpu().numpy()[0, :, 3].max() - 1.0 / (k + 1)) <= 1e-6
+        gm.close()
+
+
+def test_map_feedback_argument_errors(env):
+    torch, vgpr, ctx = env
+    p = parity.gpu_params(vgpr, configs.params_for("paper_stream"))
+    say("feedback map argument errors")
+    with pytest.raises(vgpr.VgprError) as ei:
+        h = vgpr.C.c_void_p()
+        ctx._check(ctx.lib.vgpr_map_create_ex(ctx.h, vgpr.C.byref(p), 100, 2, vgpr.C.byref(h)), "create_ex")
+    assert ei.value.status == vgpr.E_INVALID
+    big = parity.gpu_params(vgpr, configs.params_for("paper_stream"), max_pts=512)  # 81 + 512 > 512
+    with pytest.raises(vgpr.VgprError) as ei:
+        vgpr.Map(ctx, big, max_voxels=100, feedback=True)
+    assert ei.value.status == vgpr.E_INVALID
+    vgpr.Map(ctx, big, max_voxels=100).close()  # mode 0 accepts it
+
+
 def test_map_capacity_rejects_frame(env):
     torch, vgpr, ctx = env
     p = parity.gpu_params(vgpr, configs.params_for("paper_stream"))
