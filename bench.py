@@ -454,6 +454,17 @@ def serve_leg(args, vgpr) -> dict:
         backlog[f"workers{workers}"] = {k: sb[k] for k in ("frames", "failed", "solves", "solves_per_s", "wall_s",
                                                            "max_inflight")}
     backlog["speedup"] = backlog["workers8"]["solves_per_s"] / backlog["workers1"]["solves_per_s"]
+    # the same backlog through maps with the covariance-centred update of type (c)
+    # voxels (every re-solve of a voxel in the map stacks its 81 carried rows)
+    be = serve.GpuBackend(p, frames, max_voxels=250000, feedback=True)
+    be.warmup()
+    sb = serve.serve(be, sizes, rate_hz=10.0, duration_s=1.0, workers=8, budget_bytes=8 << 30,
+                     m=p.grid_side ** 2, realtime=False).summary()
+    conv = sum(mp.stats()["converged"] for mp in be.maps)
+    be.close()
+    backlog["feedback_workers8"] = {k: sb[k] for k in ("frames", "failed", "solves", "solves_per_s", "wall_s",
+                                                       "max_inflight")}
+    backlog["feedback_workers8"]["converged_voxels"] = int(conv)
     out["backlog"] = backlog
     return out
 

@@ -135,7 +135,8 @@ VGPR_API vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget
 /* Fails with VGPR_E_INVALID (and frees nothing) while maps created on ctx are alive. */
 VGPR_API vgpr_status vgpr_destroy(vgpr_ctx* ctx);
 VGPR_API vgpr_status vgpr_set_stream(vgpr_ctx* ctx, void* hip_stream);
-/* Message of the last failed call on this context (static until the next call). */
+/* Message of the last failed call on this context (static until the next call);
+ * with ctx = NULL, why the calling thread's last vgpr_create failed. */
 VGPR_API const char* vgpr_last_error(const vgpr_ctx* ctx);
 /* Scratch bytes the context currently holds on the device. */
 VGPR_API size_t vgpr_workspace_bytes(const vgpr_ctx* ctx);

@@ -163,23 +163,32 @@ const char* vgpr_status_str(vgpr_status s) {
   return "VGPR_E_UNKNOWN";
 }
 
+// Why the calling thread's last vgpr_create failed (no context exists to hold it).
+static thread_local std::string create_error;
+
+static vgpr_status create_fail(vgpr_status st, const char* what, hipError_t e) {
+  create_error = std::string(what) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+  return st;
+}
+
 vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget_bytes, vgpr_ctx** out) {
-  if (!out) return VGPR_E_INVALID;
+  if (!out) return create_fail(VGPR_E_INVALID, "out is NULL", hipSuccess);
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VGPR_E_DEVICE;
-  if (hipSetDevice(device) != hipSuccess) return VGPR_E_DEVICE;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return create_fail(VGPR_E_DEVICE, "hipGetDeviceCount", e);
+  if (device < 0 || device >= n) return create_fail(VGPR_E_DEVICE, "device index out of range", hipSuccess);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return create_fail(VGPR_E_DEVICE, "hipSetDevice", e);
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return create_fail(VGPR_E_DEVICE, "hipDeviceGetAttribute(multiprocessor count)", e);
   vgpr_ctx* c = new (std::nothrow) vgpr_ctx();
-  if (!c) return VGPR_E_NOMEM;
+  if (!c) return create_fail(VGPR_E_NOMEM, "out of host memory", hipSuccess);
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = hbm_budget_bytes;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    delete c;
-    return VGPR_E_DEVICE;
-  }
-  c->cu_count = prop.multiProcessorCount;
+  c->cu_count = cus;
   *out = c;
   return VGPR_OK;
 }
@@ -216,7 +225,7 @@ vgpr_status vgpr_set_stream(vgpr_ctx* ctx, void* hip_stream) {
   return VGPR_OK;
 }
 
-const char* vgpr_last_error(const vgpr_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+const char* vgpr_last_error(const vgpr_ctx* ctx) { return ctx ? ctx->last_error.c_str() : create_error.c_str(); }
 
 size_t vgpr_workspace_bytes(const vgpr_ctx* ctx) { return ctx ? ctx->held : 0; }
 

@@ -84,9 +84,11 @@ class Backend:
 
 
 class GpuBackend(Backend):
-    """Per-stream context, HIP stream and device map; frames resident in HBM."""
+    """Per-stream context, HIP stream and device map; frames resident in HBM.
+    feedback=True gives every stream a map with the covariance-centred update of
+    type (c) voxels (update mode 1)."""
 
-    def __init__(self, params, frames_by_stream, max_voxels: int, device: int = 0):
+    def __init__(self, params, frames_by_stream, max_voxels: int, device: int = 0, feedback: bool = False):
         import torch
 
         from . import vgpr
@@ -104,7 +106,7 @@ class GpuBackend(Backend):
             ctx = vgpr.Context(device, stream=st)
             self.streams.append(st)
             self.ctxs.append(ctx)
-            self.maps.append(vgpr.Map(ctx, params, max_voxels))
+            self.maps.append(vgpr.Map(ctx, params, max_voxels, feedback=feedback))
             dev = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(f"cuda:{device}") for f in frames]
             self.frames.append(dev)
             cap = max(len(f) for f in frames)

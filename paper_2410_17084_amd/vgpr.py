@@ -86,6 +86,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    # PyTorch ships its own HIP runtime under the same soname as the system's.
+    # Importing it first makes libvgpr.so bind to that runtime, the one that owns
+    # the tensors and streams passed in; loaded the other way round, the process
+    # would hold two HIP runtimes and the second to initialise sees no device.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
     P = C.POINTER
@@ -157,7 +162,8 @@ class Context:
         h = C.c_void_p()
         st = self.lib.vgpr_create(device, C.c_void_p(self.stream.cuda_stream), hbm_budget, C.byref(h))
         if st != OK:
-            raise VgprError(st, f"vgpr_create failed: {self.lib.vgpr_status_str(st).decode()}")
+            why = (self.lib.vgpr_last_error(None) or b"").decode()
+            raise VgprError(st, f"vgpr_create failed: {self.lib.vgpr_status_str(st).decode()} ({why})")
         self.h = h
         self._maps = weakref.WeakSet()
         self._graphs = weakref.WeakSet()

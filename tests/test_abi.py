@@ -66,3 +66,20 @@ def test_null_arguments_rejected_on_host():
     p = vgpr.default_params()
     assert lib.vgpr_voxelize(None, None, 0, None, 1, C.byref(p), None, None, None, None, 0, C.byref(n), None,
                              None) == vgpr.E_INVALID
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Loaded first in a fresh process, libvgpr.so must still share PyTorch's HIP
+    runtime (one libamdhip64 mapped), or torch's tensors and streams would belong
+    to another runtime than the library's."""
+    import subprocess
+    import sys
+    code = ("from paper_2410_17084_amd import vgpr\n"
+            "vgpr.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"

@@ -22,21 +22,22 @@ def _frames(n_frames):
     return frames
 
 
-def _backend(vgpr, frames):
+def _backend(vgpr, frames, feedback=False):
     w = configs.params_for("paper_stream")
     p = parity.gpu_params(vgpr, w)
-    be = serve.GpuBackend(p, frames, max_voxels=200000)
+    be = serve.GpuBackend(p, frames, max_voxels=200000, feedback=feedback)
     be.keep_results = True
     be.warmup()
     return be, p
 
 
-def test_each_stream_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("feedback", [False, True])
+def test_each_stream_same_alone_and_in_the_mix(feedback):
     from paper_2410_17084_amd import vgpr
     frames = _frames(4)
     sizes = [[len(f) for f in fr] for fr in frames]
-    print("[case] serving isolation", sizes, flush=True)
-    be_mix, p = _backend(vgpr, frames)
+    print("[case] serving isolation", "feedback" if feedback else "stored points", sizes, flush=True)
+    be_mix, p = _backend(vgpr, frames, feedback)
     # backlog: every frame queued at t = 0, so frames of different streams overlap on the device
     st = serve.serve(be_mix, sizes, rate_hz=4.0, duration_s=1.0, workers=4, budget_bytes=1 << 34,
                      m=p.grid_side ** 2, realtime=False)
@@ -46,7 +47,7 @@ def test_each_stream_same_alone_and_in_the_mix():
     mix = dict(be_mix.results)
     be_mix.close()
     for j in range(len(STREAMS)):
-        be_one, _ = _backend(vgpr, frames)
+        be_one, _ = _backend(vgpr, frames, feedback)
         serve.serve(be_one, sizes, rate_hz=4.0, duration_s=1.0, workers=1, budget_bytes=1 << 34,
                     m=p.grid_side ** 2, streams=[j], realtime=False)
         for k in range(4):
