@@ -591,3 +591,57 @@ def gauss_init(out: np.ndarray, status: np.ndarray, grid_side: int, n_r: int, va
                 phi = Q.T @ np.diag(w) @ Q / sw
                 res[v, bi * n_s + bj] = [p[0], p[1], p[2], sw, phi[0, 0], phi[1, 1], phi[2, 2], 0.0]
     return res
+
+
+def gaussian_mean_scale(gauss: np.ndarray, scale_mode: int) -> np.ndarray:
+    """S-bar_k of Eq. (9): the mean of Gaussian k's three scale values. Rows are
+    in the layout gauss_init returns (p_x, p_y, p_z, sum w, S_x, S_y, S_z, 0).
+    scale_mode 0 averages S as stored; scale_mode 1 averages their square roots
+    (S holding variances, as the initial Gaussians of Sec. 3.2 do)."""
+    G = np.asarray(gauss, dtype=np.float32).astype(np.float64).reshape(-1, 8)
+    S = G[:, 4:7]
+    if scale_mode == 1:
+        with np.errstate(invalid="ignore"):
+            S = np.sqrt(S)
+    elif scale_mode != 0:
+        raise ValueError("scale_mode must be 0 or 1")
+    return S.mean(axis=1)
+
+
+def structure_loss(pts: np.ndarray, gauss: np.ndarray, scale_mode: int = 0, chunk: int = 2048) -> dict:
+    """Structure similarity loss L_p of Eq. (9) (Sec. 3.3).
+
+    For every scan point P_j: value_j = min over Gaussians k of
+    (|P_j - p_k|_2 - S-bar_k), and the k attaining it (the lowest k among equal
+    values); L_p is the mean of value_j over the frame's points. Readings: the
+    sum runs over the n points (Eq. (9) writes j = 0..n against 1/n);
+    non-finite points are left out of the mean (value NaN, index -1); a Gaussian
+    whose centre or S-bar is not finite (an unsolved voxel's NaN row) is not a
+    candidate. With no candidate at all every finite point gets +inf and index
+    -1, and L_p is +inf; with no finite point L_p is NaN.
+
+    Returns {"value": (n,), "arg": (n,), "loss": float, "n_valid": int}.
+    """
+    P = np.asarray(pts, dtype=np.float32).astype(np.float64).reshape(-1, 3)
+    G = np.asarray(gauss, dtype=np.float32).astype(np.float64).reshape(-1, 8)
+    sbar = gaussian_mean_scale(G, scale_mode)
+    cand = np.flatnonzero(np.isfinite(G[:, :3]).all(axis=1) & np.isfinite(sbar))
+    n = len(P)
+    value = np.full(n, np.nan)
+    arg = np.full(n, -1, dtype=np.int64)
+    fin = np.isfinite(P).all(axis=1)
+    idx = np.flatnonzero(fin)
+    if len(cand) == 0:
+        value[idx] = np.inf
+    else:
+        C = G[cand, :3]
+        s = sbar[cand]
+        for a in range(0, len(idx), chunk):
+            rows = idx[a:a + chunk]
+            D = np.sqrt(((P[rows, None, :] - C[None, :, :]) ** 2).sum(axis=2)) - s[None, :]
+            j = np.argmin(D, axis=1)  # first minimum: candidates are in ascending k
+            value[rows] = D[np.arange(len(rows)), j]
+            arg[rows] = cand[j]
+    n_valid = int(fin.sum())
+    loss = float(value[idx].mean()) if n_valid else float("nan")
+    return {"value": value, "arg": arg, "loss": loss, "n_valid": n_valid}

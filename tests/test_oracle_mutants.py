@@ -357,3 +357,99 @@ def test_feedback_pins_catch_input_mutant(monkeypatch, name, mutant):
 def test_feedback_pins_catch_growing_pool(monkeypatch):
     monkeypatch.setattr(O.VoxelMap, "update", _fb_pool_grows)
     assert _fb_caught()
+
+
+# ---------------------------------------------------------------------------
+# Eq. (9) structure similarity loss
+# ---------------------------------------------------------------------------
+_orig_sloss = O.structure_loss
+_orig_mean_scale = O.gaussian_mean_scale
+
+
+def _sloss_variant(P, G, scale_mode=0, squared=False, plus=False, nearest_first=False):
+    P = np.asarray(P, np.float32).astype(np.float64).reshape(-1, 3)
+    G = np.asarray(G, np.float32).astype(np.float64).reshape(-1, 8)
+    s = O.gaussian_mean_scale(G, scale_mode)
+    cand = np.flatnonzero(np.isfinite(G[:, :3]).all(1) & np.isfinite(s))
+    n = len(P)
+    value, arg = np.full(n, np.nan), np.full(n, -1)
+    fin = np.isfinite(P).all(1)
+    for j in np.flatnonzero(fin):
+        if len(cand) == 0:
+            value[j] = np.inf
+            continue
+        d2 = ((P[j] - G[cand, :3]) ** 2).sum(1)
+        d = d2 if squared else np.sqrt(d2)
+        if nearest_first:
+            k = int(np.argmin(d))
+            v = d[k] - s[cand][k]
+        else:
+            vals = d + s[cand] if plus else d - s[cand]
+            k = int(np.argmin(vals))
+            v = vals[k]
+        value[j], arg[j] = v, cand[k]
+    nv = int(fin.sum())
+    return {"value": value, "arg": arg, "loss": float(value[fin].mean()) if nv else float("nan"), "n_valid": nv}
+
+
+def _sloss_squared(P, G, scale_mode=0, chunk=2048):
+    return _sloss_variant(P, G, scale_mode, squared=True)
+
+
+def _sloss_plus(P, G, scale_mode=0, chunk=2048):
+    return _sloss_variant(P, G, scale_mode, plus=True)
+
+
+def _sloss_nearest_first(P, G, scale_mode=0, chunk=2048):
+    return _sloss_variant(P, G, scale_mode, nearest_first=True)
+
+
+def _sloss_sum(P, G, scale_mode=0, chunk=2048):
+    r = _orig_sloss(P, G, scale_mode, chunk)
+    r["loss"] = r["loss"] * max(r["n_valid"], 1)  # sum where the mean belongs
+    return r
+
+
+def _mean_scale_max(G, scale_mode):
+    G = np.asarray(G, np.float32).astype(np.float64).reshape(-1, 8)
+    S = np.sqrt(G[:, 4:7]) if scale_mode == 1 else G[:, 4:7]
+    return S.max(axis=1)  # largest scale instead of the mean
+
+
+def _mean_scale_no_sqrt(G, scale_mode):
+    return _orig_mean_scale(G, 0)  # variances averaged as if they were scales
+
+
+SLOSS_PINS = [
+    lambda: pins.test_structure_loss_worked_example_exact(),
+    lambda: pins.test_structure_loss_zero_scale_is_nearest_neighbour(),
+    lambda: pins.test_structure_loss_minimises_the_difference_not_the_distance(),
+    lambda: pins.test_structure_loss_scale_modes_and_invariances(),
+    lambda: pins.test_structure_loss_invalid_rows_points_and_empty_map(),
+]
+
+
+def _sloss_caught():
+    for t in SLOSS_PINS:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError):
+            return True
+    return False
+
+
+def test_structure_loss_pins_green_on_unmodified_oracle():
+    assert not _sloss_caught()
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("squared distance", "structure_loss", _sloss_squared),
+    ("scale added", "structure_loss", _sloss_plus),
+    ("nearest centre first, then its scale", "structure_loss", _sloss_nearest_first),
+    ("sum over points", "structure_loss", _sloss_sum),
+    ("largest scale instead of the mean", "gaussian_mean_scale", _mean_scale_max),
+    ("variances averaged without the square root", "gaussian_mean_scale", _mean_scale_no_sqrt),
+])
+def test_structure_loss_pins_catch_mutant(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(O, target, mutant)
+    assert _sloss_caught(), f"no pin caught the mutant: {name}"

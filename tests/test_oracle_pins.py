@@ -794,3 +794,90 @@ def test_rotated_frame_orthonormal_and_continuous():
         e1b, e2b, vb = O.rotated_frame(O.local_frame(P + 1e-9 * r0.normal(size=P.shape)))
         if np.argmin(np.abs(v)) == np.argmin(np.abs(vb)):
             assert np.abs(np.stack([e1b, e2b, vb]) - M).max() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Eq. (9): structure similarity loss L_p
+# ---------------------------------------------------------------------------
+def _gauss_rows(centres, scales):
+    G = np.zeros((len(centres), 8), np.float32)
+    G[:, :3] = centres
+    G[:, 4:7] = scales
+    return G
+
+
+def test_structure_loss_worked_example_exact():
+    """Hand-computed: 3-4-5 and 5-12-13 distances with rational scale means."""
+    G = _gauss_rows([[0, 0, 0], [6, 8, 0], [0, 0, 13]],
+                    [[0.5, 0.5, 0.5], [1.0, 2.0, 3.0], [0.25, 0.25, 0.25]])
+    P = np.array([[3, 4, 0], [0, 5, 1], [6, 8, 0.5]], np.float32)
+    # point 0: |.|=5 -> 4.5; |(3,4,0)-(6,8,0)|=5 -> 3; to (0,0,13): sqrt(9+16+169) -> larger
+    # point 1: to (0,0,0): sqrt(26) - 0.5; to (6,8,0): sqrt(36+9+1) - 2; to (0,0,13): 13 - 0.25
+    # point 2: to (6,8,0): 0.5 - 2 = -1.5
+    r = O.structure_loss(P, G)
+    v1 = [math.sqrt(26) - 0.5, math.sqrt(46) - 2, 13 - 0.25]
+    assert r["arg"].tolist() == [1, int(np.argmin(v1)), 1]
+    assert r["value"][0] == pytest.approx(3.0, abs=1e-12)
+    assert r["value"][1] == pytest.approx(min(v1), abs=1e-12)
+    assert r["value"][2] == pytest.approx(-1.5, abs=1e-12)
+    assert r["loss"] == pytest.approx((3.0 + min(v1) - 1.5) / 3, abs=1e-12)
+    assert r["n_valid"] == 3
+
+
+def test_structure_loss_zero_scale_is_nearest_neighbour():
+    """S-bar = 0 reduces Eq. (9) to the nearest-neighbour distance (scipy's k-d tree);
+    a common S-bar = c shifts every value by -c with the same nearest index."""
+    import scipy.spatial
+    r = rng(70)
+    C = r.uniform(-5, 5, (400, 3)).astype(np.float32)
+    P = r.uniform(-6, 6, (300, 3)).astype(np.float32)
+    d, k = scipy.spatial.cKDTree(C.astype(np.float64)).query(P.astype(np.float64))
+    r0 = O.structure_loss(P, _gauss_rows(C, np.zeros((400, 3))))
+    assert np.allclose(r0["value"], d, rtol=0, atol=1e-12)
+    assert np.array_equal(r0["arg"], k)
+    rc = O.structure_loss(P, _gauss_rows(C, np.full((400, 3), 0.75)))
+    assert np.allclose(rc["value"], d - 0.75, rtol=0, atol=1e-12)
+    assert np.array_equal(rc["arg"], k)
+    assert rc["loss"] == pytest.approx(d.mean() - 0.75, abs=1e-12)
+
+
+def test_structure_loss_minimises_the_difference_not_the_distance():
+    """A farther Gaussian with a larger scale wins: the minimum is over
+    |P - p_k| - S-bar_k, not S-bar of the nearest centre."""
+    G = _gauss_rows([[1, 0, 0], [3, 0, 0]], [[0, 0, 0], [2.5, 2.5, 2.5]])
+    r = O.structure_loss(np.array([[0, 0, 0]], np.float32), G)
+    assert r["arg"].tolist() == [1] and r["value"][0] == pytest.approx(0.5, abs=1e-12)
+
+
+def test_structure_loss_scale_modes_and_invariances():
+    G = _gauss_rows([[0, 0, 0]], [[1.0, 4.0, 9.0]])
+    P = np.array([[0, 0, 10]], np.float32)
+    assert O.structure_loss(P, G, scale_mode=0)["value"][0] == pytest.approx(10 - 14 / 3, abs=1e-12)
+    assert O.structure_loss(P, G, scale_mode=1)["value"][0] == pytest.approx(10 - 2.0, abs=1e-12)
+    r = rng(71)
+    C = r.uniform(-2, 2, (60, 3)).astype(np.float32)
+    S = r.uniform(0, 0.3, (60, 3)).astype(np.float32)
+    Q = r.uniform(-3, 3, (50, 3)).astype(np.float32)
+    base = O.structure_loss(Q, _gauss_rows(C, S))
+    # translation by a dyadic offset (exact in float32 at these magnitudes)
+    t = np.array([8.0, -4.0, 2.0], np.float32)
+    moved = O.structure_loss(Q + t, _gauss_rows(C + t, S))
+    assert np.allclose(moved["value"], base["value"], rtol=0, atol=1e-6)
+    # permuting the Gaussians permutes the indices only
+    perm = r.permutation(60)
+    pr = O.structure_loss(Q, _gauss_rows(C[perm], S[perm]))
+    assert np.allclose(pr["value"], base["value"], rtol=0, atol=1e-12)
+    assert np.array_equal(perm[pr["arg"]], base["arg"])
+
+
+def test_structure_loss_invalid_rows_points_and_empty_map():
+    G = _gauss_rows([[0, 0, 0], [1, 0, 0]], [[0.1] * 3, [0.1] * 3])
+    G[0, :] = np.nan                                           # an unsolved voxel's row
+    P = np.array([[0, 0, 0], [np.nan, 0, 0], [2, 0, 0]], np.float32)
+    r = O.structure_loss(P, G)
+    assert r["arg"].tolist() == [1, -1, 1] and np.isnan(r["value"][1])
+    assert r["n_valid"] == 2
+    assert r["loss"] == pytest.approx(((1 - 0.1) + (1 - 0.1)) / 2, abs=1e-7)
+    e = O.structure_loss(P, G[:1])
+    assert np.isinf(e["value"][0]) and e["arg"][0] == -1 and np.isinf(e["loss"])
+    assert np.isnan(O.structure_loss(np.zeros((0, 3), np.float32), G)["loss"])
