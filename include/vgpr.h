@@ -286,6 +286,32 @@ VGPR_API vgpr_status vgpr_gauss_init(vgpr_ctx* ctx, const float* d_out, const ui
                                      int32_t grid_side, int32_t n_r, float var_floor, float* d_gauss);
 
 /*
+ * vgpr_structure_loss - structure similarity loss L_p of Eq. (9) (Sec. 3.3).
+ *
+ * d_pts: n_pts scan points (float32 x, y, z). d_gauss: n_gauss Gaussians of 8
+ * floats in the vgpr_gauss_init layout (p_x, p_y, p_z, *, S_x, S_y, S_z, *),
+ * 16-byte aligned. S-bar_k = mean of S_x, S_y, S_z (scale_mode 0) or of their
+ * square roots (scale_mode 1: S holds variances, as vgpr_gauss_init writes).
+ * A Gaussian whose centre or S-bar is not finite (an unsolved voxel's NaN row)
+ * is not a candidate. For every point: value = min over candidates of
+ * (|P - p_k|_2 - S-bar_k) in float32, index = the k attaining it (the lowest k
+ * among equal values); *h_loss = the mean of the values over the finite
+ * points (accumulated in double, in a fixed order), *h_n_valid their number.
+ * Non-finite points get value NaN and index -1 and are left out; with no
+ * candidate every finite point gets +inf and -1 and the loss is +inf; with no
+ * finite point the loss is NaN. The search is exact on a uniform grid of
+ * cell_size (> 0; a spacing near that of the Gaussians is fastest); the
+ * result does not depend on cell_size. d_value (n_pts floats) and d_arg
+ * (n_pts int32) are caller-owned and nullable. Synchronises the context's
+ * stream. Errors: E_INVALID (sizes, null or misaligned pointers, cell_size,
+ * scale_mode), E_RANGE (a Gaussian's cell index beyond +-(2^20 - 1)),
+ * E_BUDGET.
+ */
+VGPR_API vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, int64_t n_pts, const float* d_gauss,
+                                         int64_t n_gauss, float cell_size, int scale_mode, float* d_value,
+                                         int32_t* d_arg, double* h_loss, int64_t* h_n_valid);
+
+/*
  * Captured form of vgpr_fit_predict (the batching form: every size bucket's
  * persistent launch, the side-stream fork and join, recorded once as a HIP
  * graph and replayed with one launch).

@@ -1,0 +1,402 @@
+// vgpr_structure_loss: the structure similarity loss L_p of Eq. (9) (paper
+// Sec. 3.3). For every scan point P_j the value min_k (|P_j - p_k| - S_k) over
+// the Gaussians k (S_k the mean of Gaussian k's three scales) and the k that
+// attains it (the lowest k among equal values); L_p is their mean over the
+// frame's finite points.
+//
+// Exact search on a uniform grid of cell size h. The Gaussian centres are
+// sorted into cells with the voxelizer (Alg. S1's keys), each cell's range
+// goes into an open-addressing table, and each point visits the cells of
+// growing cubes around its own cell (rings r = 0, 1, ...). Every Gaussian
+// outside the cube of radius r lies at least lb_r (the distance from P_j to the
+// cube's faces) away, so its value is at least lb_r - max_k S_k; once that
+// bound exceeds the best value by a rounding margin no unvisited Gaussian can
+// win. Points still open after kRingMax rings (far from the map) are resolved
+// by a brute-force pass over all Gaussians. Both passes take the minimum of
+// the same float values with the same tie rule, so the result does not depend
+// on h, which only sets the speed.
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "scan.cuh"
+#include "vgpr_internal.h"
+
+namespace vgpr {
+namespace {
+
+constexpr int kRingMax = 3;
+constexpr int kReduceTile = 1024;
+
+__device__ __forceinline__ uint32_t float_order(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float float_unorder(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Value of Gaussian g (centre, mean scale in w) for point (x, y, z); every
+// pass evaluates it through this one function.
+__device__ __forceinline__ float gauss_value(float x, float y, float z, float4 g) {
+  const float dx = x - g.x, dy = y - g.y, dz = z - g.z;
+  return __fsub_rn(__fsqrt_rn(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz))), g.w);
+}
+
+__device__ __forceinline__ void take_min(float v, int k, float* best, int* bk) {
+  if (v < *best || (v == *best && k < *bk)) {
+    *best = v;
+    *bk = k;
+  }
+}
+
+// Centres (NaN for a Gaussian that is not a candidate, so the voxelizer drops
+// it), mean scales, and the largest mean scale among candidates.
+__global__ void __launch_bounds__(256) prepare_kernel(const float4* __restrict__ rows, int64_t ng, int scale_mode,
+                                                      float* __restrict__ cen, float* __restrict__ sb,
+                                                      uint32_t* __restrict__ smax) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t m = 0u;
+  if (k < ng) {
+    const float4 a = rows[2 * k], b = rows[2 * k + 1];
+    float s;
+    if (scale_mode == 1)
+      s = __fdiv_rn(__fadd_rn(__fadd_rn(__fsqrt_rn(b.x), __fsqrt_rn(b.y)), __fsqrt_rn(b.z)), 3.0f);
+    else
+      s = __fdiv_rn(__fadd_rn(__fadd_rn(b.x, b.y), b.z), 3.0f);
+    const bool ok = isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(s);
+    cen[3 * k + 0] = ok ? a.x : __int_as_float(0x7fc00000);
+    cen[3 * k + 1] = a.y;
+    cen[3 * k + 2] = a.z;
+    sb[k] = s;
+    if (ok) m = float_order(s);
+  }
+  // wave max, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+  if (lane_id() == 0 && m) atomicMax(smax, m);
+}
+
+// Gaussians in cell order as (x, y, z, S) with their original index, and the
+// cell table (key -> cell).
+__global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ cen, const float* __restrict__ sb,
+                                                     const int32_t* __restrict__ perm, int64_t nvalid,
+                                                     float4* __restrict__ G, int32_t* __restrict__ gi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvalid) return;
+  const int k = perm[i];
+  G[i] = make_float4(cen[3 * (size_t)k], cen[3 * (size_t)k + 1], cen[3 * (size_t)k + 2], sb[k]);
+  gi[i] = k;
+}
+
+__global__ void __launch_bounds__(256) table_kernel(const uint64_t* __restrict__ ckeys, int64_t nc,
+                                                    uint64_t* __restrict__ tkey, int32_t* __restrict__ tcell,
+                                                    int64_t nslots) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const uint64_t key = ckeys[c];
+  int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
+  for (int64_t probe = 0; probe < nslots; ++probe) {
+    const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tkey[s]),
+                                              (unsigned long long)kKeySentinel, (unsigned long long)key);
+    if (prev == kKeySentinel) {  // cell keys are unique: no two threads insert the same key
+      tcell[s] = (int32_t)c;
+      return;
+    }
+    s = (s + 1) & (nslots - 1);
+  }
+}
+
+__device__ __forceinline__ int lookup(const uint64_t* __restrict__ tkey, const int32_t* __restrict__ tcell,
+                                      int64_t nslots, uint64_t key) {
+  int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
+  for (int64_t probe = 0; probe < nslots; ++probe) {
+    const uint64_t k = tkey[s];
+    if (k == key) return tcell[s];
+    if (k == kKeySentinel) return -1;
+    s = (s + 1) & (nslots - 1);
+  }
+  return -1;
+}
+
+struct Grid {
+  const float4* G;
+  const int32_t* gi;
+  const uint64_t* tkey;
+  const int32_t* tcell;
+  int64_t nslots;
+  const int32_t* coff;
+  const int32_t* ccnt;
+  double inv_h, h;
+  const uint32_t* smax;
+};
+
+__global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pts, int64_t n, Grid g, int has_cand,
+                                                    float* __restrict__ val, int32_t* __restrict__ arg,
+                                                    int32_t* __restrict__ fb, uint32_t* __restrict__ fb_n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    val[i] = __int_as_float(0x7fc00000);
+    arg[i] = -1;
+    return;
+  }
+  if (!has_cand) {
+    val[i] = INFINITY;
+    arg[i] = -1;
+    return;
+  }
+  const double smax = (double)float_unorder(*g.smax);
+  const double kx = floor(__dmul_rn((double)x, g.inv_h));
+  const double ky = floor(__dmul_rn((double)y, g.inv_h));
+  const double kz = floor(__dmul_rn((double)z, g.inv_h));
+  const double lim = (double)kKeyAxisLimit;
+  float best = INFINITY;
+  int bk = INT_MAX;
+  bool done = false;
+  for (int r = 0; r <= kRingMax && !done; ++r) {
+    for (int dx = -r; dx <= r; ++dx) {
+      const double cx = kx + dx;
+      if (fabs(cx) > lim) continue;
+      for (int dy = -r; dy <= r; ++dy) {
+        const double cy = ky + dy;
+        if (fabs(cy) > lim) continue;
+        // the shell of radius r: full columns on its x / y faces, the two z caps elsewhere
+        const bool face = dx == -r || dx == r || dy == -r || dy == r;
+        const int step = face ? 1 : 2 * r;
+        for (int dz = -r; dz <= r; dz += step) {
+          const double cz = kz + dz;
+          if (fabs(cz) > lim) continue;
+          const uint64_t key = ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
+                               ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) |
+                               (uint64_t)((int64_t)cz + kKeyBias);
+          const int c = lookup(g.tkey, g.tcell, g.nslots, key);
+          if (c < 0) continue;
+          const int e = g.coff[c] + g.ccnt[c];
+          for (int j = g.coff[c]; j < e; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
+        }
+      }
+    }
+    // distance from the point to the faces of the visited cube of cells
+    const double lo = (double)r, hi = (double)(r + 1);
+    double lb = (double)x - (kx - lo) * g.h;
+    lb = fmin(lb, (kx + hi) * g.h - (double)x);
+    lb = fmin(lb, (double)y - (ky - lo) * g.h);
+    lb = fmin(lb, (ky + hi) * g.h - (double)y);
+    lb = fmin(lb, (double)z - (kz - lo) * g.h);
+    lb = fmin(lb, (kz + hi) * g.h - (double)z);
+    // margin: float rounding of the values compared (a few ulps of the distances and scales involved)
+    const double margin = 1e-5 * (fabs(lb) + fabs(smax) + fabs((double)best)) + 1e-7 * g.h;
+    if (bk != INT_MAX && lb - smax > (double)best + margin) done = true;
+  }
+  if (done) {
+    val[i] = best;
+    arg[i] = bk;
+  } else {
+    const uint32_t slot = atomicAdd(fb_n, 1u);
+    fb[slot] = (int32_t)i;
+  }
+}
+
+// One workgroup per open point: the minimum over every candidate Gaussian.
+__global__ void __launch_bounds__(256) brute_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
+                                                    const float4* __restrict__ G, const int32_t* __restrict__ gi,
+                                                    int64_t nvalid, float* __restrict__ val,
+                                                    int32_t* __restrict__ arg) {
+  const int i = fb[blockIdx.x];
+  const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+  float best = INFINITY;
+  int bk = INT_MAX;
+  for (int64_t j = threadIdx.x; j < nvalid; j += blockDim.x) take_min(gauss_value(x, y, z, G[j]), gi[j], &best, &bk);
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(best, o, 64);
+    const int ok = __shfl_xor(bk, o, 64);
+    take_min(ov, ok, &best, &bk);
+  }
+  __shared__ float sv[4];
+  __shared__ int sk[4];
+  if (lane_id() == 0) {
+    sv[threadIdx.x >> 6] = best;
+    sk[threadIdx.x >> 6] = bk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) take_min(sv[w], sk[w], &best, &bk);
+    val[i] = best;
+    arg[i] = bk;
+  }
+}
+
+// Deterministic sum of the finite points' values: fixed per-tile order, then
+// the tiles in order.
+__global__ void __launch_bounds__(256) sum_tiles(const float* __restrict__ val, const float* __restrict__ pts, int64_t n, double* __restrict__ tsum,
+                                                 uint32_t* __restrict__ tcnt) {
+  const int64_t base = (int64_t)blockIdx.x * kReduceTile + threadIdx.x * 4;
+  double s = 0.0;
+  uint32_t c = 0;
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + e;
+    if (i < n) {
+      const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+      if (isfinite(x) && isfinite(y) && isfinite(z)) {
+        s += (double)val[i];
+        c += 1;
+      }
+    }
+  }
+  __shared__ double ss[256];
+  __shared__ uint32_t sc[256];
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      sc[threadIdx.x] += sc[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tsum[blockIdx.x] = ss[0];
+    tcnt[blockIdx.x] = sc[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) sum_final(const double* __restrict__ tsum, const uint32_t* __restrict__ tcnt,
+                                                 int64_t nt, double* __restrict__ out) {
+  __shared__ double ss[256];
+  __shared__ unsigned long long sc[256];
+  double s = 0.0;
+  unsigned long long c = 0;
+  for (int64_t t = threadIdx.x; t < nt; t += 256) {
+    s += tsum[t];
+    c += tcnt[t];
+  }
+  ss[threadIdx.x] = s;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      sc[threadIdx.x] += sc[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = ss[0];
+    out[1] = (double)sc[0];
+  }
+}
+
+}  // namespace
+}  // namespace vgpr
+
+using namespace vgpr;
+
+extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, int64_t n_pts, const float* d_gauss,
+                                           int64_t n_gauss, float cell_size, int scale_mode, float* d_value,
+                                           int32_t* d_arg, double* h_loss, int64_t* h_n_valid) {
+  if (!ctx || !h_loss) return VGPR_E_INVALID;
+  *h_loss = NAN;
+  if (h_n_valid) *h_n_valid = 0;
+  if (n_pts < 0 || n_pts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_pts out of range");
+  if (n_gauss < 0 || n_gauss >= (int64_t(1) << 30)) return fail(ctx, VGPR_E_INVALID, "n_gauss out of range");
+  if (!(cell_size > 0.0f) || !std::isfinite(cell_size)) return fail(ctx, VGPR_E_INVALID, "cell_size must be > 0");
+  if (scale_mode != 0 && scale_mode != 1) return fail(ctx, VGPR_E_INVALID, "scale_mode must be 0 or 1");
+  if (n_pts > 0 && !d_pts) return fail(ctx, VGPR_E_INVALID, "d_pts is NULL");
+  if (n_gauss > 0 && !d_gauss) return fail(ctx, VGPR_E_INVALID, "d_gauss is NULL");
+  if (n_gauss > 0 && (reinterpret_cast<uintptr_t>(d_gauss) & 15))
+    return fail(ctx, VGPR_E_INVALID, "d_gauss must be 16-byte aligned");
+  if (n_pts == 0) return VGPR_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  const int64_t n = n_pts, ng = n_gauss;
+  int64_t ns = 2;
+  while (ns < 2 * ng) ns <<= 1;
+  const int64_t nt = (n + kReduceTile - 1) / kReduceTile;
+  size_t head = 0;
+  auto sub = [&](size_t bytes) {
+    head = (head + 255) & ~size_t(255);
+    size_t r = head;
+    head += bytes;
+    return r;
+  };
+  const size_t o_cen = sub(12 * (size_t)ng + 16), o_sb = sub(4 * (size_t)ng + 16), o_ck = sub(8 * (size_t)ng + 16),
+               o_co = sub(4 * (size_t)ng + 16), o_cc = sub(4 * (size_t)ng + 16), o_pm = sub(4 * (size_t)ng + 16),
+               o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
+               o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_val = sub(d_value ? 0 : 4 * (size_t)n),
+               o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
+               o_misc = sub(64);
+  head = (head + 255) & ~size_t(255);
+  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)ng + 4096 * 16 + (1 << 20));
+  if (st != VGPR_OK) return st;
+  st = reserve_pinned(ctx, 64);
+  if (st != VGPR_OK) return st;
+  char* w = static_cast<char*>(ctx->work.ptr);
+  float* cen = reinterpret_cast<float*>(w + o_cen);
+  float* sb = reinterpret_cast<float*>(w + o_sb);
+  uint64_t* ckeys = reinterpret_cast<uint64_t*>(w + o_ck);
+  int32_t* coff = reinterpret_cast<int32_t*>(w + o_co);
+  int32_t* ccnt = reinterpret_cast<int32_t*>(w + o_cc);
+  int32_t* perm = reinterpret_cast<int32_t*>(w + o_pm);
+  float4* G = reinterpret_cast<float4*>(w + o_G);
+  int32_t* gi = reinterpret_cast<int32_t*>(w + o_gi);
+  uint64_t* tkey = reinterpret_cast<uint64_t*>(w + o_tk);
+  int32_t* tcell = reinterpret_cast<int32_t*>(w + o_tc);
+  int32_t* fb = reinterpret_cast<int32_t*>(w + o_fb);
+  float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
+  int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
+  double* tsum = reinterpret_cast<double*>(w + o_ts);
+  uint32_t* tcnt = reinterpret_cast<uint32_t*>(w + o_tn);
+  uint32_t* misc = reinterpret_cast<uint32_t*>(w + o_misc);  // [0] max mean scale (ordered bits), [1] open points
+  double* dsum = reinterpret_cast<double*>(w + o_misc + 16);
+
+  VGPR_HIP(ctx, hipMemsetAsync(misc, 0, 64, ctx->stream));
+  int64_t nc = 0, n_bad = 0;
+  if (ng > 0) {
+    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const float4*>(d_gauss), ng, scale_mode, cen, sb, misc);
+    VGPR_HIP(ctx, hipGetLastError());
+    st = voxelize_impl(ctx, cen, ng, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, ng, &nc, nullptr, &n_bad, head);
+    if (st != VGPR_OK) return st;
+    if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during the loss");
+  }
+  const int64_t nvalid = ng - n_bad;
+  const bool has_cand = nvalid > 0;
+  if (has_cand) {
+    VGPR_HIP(ctx, hipMemsetAsync(tkey, 0xFF, 8 * (size_t)ns, ctx->stream));
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nvalid + 255) / 256)), dim3(256), 0, ctx->stream, cen, sb,
+                       perm, nvalid, G, gi);
+    hipLaunchKernelGGL(table_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, ctx->stream, ckeys, nc, tkey,
+                       tcell, ns);
+    VGPR_HIP(ctx, hipGetLastError());
+  }
+  const double inv_h = 1.0 / (double)cell_size;
+  Grid grid{G, gi, tkey, tcell, ns, coff, ccnt, inv_h, (double)cell_size, misc};
+  {
+    ProfScope ps(ctx, "structure_loss");
+    hipLaunchKernelGGL(query_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, d_pts, n, grid,
+                       has_cand ? 1 : 0, val, arg, fb, misc + 1);
+    VGPR_HIP(ctx, hipGetLastError());
+  }
+  // the voxelizer may have grown the pinned staging area: take its address only now
+  void* hp = ctx->pinned;
+  VGPR_HIP(ctx, hipMemcpyAsync(hp, misc, 8, hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const uint32_t n_open = static_cast<uint32_t*>(hp)[1];
+  if (n_open > 0) {
+    hipLaunchKernelGGL(brute_kernel, dim3(n_open), dim3(256), 0, ctx->stream, d_pts, fb, G, gi, nvalid, val, arg);
+    VGPR_HIP(ctx, hipGetLastError());
+  }
+  hipLaunchKernelGGL(sum_tiles, dim3((unsigned)nt), dim3(256), 0, ctx->stream, val, d_pts, n, tsum, tcnt);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, ctx->stream, tsum, tcnt, nt, dsum);
+  VGPR_HIP(ctx, hipGetLastError());
+  VGPR_HIP(ctx, hipMemcpyAsync(hp, dsum, 16, hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double res[2];
+  std::memcpy(res, hp, 16);
+  const int64_t n_valid = (int64_t)res[1];
+  if (h_n_valid) *h_n_valid = n_valid;
+  *h_loss = n_valid > 0 ? res[0] / (double)n_valid : NAN;
+  return VGPR_OK;
+}

@@ -52,16 +52,6 @@ namespace {
 // into a re-solve (a posterior variance can round to 0).
 constexpr float kPredNoiseFloor = 1e-6f;
 
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-  // splitmix64 finaliser (a published 64-bit mixing function)
-  x ^= x >> 30;
-  x *= 0xbf58476d1ce4e5b9ull;
-  x ^= x >> 27;
-  x *= 0x94d049bb133111ebull;
-  x ^= x >> 31;
-  return x;
-}
-
 __device__ __forceinline__ int64_t find_slot(const uint64_t* slot_key, int64_t nslots, uint64_t key, bool* found) {
   int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
   for (int64_t probe = 0; probe < nslots; ++probe) {

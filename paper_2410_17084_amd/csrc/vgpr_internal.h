@@ -27,6 +27,17 @@ constexpr int kNumBuckets = 7;
 constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 96, 128, 256, 512};
 
 
+// Hash of a 64-bit voxel key for open-addressing tables (the splitmix64
+// finaliser, a published 64-bit mixing function).
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
 struct DeviceBuffer {
   void* ptr = nullptr;
   size_t bytes = 0;

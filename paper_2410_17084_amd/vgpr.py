@@ -24,7 +24,7 @@ SYMBOLS = [
     "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create", "vgpr_map_create_ex",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
     "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
-    "vgpr_gauss_init",
+    "vgpr_gauss_init", "vgpr_structure_loss",
 ]
 
 
@@ -118,6 +118,8 @@ def load():
         "vgpr_graph_launch": (C.c_int, [vp]),
         "vgpr_graph_destroy": (C.c_int, [vp]),
         "vgpr_gauss_init": (C.c_int, [vp, vp, vp, i64, i32, i32, C.c_float, vp]),
+        "vgpr_structure_loss": (C.c_int, [vp, vp, i64, vp, i64, C.c_float, C.c_int, vp, vp, P(C.c_double),
+                                          P(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -271,6 +273,23 @@ class Context:
                                       float(var_floor), _ptr(gauss))
         self._check(st, "vgpr_gauss_init")
         return gauss[:v]
+
+    def structure_loss(self, pts, gauss, cell_size: float, scale_mode: int = 0, value=None, arg=None):
+        """L_p of Eq. (9) for the scan points against Gaussians in the gauss_init
+        layout: (loss, n_valid, value (n,) float32, index (n,) int32)."""
+        torch = self.torch
+        n = pts.numel() // 3
+        g = gauss.reshape(-1, 8) if gauss.numel() else gauss
+        ng = gauss.numel() // 8
+        if value is None:
+            value = torch.empty(max(n, 1), dtype=torch.float32, device=pts.device)
+        if arg is None:
+            arg = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+        loss, nv = C.c_double(), C.c_int64()
+        st = self.lib.vgpr_structure_loss(self.h, _ptr(pts), n, _ptr(g) if ng else None, ng, float(cell_size),
+                                          int(scale_mode), _ptr(value), _ptr(arg), C.byref(loss), C.byref(nv))
+        self._check(st, "vgpr_structure_loss")
+        return loss.value, nv.value, value[:n], arg[:n]
 
     # -- launch tuning ----------------------------------------------------------
     def tuning(self) -> Tuning:
