@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="search launch choices first and cache them")
     ap.add_argument("--gauss-launches", type=int, default=20,
                     help="timed launches of the 3D-Gaussian initialisation on the batch's grids (0 skips)")
+    ap.add_argument("--loss-launches", type=int, default=10, help="timed structure-loss calls (0 = skip)")
     ap.add_argument("--graph-steps", type=int, default=20,
                     help="steps of the captured-graph form of the batch (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -362,6 +363,40 @@ def main():
                  "hbm_frac": gbytes / per / 1e9 / HBM_PEAK, "bound": "hbm"}
         log(f"gauss_init: {gauss}")
 
+    # structure similarity loss L_p (Eq. (9)) of one scan against the batch's
+    # Gaussians (S from variances: scale_mode 1), cell = the Gaussian spacing
+    sloss = None
+    if args.gauss_launches > 0 and args.loss_launches > 0:
+        xs = xyz[int(fo[0]):int(fo[1])]
+        spacing = w["voxel_size"] / ns
+        by_cell = {}
+        for mult in (1, 2, 4, 8):
+            cell = spacing * mult
+            ctx.structure_loss(xs, gbuf, cell, scale_mode=1)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            fams = ("structure_loss", "structure_loss_brute", "voxelize_key", "voxelize_sort", "voxelize_segment")
+            for fam in fams:
+                ctx.profile_read(fam)
+            t1 = time.perf_counter()
+            for _ in range(args.loss_launches):
+                lp, nvp, _, _ = ctx.structure_loss(xs, gbuf, cell, scale_mode=1)
+            wall = (time.perf_counter() - t1) / args.loss_launches
+            ph = {fam: ctx.profile_read(fam) for fam in fams}
+            ctx.profile(False)
+            by_cell[f"{cell:g}"] = {"ms_per_call": wall * 1e3,
+                                    "query_kernel_ms": ph["structure_loss"][0] / max(ph["structure_loss"][1], 1),
+                                    "brute_ms_per_call": ph["structure_loss_brute"][0] / args.loss_launches,
+                                    "grid_sort_ms": sum(ph[f][0] for f in ph if f.startswith("voxelize")) /
+                                    args.loss_launches}
+        best = min(by_cell, key=lambda c: by_cell[c]["ms_per_call"])
+        sloss = {"loss_m": lp, "points": int(nvp), "gaussians": int(V * ns * ns), "cell_m": float(best),
+                 "ms_per_call": by_cell[best]["ms_per_call"],
+                 "points_per_s": nvp / (by_cell[best]["ms_per_call"] / 1e3), "by_cell": by_cell,
+                 "what": "one scan against all Gaussians of the batch: grid build (voxelize the centres, cell "
+                         "table) + ring search + mean, host clock, synchronised"}
+        log(f"structure loss: {sloss}")
+
     # single-frame latency (voxelize + fit of one scan, host clock, synchronised)
     lat = []
     lat_solved = []
@@ -411,6 +446,7 @@ def main():
                               if len(lat) else None),
         "batched_graph": graph,
         "gauss_init": gauss,
+        "structure_loss": sloss,
         "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(rec), flush=True)

@@ -376,7 +376,9 @@ VGPR_API vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t);
  * family `name`, the summed duration in milliseconds and the number of
  * launches since the last read of that family, then resets it. Families:
  * "voxelize_key", "voxelize_sort" (all radix passes of a call),
- * "voxelize_segment", "classify", "gauss_init", "fit_mix_n<C>" (MIXED mode tiled
+ * "voxelize_segment", "classify", "gauss_init", "structure_loss" (the ring-search
+ * kernel of vgpr_structure_loss), "structure_loss_brute" (its brute-force pass
+ * over points far from every Gaussian), "fit_mix_n<C>" (MIXED mode tiled
  * solver), "fit_f32_n<C>" / "fit_f64_n<C>" (the
  * per-voxel solver over the size bucket of capacity C = 16, 32, 64, 96, 128, 256, 512) and
  * "refine_f64_n<C>" (the FP64 re-solve of flagged voxels of that bucket).

@@ -12,9 +12,12 @@
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
 // win. Points still open after kRingMax rings (far from the map) are resolved
-// by a brute-force pass over all Gaussians. Both passes take the minimum of
-// the same float values with the same tie rule, so the result does not depend
-// on h, which only sets the speed.
+// by a tiled brute-force pass: each workgroup stages a chunk of Gaussians in
+// LDS and evaluates it against every open point, and the chunks' minima merge
+// through a 64-bit atomic minimum of (ordered value bits, index). Both passes
+// take the minimum of the same float values with the same tie rule (lowest
+// value, then lowest index), so the result does not depend on h, which only
+// sets the speed.
 #include <cfloat>
 #include <climits>
 #include <cmath>
@@ -27,6 +30,7 @@ namespace {
 
 constexpr int kRingMax = 3;
 constexpr int kReduceTile = 1024;
+constexpr int kBruteChunk = 2048;  // Gaussians a brute-force workgroup stages in LDS (40 KB)
 
 __device__ __forceinline__ uint32_t float_order(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -41,7 +45,8 @@ __device__ __forceinline__ float float_unorder(uint32_t u) {
 // pass evaluates it through this one function.
 __device__ __forceinline__ float gauss_value(float x, float y, float z, float4 g) {
   const float dx = x - g.x, dy = y - g.y, dz = z - g.z;
-  return __fsub_rn(__fsqrt_rn(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz))), g.w);
+  const float v = __fsub_rn(__fsqrt_rn(__fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz))), g.w);
+  return __fadd_rn(v, 0.0f);  // -0 -> +0: equal values compare equal in the packed order too
 }
 
 __device__ __forceinline__ void take_min(float v, int k, float* best, int* bk) {
@@ -199,33 +204,44 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
   }
 }
 
-// One workgroup per open point: the minimum over every candidate Gaussian.
+// Tiled brute force for the open points: workgroup (bx, by) stages Gaussians
+// [bx * kBruteChunk, ...) in LDS and takes the open points by = by, by + gy,
+// ... in strides of 256; each point's minimum over the chunk merges into
+// best[o] as (ordered value bits << 32 | index), so atomicMin keeps the lowest
+// value and, among equal values, the lowest index.
 __global__ void __launch_bounds__(256) brute_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
-                                                    const float4* __restrict__ G, const int32_t* __restrict__ gi,
-                                                    int64_t nvalid, float* __restrict__ val,
-                                                    int32_t* __restrict__ arg) {
-  const int i = fb[blockIdx.x];
-  const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
-  float best = INFINITY;
-  int bk = INT_MAX;
-  for (int64_t j = threadIdx.x; j < nvalid; j += blockDim.x) take_min(gauss_value(x, y, z, G[j]), gi[j], &best, &bk);
-  for (int o = 32; o > 0; o >>= 1) {
-    const float ov = __shfl_xor(best, o, 64);
-    const int ok = __shfl_xor(bk, o, 64);
-    take_min(ov, ok, &best, &bk);
-  }
-  __shared__ float sv[4];
-  __shared__ int sk[4];
-  if (lane_id() == 0) {
-    sv[threadIdx.x >> 6] = best;
-    sk[threadIdx.x >> 6] = bk;
+                                                    uint32_t n_open, const float4* __restrict__ G,
+                                                    const int32_t* __restrict__ gi, int64_t nvalid,
+                                                    unsigned long long* __restrict__ best) {
+  __shared__ float4 sg[kBruteChunk];
+  __shared__ int32_t sk[kBruteChunk];
+  const int64_t g0 = (int64_t)blockIdx.x * kBruteChunk;
+  const int cnt = (int)min((int64_t)kBruteChunk, nvalid - g0);
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    sg[t] = G[g0 + t];
+    sk[t] = gi[g0 + t];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; ++w) take_min(sv[w], sk[w], &best, &bk);
-    val[i] = best;
-    arg[i] = bk;
+  for (uint32_t o = blockIdx.y * blockDim.x + threadIdx.x; o < n_open; o += gridDim.y * blockDim.x) {
+    const int i = fb[o];
+    const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+    float b = INFINITY;
+    int bk = INT_MAX;
+    for (int t = 0; t < cnt; ++t) take_min(gauss_value(x, y, z, sg[t]), sk[t], &b, &bk);
+    if (bk != INT_MAX)
+      atomicMin(&best[o], ((unsigned long long)float_order(b) << 32) | (unsigned long long)(uint32_t)bk);
   }
+}
+
+__global__ void __launch_bounds__(256) brute_finish(const int32_t* __restrict__ fb, uint32_t n_open,
+                                                    const unsigned long long* __restrict__ best,
+                                                    float* __restrict__ val, int32_t* __restrict__ arg) {
+  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_open) return;
+  const unsigned long long b = best[o];
+  const int i = fb[o];
+  val[i] = float_unorder((uint32_t)(b >> 32));
+  arg[i] = (int32_t)(uint32_t)(b & 0xffffffffull);
 }
 
 // Deterministic sum of the finite points' values: fixed per-tile order, then
@@ -324,7 +340,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   const size_t o_cen = sub(12 * (size_t)ng + 16), o_sb = sub(4 * (size_t)ng + 16), o_ck = sub(8 * (size_t)ng + 16),
                o_co = sub(4 * (size_t)ng + 16), o_cc = sub(4 * (size_t)ng + 16), o_pm = sub(4 * (size_t)ng + 16),
                o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
-               o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_val = sub(d_value ? 0 : 4 * (size_t)n),
+               o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
+               o_val = sub(d_value ? 0 : 4 * (size_t)n),
                o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
                o_misc = sub(64);
   head = (head + 255) & ~size_t(255);
@@ -344,6 +361,7 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   uint64_t* tkey = reinterpret_cast<uint64_t*>(w + o_tk);
   int32_t* tcell = reinterpret_cast<int32_t*>(w + o_tc);
   int32_t* fb = reinterpret_cast<int32_t*>(w + o_fb);
+  unsigned long long* bbest = reinterpret_cast<unsigned long long*>(w + o_bb);
   float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
   int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
   double* tsum = reinterpret_cast<double*>(w + o_ts);
@@ -385,7 +403,14 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
   const uint32_t n_open = static_cast<uint32_t*>(hp)[1];
   if (n_open > 0) {
-    hipLaunchKernelGGL(brute_kernel, dim3(n_open), dim3(256), 0, ctx->stream, d_pts, fb, G, gi, nvalid, val, arg);
+    ProfScope ps(ctx, "structure_loss_brute");
+    VGPR_HIP(ctx, hipMemsetAsync(bbest, 0xFF, 8 * (size_t)n_open, ctx->stream));
+    const unsigned gx = (unsigned)((nvalid + kBruteChunk - 1) / kBruteChunk);
+    const unsigned gy = (unsigned)std::min<int64_t>((n_open + 255) / 256, 16);
+    hipLaunchKernelGGL(brute_kernel, dim3(gx, gy), dim3(256), 0, ctx->stream, d_pts, fb, n_open, G, gi, nvalid,
+                       bbest);
+    hipLaunchKernelGGL(brute_finish, dim3((n_open + 255) / 256), dim3(256), 0, ctx->stream, fb, n_open, bbest, val,
+                       arg);
     VGPR_HIP(ctx, hipGetLastError());
   }
   hipLaunchKernelGGL(sum_tiles, dim3((unsigned)nt), dim3(256), 0, ctx->stream, val, d_pts, n, tsum, tcnt);
