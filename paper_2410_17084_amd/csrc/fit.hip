@@ -103,6 +103,11 @@ struct Lists {
 __device__ __forceinline__ float k_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double k_exp(double x) { return exp(x); }
 
+// Pivot reciprocal: the hardware estimate (1 ulp) in FP32, whose elimination error
+// is far above it; IEEE division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -423,8 +428,17 @@ __device__ __forceinline__ float4 make_row(const FitParams& P, const FrameRec& f
 // ---------------------------------------------------------------------------
 // 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
 // ---------------------------------------------------------------------------
+// Waves per SIMD the register allocation must allow: four for the FP32 16-point
+// solver (the bulk of small voxels; latency bound, it spills 40 bytes a lane
+// for it), the compiler's choice elsewhere.
 template <typename T, int NMAX, int QR>
-__global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
+constexpr int wave_min_waves() {
+  return (sizeof(T) == 4 && NMAX == 16 && QR == 1) ? 4 : 1;
+}
+
+template <typename T, int NMAX, int QR>
+__global__ void __launch_bounds__(kWaveThreads) __attribute__((amdgpu_waves_per_eu(wave_min_waves<T, NMAX, QR>(), 8)))
+fit_wave_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
                                                                 const RotRec* __restrict__ rots,
                                                                 const float4* __restrict__ staged,
@@ -588,7 +602,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       const T cjB = B[0];
       const T d = bcast(cjB, j);
       const T y = bcast(fy, j);  // y_j = (L^-1 f~)_j, final once step j is reached
-      const T inv = (T)1 / d;
+      const T inv = recip(d);
       const T tB = cjB * inv;
 #pragma unroll
       for (int r = 0; r < QR; ++r) {
