@@ -36,11 +36,14 @@ TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_spin32_batch64.json")
 
 
 def source_hash() -> str:
-    """Hash of the library sources (kernels and ABI header): ties stored counter readings to the code."""
+    """Hash of the sources the solver kernels and their launches are built from (the
+    solver file, the context and launch-choice code, the internal and ABI headers):
+    ties stored counter readings of the solver kernels to the code."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2410_17084_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)) + [os.path.join(HERE, "include", "vgpr.h")]
+    files = [os.path.join(csrc, f) for f in ("ctx.hip", "fit.hip", "scan.cuh", "vgpr_internal.h")] + \
+        [os.path.join(HERE, "include", "vgpr.h")]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -161,6 +164,8 @@ def main():
     ap.add_argument("--gauss-launches", type=int, default=20,
                     help="timed launches of the 3D-Gaussian initialisation on the batch's grids (0 skips)")
     ap.add_argument("--loss-launches", type=int, default=10, help="timed structure-loss calls (0 = skip)")
+    ap.add_argument("--isolated-steps", type=int, default=5,
+                    help="steps with every bucket on one stream, for each kernel's own duration (0 = skip)")
     ap.add_argument("--graph-steps", type=int, default=20,
                     help="steps of the captured-graph form of the batch (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -298,6 +303,47 @@ def main():
         tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
+
+    # The buckets run concurrently on side streams, so a launch's duration in the
+    # timed region includes time spent waiting for CUs that other buckets hold
+    # (and rocprofv3 sees the same). The same launch choices with every bucket
+    # on one stream give each kernel's own duration: the per-kernel roofline.
+    isolated = None
+    if fam_time and args.isolated_steps > 0:
+        t_saved = ctx.tuning().as_dict()
+        t_ser = dict(t_saved)
+        t_ser["streams"] = 1
+        ctx.set_tuning(vgpr.Tuning.from_dict(t_ser))
+        step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for fam in FAMILIES:
+            ctx.profile_read(fam)
+        for _ in range(args.isolated_steps):
+            step()
+        iso = {fam: ctx.profile_read(fam) for fam in FAMILIES}
+        ctx.profile(False)
+        ctx.set_tuning(vgpr.Tuning.from_dict(t_saved))
+        b_of = bucket_of(n_kept)
+        fl = voxel_flops(n_kept, m)
+        per = {}
+        for fam, (ms, cnt) in iso.items():
+            if not cnt or not fam.startswith(("fit", "refine")):
+                continue
+            b = BUCKETS.index(int(fam.rsplit("_n", 1)[1]))
+            sel = solved & (b_of == b) & (refined if fam.startswith("refine") else True)
+            lps = cnt / args.isolated_steps
+            sec = ms / cnt / 1e3
+            tf = float(fl[sel].sum()) / lps / sec / 1e12
+            dt = "f64" if "f64" in fam else "f32"
+            per[fam] = {"ms_per_launch": ms / cnt, "voxels_per_launch": int(sel.sum() / lps), "tflops": tf,
+                        "frac": tf / PEAK[dt]}
+        dom_iso = max(per, key=lambda f: per[f]["ms_per_launch"]) if per else None
+        isolated = {"what": "same launch choices, every bucket on one stream (each kernel's own duration, HIP "
+                            "events); peak FP64 78.6 / FP32 157.3 TFLOP/s", "dominant": dom_iso,
+                    "ms_per_step_serial": sum(v[0] for f, v in iso.items() if v[1]) / args.isolated_steps,
+                    "kernels": per}
+        log(f"isolated launches: dominant {dom_iso} {per.get(dom_iso)}")
 
     # batched form captured as a graph: the same batch voxelized into fixed
     # buffers, then one replay of the captured fit_predict per step
@@ -447,7 +493,7 @@ def main():
         "batched_graph": graph,
         "gauss_init": gauss,
         "structure_loss": sloss,
-        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
+        "roofline": roof, "roofline_isolated": isolated, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
