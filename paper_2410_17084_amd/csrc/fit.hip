@@ -1065,13 +1065,17 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           // L(I,I)^-1 by forward substitution, lane k computing column k; the sums
-          // run as four independent chains and the division is by the stored 1/L_ii
+          // run as four independent chains and the division is by the stored 1/L_ii.
+          // Entries above the diagonal of a column are exactly zero, so the sums
+          // start at zero and the unit right-hand side enters as + 1/L_ii on the
+          // diagonal (an identity constant per row would be hoisted out of the
+          // voxel loop and spilled).
           if (lane < kTile) {
             double x[kTile];
             const double* __restrict__ Ld = rb + I * kTile;
 #pragma unroll
             for (int i = 0; i < kTile; ++i) {
-              double s0 = i == lane ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+              double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
               for (int j0 = 0; j0 < i; j0 += 8) {
                 // eight entries of row i read together, then four independent chains
@@ -1086,7 +1090,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
                   if (j0 + e + 3 < i) s3 -= lr[e + 3] * x[j0 + e + 3];
                 }
               }
-              x[i] = ((s0 + s1) + (s2 + s3)) * srd[i];
+              const double ri = srd[i];
+              x[i] = ((s0 + s1) + (s2 + s3)) * ri + (i == lane ? ri : 0.0);
             }
             double* __restrict__ Wi = Wt + (size_t)I * kTileDoubles;
 #pragma unroll
@@ -1376,14 +1381,15 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
           const float* __restrict__ Ld = rb + I * kTile;
 #pragma unroll
           for (int i = 0; i < kTile; ++i) {
-            float s0 = i == lane ? 1.f : 0.f, s1 = 0.f;
+            float s0 = 0.f, s1 = 0.f;  // as in the FP64 solver: the unit enters on the diagonal
 #pragma unroll
             for (int j = 0; j + 1 < i; j += 2) {
               s0 -= Ld[i * LD + j] * x[j];
               s1 -= Ld[i * LD + j + 1] * x[j + 1];
             }
             if (i & 1) s0 -= Ld[i * LD + i - 1] * x[i - 1];
-            x[i] = (s0 + s1) * srdf[i];
+            const float ri = srdf[i];
+            x[i] = (s0 + s1) * ri + (i == lane ? ri : 0.f);
           }
           const size_t t = (size_t)I * kTileDoubles;
 #pragma unroll
