@@ -428,17 +428,8 @@ __device__ __forceinline__ float4 make_row(const FitParams& P, const FrameRec& f
 // ---------------------------------------------------------------------------
 // 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
 // ---------------------------------------------------------------------------
-// Waves per SIMD the register allocation must allow: four for the FP32 16-point
-// solver (the bulk of small voxels; latency bound, it spills 40 bytes a lane
-// for it), the compiler's choice elsewhere.
 template <typename T, int NMAX, int QR>
-constexpr int wave_min_waves() {
-  return (sizeof(T) == 4 && NMAX == 16 && QR == 1) ? 4 : 1;
-}
-
-template <typename T, int NMAX, int QR>
-__global__ void __launch_bounds__(kWaveThreads) __attribute__((amdgpu_waves_per_eu(wave_min_waves<T, NMAX, QR>(), 8)))
-fit_wave_kernel(FitParams P, FitArgs io,
+__global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
                                                                 const RotRec* __restrict__ rots,
                                                                 const float4* __restrict__ staged,

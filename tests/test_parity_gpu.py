@@ -550,10 +550,15 @@ def test_fit_graph_replays(env):
             st.synchronize()
             out = g.launch()
             st.synchronize()
-            for a, b in zip(out, ref):
-                assert np.array_equal(a.cpu().numpy(), b, equal_nan=True)
-            for a, b in zip(eager, ref):
-                assert np.array_equal(a.cpu().numpy(), b, equal_nan=True)
+            for what, got in (("graph", out), ("eager", eager)):
+                for name, a, b in zip(("out", "axis", "status"), got, ref):
+                    a = a.cpu().numpy()
+                    if not np.array_equal(a, b, equal_nan=True):
+                        bad = np.flatnonzero(~((a == b) | (np.isnan(a) & np.isnan(b))).reshape(len(a), -1).all(1))
+                        cnts = vox.counts.cpu().numpy()[bad[:8]]
+                        raise AssertionError(f"{what} replay {rep}: {name} differs in {len(bad)} voxels, "
+                                             f"first {bad[:8].tolist()} counts {cnts.tolist()} "
+                                             f"status {ref[2][bad[:8]].tolist()} vs {got[2].cpu().numpy()[bad[:8]].tolist()}")
         new_noise = rng(16).uniform(2e-4, 5e-3, size=len(xyz)).astype(np.float32)
         noise.copy_(torch.from_numpy(new_noise))
         torch.cuda.synchronize()
