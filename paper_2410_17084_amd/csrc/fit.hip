@@ -185,21 +185,34 @@ __global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, floa
       while (lst < kNumBuckets - 1 && n > P.bcap[lst]) ++lst;
     }
   }
-  // slot in the voxel's list: one atomic per wavefront and list
+  // slot in the voxel's list: wavefront offsets within the workgroup through LDS,
+  // then one global atomic per workgroup and list
+  __shared__ uint32_t s_cnt[kLists], s_base[kLists];
   const int lane = lane_id();
   const unsigned long long lt = (1ull << lane) - 1ull;
-  int slot = 0;
+  if (threadIdx.x < kLists) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t woff = 0;
+  unsigned long long mymask = 0;
 #pragma unroll
   for (int l = 0; l < kLists; ++l) {
     const unsigned long long mk = __ballot(lst == l);
     if (mk) {
       const int leader = __ffsll((long long)mk) - 1;
       uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&L.count[l], (uint32_t)__popcll(mk));
+      if (lane == leader) base = atomicAdd(&s_cnt[l], (uint32_t)__popcll(mk));
       base = __shfl(base, leader, 64);
-      if (lst == l) slot = (int)(base + __popcll(mk & lt));
+      if (lst == l) {
+        woff = base;
+        mymask = mk;
+      }
     }
   }
+  __syncthreads();
+  if (threadIdx.x < kLists && s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&L.count[threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  int slot = 0;
+  if (lst >= 0) slot = (int)(s_base[lst] + woff + __popcll(mymask & lt));
   if (lst == kNanList) L.nan_list[slot] = (int32_t)v;
   if (lst < 0 || lst == kNanList) return;
 
