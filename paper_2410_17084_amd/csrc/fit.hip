@@ -387,18 +387,28 @@ __device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& 
   io.axis[v] = (int8_t)(axes & 3);
 }
 
-__device__ __forceinline__ void query_coords(const FitParams& P, const FrameRec& fr, int q, float* gu, float* gw) {
-  const int i = q / P.nq, j = q - (q / P.nq) * P.nq;
+// Fraction (i + 0.5) / nq of grid index i, correctly rounded: voxel-independent,
+// so the solvers compute it once per lane (or table) instead of once per voxel.
+__device__ __forceinline__ double grid_frac(const FitParams& P, int i) {
+  return __ddiv_rn((double)i + 0.5, (double)P.nq);
+}
+
+// Grid coordinates of the query with fractions (ti, tj) of its row and column.
+__device__ __forceinline__ void coords_from_frac(const FitParams& P, const FrameRec& fr, double ti, double tj,
+                                                 float* gu, float* gw) {
   if (P.frame_mode == 1) {
     // interval centres of an s x s square centred on the centroid, in the (e1, e2) plane
-    *gu = (float)__dmul_rn(__dadd_rn(__ddiv_rn((double)i + 0.5, (double)P.nq), -0.5), P.s);
-    *gw = (float)__dmul_rn(__dadd_rn(__ddiv_rn((double)j + 0.5, (double)P.nq), -0.5), P.s);
+    *gu = (float)__dmul_rn(__dadd_rn(ti, -0.5), P.s);
+    *gw = (float)__dmul_rn(__dadd_rn(tj, -0.5), P.s);
     return;
   }
-  const double ti = __ddiv_rn((double)i + 0.5, (double)P.nq);
-  const double tj = __ddiv_rn((double)j + 0.5, (double)P.nq);
   *gu = (float)__dmul_rn(__dadd_rn((double)fr.ku, ti), P.s);
   *gw = (float)__dmul_rn(__dadd_rn((double)fr.kw, tj), P.s);
+}
+
+__device__ __forceinline__ void query_coords(const FitParams& P, const FrameRec& fr, int q, float* gu, float* gw) {
+  const int i = q / P.nq, j = q - (q / P.nq) * P.nq;
+  coords_from_frac(P, fr, grid_frac(P, i), grid_frac(P, j), gu, gw);
 }
 
 __device__ __forceinline__ float4 out_row(int ax, int u, float mv, float gu, float gw, float vv) {
@@ -474,6 +484,18 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     if (lane < rn.fr.n) pn = staged[rn.off + lane];
   }
   if (it + nw < cnt_items) rnn = recs[slots ? slots[it + nw] : it + nw];
+  // grid fractions of this lane's query rows and of grid index `lane` (voxel-independent)
+  double fti[QR], ftj[QR];
+  int qi[QR], qj[QR];
+#pragma unroll
+  for (int r = 0; r < QR; ++r) {
+    const int q = lane + 64 * r < P.m ? lane + 64 * r : 0;
+    qi[r] = q / P.nq;
+    qj[r] = q - qi[r] * P.nq;
+    fti[r] = grid_frac(P, qi[r]);
+    ftj[r] = grid_frac(P, qj[r]);
+  }
+  const double flane = grid_frac(P, lane < P.nq ? lane : 0);
   for (; it < cnt_items; it += nw) {
     const SlotRec r = rn;
     const float4 pt = pn;
@@ -501,14 +523,8 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     }
     // this lane's query points q = lane + 64 r (r < QR, q < m): row i, column j of the grid
     float gu[QR], gwv[QR];
-    int qi[QR], qj[QR];
 #pragma unroll
-    for (int r = 0; r < QR; ++r) {
-      const int q = lane + 64 * r < P.m ? lane + 64 * r : 0;
-      query_coords(P, fr, q, &gu[r], &gwv[r]);
-      qi[r] = q / P.nq;
-      qj[r] = q - qi[r] * P.nq;
-    }
+    for (int r = 0; r < QR; ++r) coords_from_frac(P, fr, fti[r], ftj[r], &gu[r], &gwv[r]);
     const bool dlane = lane < n;
 
     // Kernel entries with few exponentials. The query entries factor as
@@ -527,8 +543,7 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
     if (lane < P.nq) {
       // grid coordinate i (and j) of the face: the same formula as query_coords
       float gi, gj;
-      FrameRec f2 = fr;
-      query_coords(P, f2, lane * P.nq + lane, &gi, &gj);
+      coords_from_frac(P, fr, flane, flane, &gi, &gj);
       su[NMAX + lane] = (T)((double)gi - fr.anc_u);
       sw[NMAX + lane] = (T)((double)gj - fr.anc_w);
     }
@@ -670,6 +685,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
   __shared__ T su[NMAX + 4], sw[NMAX + 4], sf[NMAX + 4], sn[NMAX + 4];
   __shared__ __attribute__((aligned(16))) T col[2][NMAX + 8];
   __shared__ T piv[2][2];
+  __shared__ double s_frac[kMaxGridSide];  // grid fractions (i + 0.5) / nq, written once
   __shared__ int s_item;
   __shared__ unsigned s_maxvar;
   __shared__ int s_flag;
@@ -678,6 +694,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
   const int NT = blockDim.x;
   const int cnt_items = (int)*count;
   const T sf2 = (T)P.sf2;
+  if (tid < P.nq) s_frac[tid] = grid_frac(P, tid);  // read after the first barrier of the loop
 
   for (;;) {
     if (tid == 0) {
@@ -725,7 +742,8 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
         fy = sf[tid];
         nz = sn[tid];
       } else if (is_query) {
-        query_coords(P, fr, q, &gu, &gwv);
+        const int qi = q / P.nq;
+        coords_from_frac(P, fr, s_frac[qi], s_frac[q - qi * P.nq], &gu, &gwv);
         xu = (T)((double)gu - fr.anc_u);
         xw = (T)((double)gwv - fr.anc_w);
       }
