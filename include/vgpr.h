@@ -265,6 +265,33 @@ VGPR_API vgpr_status vgpr_map_stats(vgpr_map* map, int64_t* h_n_voxels, int64_t*
                            int64_t* h_n_converged);
 
 /*
+ * vgpr_map_export / vgpr_map_import - checkpoint and resume of a map (the
+ * state of Sec. 3.3 that the paper keeps across frames), through host memory.
+ *
+ * Export writes the map's whole state into the caller's host buffer h_buf of
+ * buf_bytes bytes: an 80-byte header (magic "VGPRMAP1" at byte 0, version 1
+ * as u32 at 8, update mode as i32 at 12, voxel count V as i64 at 16, the
+ * vgpr_params the map was created with at 24), then in native
+ * (little-endian) byte order: V voxel keys (u64, in insertion order), V
+ * stored point counts (i32), V arrived point counts (i32), V converged flags
+ * (u8), for update mode 1 V in-map flags (u8), the point pool (V * max_pts *
+ * 3 float32), and for update mode 1 the predicted rows (V * grid_side^2 *
+ * 4 float32). *h_needed receives the size; with h_buf = NULL only the size is
+ * returned. Synchronises the map's stream. Errors: E_CAPACITY when buf_bytes <
+ * *h_needed.
+ *
+ * Import creates a new map on ctx (as vgpr_map_create_ex, with the serialised
+ * parameters and update mode, and max_voxels >= V) holding that state: later
+ * updates of it give the same results as updates of the exported map would.
+ * Errors: E_INVALID (not a serialised map, wrong version, truncated buffer,
+ * max_voxels < V, a stored count outside [0, max_pts], parameters the library
+ * rejects), E_BUDGET, E_DEVICE.
+ */
+VGPR_API vgpr_status vgpr_map_export(vgpr_map* map, void* h_buf, size_t buf_bytes, size_t* h_needed);
+VGPR_API vgpr_status vgpr_map_import(vgpr_ctx* ctx, const void* h_buf, size_t buf_bytes, int64_t max_voxels,
+                                     vgpr_map** out);
+
+/*
  * vgpr_gauss_init - initial 3D Gaussians from the predicted grids (Sec. 3.2).
  *
  * d_out / d_status: n_vox voxels as written by vgpr_fit_predict (or

@@ -321,6 +321,59 @@ __global__ void __launch_bounds__(256) stats_kernel(vgpr_map M, unsigned long lo
   atomicAdd(&out[1], conv);
 }
 
+// Map import: the hash table from the voxel records (keys are unique).
+__global__ void __launch_bounds__(256) rebuild_kernel(vgpr_map M, int64_t nv) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nv) return;
+  const uint64_t key = M.vkey[id];
+  int64_t s = (int64_t)(mix64(key) & (uint64_t)(M.nslots - 1));
+  for (int64_t probe = 0; probe < M.nslots; ++probe) {
+    const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&M.slot_key[s]),
+                                              (unsigned long long)kKeySentinel, (unsigned long long)key);
+    if (prev == kKeySentinel) {
+      M.slot_id[s] = (int32_t)id;
+      return;
+    }
+    s = (s + 1) & (M.nslots - 1);
+  }
+}
+
+// Serialised map: a fixed header, then the per-voxel arrays in this order.
+constexpr char kMapMagic[8] = {'V', 'G', 'P', 'R', 'M', 'A', 'P', '1'};
+constexpr uint32_t kMapVersion = 1;
+struct MapHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t update_mode;
+  int64_t n_voxels;
+  vgpr_params params;
+};
+
+struct MapLayout {
+  size_t keys, stored, total, conv, vpred, pool, pred, end;
+};
+
+MapLayout map_layout(int mode, int64_t nv, int cap, int m) {
+  MapLayout L{};
+  size_t o = sizeof(MapHeader);
+  L.keys = o;
+  o += 8 * (size_t)nv;
+  L.stored = o;
+  o += 4 * (size_t)nv;
+  L.total = o;
+  o += 4 * (size_t)nv;
+  L.conv = o;
+  o += (size_t)nv;
+  L.vpred = o;
+  o += mode == 1 ? (size_t)nv : 0;
+  L.pool = o;
+  o += 12 * (size_t)cap * (size_t)nv;
+  L.pred = o;
+  o += mode == 1 ? 16 * (size_t)m * (size_t)nv : 0;
+  L.end = o;
+  return L;
+}
+
 }  // namespace
 }  // namespace vgpr
 
@@ -571,6 +624,95 @@ vgpr_status vgpr_map_stats(vgpr_map* M, int64_t* h_n_voxels, int64_t* h_n_points
   if (h_n_voxels) *h_n_voxels = (int64_t)h[2];
   if (h_n_points) *h_n_points = (int64_t)h[0];
   if (h_n_converged) *h_n_converged = (int64_t)h[1];
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_map_export(vgpr_map* M, void* h_buf, size_t buf_bytes, size_t* h_needed) {
+  if (!M || !h_needed) return VGPR_E_INVALID;
+  vgpr_ctx* ctx = M->ctx;
+  *h_needed = 0;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  unsigned long long nv_u = 0;
+  VGPR_HIP(ctx, hipMemcpy(&nv_u, M->counters, sizeof(nv_u), hipMemcpyDeviceToHost));
+  const int64_t nv = (int64_t)nv_u < M->max_voxels ? (int64_t)nv_u : M->max_voxels;
+  const int cap = M->params.max_pts, m = M->params.grid_side * M->params.grid_side;
+  const MapLayout L = map_layout(M->mode, nv, cap, m);
+  *h_needed = L.end;
+  if (!h_buf) return VGPR_OK;
+  if (buf_bytes < L.end) return fail(ctx, VGPR_E_CAPACITY, "export buffer smaller than *h_needed");
+  char* b = static_cast<char*>(h_buf);
+  MapHeader h{};
+  std::memcpy(h.magic, kMapMagic, sizeof(kMapMagic));
+  h.version = kMapVersion;
+  h.update_mode = M->mode;
+  h.n_voxels = nv;
+  h.params = M->params;
+  std::memcpy(b, &h, sizeof(h));
+  if (nv > 0) {
+    VGPR_HIP(ctx, hipMemcpy(b + L.keys, M->vkey, 8 * (size_t)nv, hipMemcpyDeviceToHost));
+    VGPR_HIP(ctx, hipMemcpy(b + L.stored, M->vstored, 4 * (size_t)nv, hipMemcpyDeviceToHost));
+    VGPR_HIP(ctx, hipMemcpy(b + L.total, M->vtotal, 4 * (size_t)nv, hipMemcpyDeviceToHost));
+    VGPR_HIP(ctx, hipMemcpy(b + L.conv, M->vconv, (size_t)nv, hipMemcpyDeviceToHost));
+    VGPR_HIP(ctx, hipMemcpy(b + L.pool, M->pool, 12 * (size_t)cap * (size_t)nv, hipMemcpyDeviceToHost));
+    if (M->mode == 1) {
+      VGPR_HIP(ctx, hipMemcpy(b + L.vpred, M->vpred, (size_t)nv, hipMemcpyDeviceToHost));
+      VGPR_HIP(ctx, hipMemcpy(b + L.pred, M->pred, 16 * (size_t)m * (size_t)nv, hipMemcpyDeviceToHost));
+    }
+  }
+  return VGPR_OK;
+}
+
+vgpr_status vgpr_map_import(vgpr_ctx* ctx, const void* h_buf, size_t buf_bytes, int64_t max_voxels, vgpr_map** out) {
+  if (!ctx || !out) return VGPR_E_INVALID;
+  *out = nullptr;
+  if (!h_buf || buf_bytes < sizeof(MapHeader)) return fail(ctx, VGPR_E_INVALID, "buffer too short for a map header");
+  MapHeader h;
+  std::memcpy(&h, h_buf, sizeof(h));
+  if (std::memcmp(h.magic, kMapMagic, sizeof(kMapMagic)) != 0 || h.version != kMapVersion)
+    return fail(ctx, VGPR_E_INVALID, "not a serialised map of this version");
+  if (h.n_voxels < 0 || h.n_voxels > max_voxels)
+    return fail(ctx, VGPR_E_INVALID, "max_voxels is below the serialised voxel count");
+  vgpr_map* M = nullptr;
+  vgpr_status st = vgpr_map_create_ex(ctx, &h.params, max_voxels, h.update_mode, &M);
+  if (st != VGPR_OK) return st;
+  const int64_t nv = h.n_voxels;
+  const int cap = M->params.max_pts, m = M->params.grid_side * M->params.grid_side;
+  const MapLayout L = map_layout(M->mode, nv, cap, m);
+  const char* b = static_cast<const char*>(h_buf);
+  auto bad = [&](const char* msg) {
+    vgpr_map_destroy(M);
+    return fail(ctx, VGPR_E_INVALID, msg);
+  };
+  if (buf_bytes < L.end) return bad("buffer shorter than the serialised map");
+  for (int64_t v = 0; v < nv; ++v) {
+    int32_t stored;
+    std::memcpy(&stored, b + L.stored + 4 * (size_t)v, 4);
+    if (stored < 0 || stored > cap) return bad("a stored point count is outside [0, max_pts]");
+  }
+  auto copy_in = [&](void* dst, size_t off, size_t bytes) {
+    return hipMemcpy(dst, b + off, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = true;
+  if (nv > 0) {
+    ok = copy_in(M->vkey, L.keys, 8 * (size_t)nv) && copy_in(M->vstored, L.stored, 4 * (size_t)nv) &&
+         copy_in(M->vtotal, L.total, 4 * (size_t)nv) && copy_in(M->vconv, L.conv, (size_t)nv) &&
+         copy_in(M->pool, L.pool, 12 * (size_t)cap * (size_t)nv);
+    if (ok && M->mode == 1)
+      ok = copy_in(M->vpred, L.vpred, (size_t)nv) && copy_in(M->pred, L.pred, 16 * (size_t)m * (size_t)nv);
+    if (ok) {
+      hipLaunchKernelGGL(rebuild_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, ctx->stream, *M, nv);
+      ok = hipGetLastError() == hipSuccess;
+    }
+  }
+  const unsigned long long nv_u = (unsigned long long)nv;
+  ok = ok && hipMemcpyAsync(M->counters, &nv_u, sizeof(nv_u), hipMemcpyHostToDevice, ctx->stream) == hipSuccess &&
+       hipStreamSynchronize(ctx->stream) == hipSuccess;
+  if (!ok) {
+    vgpr_map_destroy(M);
+    return fail(ctx, VGPR_E_DEVICE, "copying the serialised map to the device failed");
+  }
+  *out = M;
   return VGPR_OK;
 }
 

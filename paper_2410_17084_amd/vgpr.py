@@ -21,7 +21,7 @@ PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
 # every entry point include/vgpr.h declares
 SYMBOLS = [
     "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
-    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create", "vgpr_map_create_ex",
+    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create", "vgpr_map_create_ex", "vgpr_map_export", "vgpr_map_import",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
     "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
     "vgpr_gauss_init", "vgpr_structure_loss",
@@ -107,6 +107,8 @@ def load():
         "vgpr_fit_predict": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
         "vgpr_map_create": (C.c_int, [vp, P(Params), i64, P(vp)]),
         "vgpr_map_create_ex": (C.c_int, [vp, P(Params), i64, C.c_int, P(vp)]),
+        "vgpr_map_export": (C.c_int, [vp, vp, sz, P(sz)]),
+        "vgpr_map_import": (C.c_int, [vp, vp, sz, i64, P(vp)]),
         "vgpr_map_destroy": (C.c_int, [vp]),
         "vgpr_map_update": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, P(i64)]),
         "vgpr_map_stats": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
@@ -341,15 +343,34 @@ class Map:
     """A device-resident voxel map (vgpr_map) bound to a Context; feedback=True
     selects update mode 1 (the covariance-centred update of type (c) voxels)."""
 
-    def __init__(self, ctx: Context, params: Params, max_voxels: int, feedback: bool = False):
+    def __init__(self, ctx: Context, params: Params, max_voxels: int, feedback: bool = False, _handle=None):
         self.ctx = ctx
         self.params = params
         self.feedback = bool(feedback)
-        h = C.c_void_p()
-        ctx._check(ctx.lib.vgpr_map_create_ex(ctx.h, C.byref(params), int(max_voxels), int(self.feedback),
-                                              C.byref(h)), "vgpr_map_create_ex")
-        self.h = h
+        if _handle is None:
+            h = C.c_void_p()
+            ctx._check(ctx.lib.vgpr_map_create_ex(ctx.h, C.byref(params), int(max_voxels), int(self.feedback),
+                                                  C.byref(h)), "vgpr_map_create_ex")
+            _handle = h
+        self.h = _handle
         ctx._maps.add(self)
+
+    def export(self) -> bytes:
+        """The map's whole state as bytes (vgpr_map_export)."""
+        need = C.c_size_t()
+        self.ctx._check(self.ctx.lib.vgpr_map_export(self.h, None, 0, C.byref(need)), "vgpr_map_export")
+        buf = C.create_string_buffer(need.value)
+        self.ctx._check(self.ctx.lib.vgpr_map_export(self.h, buf, need.value, C.byref(need)), "vgpr_map_export")
+        return buf.raw[:need.value]
+
+    @classmethod
+    def load(cls, ctx: Context, data: bytes, max_voxels: int) -> "Map":
+        """A new map holding a state written by export (vgpr_map_import)."""
+        h = C.c_void_p()
+        ctx._check(ctx.lib.vgpr_map_import(ctx.h, data, len(data), int(max_voxels), C.byref(h)), "vgpr_map_import")
+        prm = Params.from_buffer_copy(data[24:24 + C.sizeof(Params)])  # header: params at byte 24
+        mode = int.from_bytes(data[12:16], "little", signed=True)
+        return cls(ctx, prm, max_voxels, feedback=mode == 1, _handle=h)
 
     def close(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):

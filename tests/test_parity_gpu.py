@@ -635,3 +635,41 @@ def test_fit_rotated_frame_reproduces_tilted_planes(env):
             xyzv = o[v, :, :3]
             res = [np.abs(a * xyzv[:, 0] + b * xyzv[:, 1] + c - xyzv[:, 2]).max() for a, b, c in planes]
             assert min(res) <= 1e-5, (v, res)  # float32 rounding of outputs up to ~17 m
+
+
+@pytest.mark.parametrize("feedback", [False, True])
+def test_map_export_import_resumes_identically(env, feedback):
+    """Checkpoint / resume: a map exported after two frames and imported into a
+    new map continues bit-identically to the original over two more frames."""
+    torch, vgpr, ctx = env
+    w = dict(configs.params_for("paper_stream"), max_pts=48, converge_var=2e-4)
+    p = parity.gpu_params(vgpr, w)
+    a = vgpr.Map(ctx, p, max_voxels=150000, feedback=feedback)
+    frames = [synth.spin_scan(synth.frame_seed(6, k), n_beams=32, n_az=1024, position=(0.05 * k, 0.02 * k),
+                              yaw=0.05 * k) for k in range(4)]
+    for k in range(2):
+        say("map export/import", feedback, "frame", k)
+        a.update(dev(torch, frames[k]))
+    data = a.export()
+    st = a.stats()
+    assert len(data) >= 80 and data[:8] == b"VGPRMAP1"
+    b = vgpr.Map.load(ctx, data, max_voxels=160000)
+    assert b.feedback == feedback and b.stats() == st
+    assert b.export() == data
+    for k in range(2, 4):
+        say("map export/import", feedback, "resume frame", k)
+        ra = [t.cpu().numpy() for t in a.update(dev(torch, frames[k]))]
+        rb = [t.cpu().numpy() for t in b.update(dev(torch, frames[k]))]
+        assert len(ra[0]) > 100
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y, equal_nan=True)
+    assert a.stats() == b.stats()
+    with pytest.raises(vgpr.VgprError) as ei:
+        vgpr.Map.load(ctx, data, max_voxels=st["voxels"] - 1)
+    assert ei.value.status == vgpr.E_INVALID
+    for bad in (b"XGPRMAP1" + data[8:], data[:len(data) - 5], data[:40]):
+        with pytest.raises(vgpr.VgprError) as ei:
+            vgpr.Map.load(ctx, bad, max_voxels=160000)
+        assert ei.value.status == vgpr.E_INVALID
+    a.close()
+    b.close()
