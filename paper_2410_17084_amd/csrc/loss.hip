@@ -7,14 +7,16 @@
 // Exact search on a uniform grid of cell size h. The Gaussian centres are
 // sorted into cells with the voxelizer (Alg. S1's keys), each cell's range
 // goes into an open-addressing table, and each point visits the cells of
-// growing cubes around its own cell (rings r = 0, 1, ...). Every Gaussian
+// growing cubes around its own cell (rings r = 0, 1, ..., eight lanes per
+// point sharing out each ring's cells). Every Gaussian
 // outside the cube of radius r lies at least lb_r (the distance from P_j to the
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
 // win. Points still open after kRingMax rings (far from the map) are resolved
 // by a tiled brute-force pass: each workgroup stages a chunk of Gaussians in
-// LDS and evaluates it against every open point, and the chunks' minima merge
-// through a 64-bit atomic minimum of (ordered value bits, index). Both passes
+// LDS and evaluates it against every open point that cannot rule the chunk out
+// by its bounding box, and the chunks' minima merge through a 64-bit atomic
+// minimum of (ordered value bits, index), seeded with what the rings found. Both passes
 // take the minimum of the same float values with the same tie rule (lowest
 // value, then lowest index), so the result does not depend on h, which only
 // sets the speed.
@@ -39,6 +41,10 @@ __device__ __forceinline__ uint32_t float_order(float f) {
 
 __device__ __forceinline__ float float_unorder(uint32_t u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ unsigned long long pack_best(float v, int k) {
+  return ((unsigned long long)float_order(v) << 32) | (unsigned long long)(uint32_t)k;
 }
 
 // Value of Gaussian g (centre, mean scale in w) for point (x, y, z); every
@@ -136,82 +142,178 @@ struct Grid {
   const uint32_t* smax;
 };
 
+// Ring search, kGroup lanes per point: the lanes of a group share out the cells
+// of each ring, then combine their minima with a butterfly of shuffles (the
+// (value, index) order is total, so the result does not depend on who visited
+// what). A group stops once its bound clears; the wavefront runs until every
+// group has stopped, so every lane takes part in the shuffles.
+constexpr int kGroup = 8;
+
 __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pts, int64_t n, Grid g, int has_cand,
                                                     float* __restrict__ val, int32_t* __restrict__ arg,
-                                                    int32_t* __restrict__ fb, uint32_t* __restrict__ fb_n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-    val[i] = __int_as_float(0x7fc00000);
-    arg[i] = -1;
-    return;
+                                                    int32_t* __restrict__ fb, uint32_t* __restrict__ fb_n,
+                                                    unsigned long long* __restrict__ bbest) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  const int gl = threadIdx.x & (kGroup - 1);
+  float x = 0.f, y = 0.f, z = 0.f;
+  bool live = false;
+  if (i < n) {
+    x = pts[3 * (size_t)i];
+    y = pts[3 * (size_t)i + 1];
+    z = pts[3 * (size_t)i + 2];
+    const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
+    if (gl == 0 && !fin) {
+      val[i] = __int_as_float(0x7fc00000);
+      arg[i] = -1;
+    } else if (gl == 0 && !has_cand) {
+      val[i] = INFINITY;
+      arg[i] = -1;
+    }
+    live = fin && has_cand;
   }
-  if (!has_cand) {
-    val[i] = INFINITY;
-    arg[i] = -1;
-    return;
-  }
-  const double smax = (double)float_unorder(*g.smax);
+  const double smax = has_cand ? (double)float_unorder(*g.smax) : 0.0;
   const double kx = floor(__dmul_rn((double)x, g.inv_h));
   const double ky = floor(__dmul_rn((double)y, g.inv_h));
   const double kz = floor(__dmul_rn((double)z, g.inv_h));
   const double lim = (double)kKeyAxisLimit;
   float best = INFINITY;
   int bk = INT_MAX;
-  bool done = false;
-  for (int r = 0; r <= kRingMax && !done; ++r) {
-    for (int dx = -r; dx <= r; ++dx) {
-      const double cx = kx + dx;
-      if (fabs(cx) > lim) continue;
-      for (int dy = -r; dy <= r; ++dy) {
-        const double cy = ky + dy;
-        if (fabs(cy) > lim) continue;
-        // the shell of radius r: full columns on its x / y faces, the two z caps elsewhere
-        const bool face = dx == -r || dx == r || dy == -r || dy == r;
-        const int step = face ? 1 : 2 * r;
-        for (int dz = -r; dz <= r; dz += step) {
-          const double cz = kz + dz;
-          if (fabs(cz) > lim) continue;
-          const uint64_t key = ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
-                               ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) |
-                               (uint64_t)((int64_t)cz + kKeyBias);
-          const int c = lookup(g.tkey, g.tcell, g.nslots, key);
-          if (c < 0) continue;
-          const int e = g.coff[c] + g.ccnt[c];
-          for (int j = g.coff[c]; j < e; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
+  bool done = !live;
+  for (int r = 0; r <= kRingMax; ++r) {
+    if (!done) {
+      // the shell of radius r: cells of the (2r+1)^3 cube with Chebyshev distance r
+      const int side = 2 * r + 1;
+      for (int t = gl; t < side * side * side; t += kGroup) {
+        const int dz = t % side - r, dy = (t / side) % side - r, dx = t / (side * side) - r;
+        if (max(max(abs(dx), abs(dy)), abs(dz)) != r) continue;
+        const double cx = kx + dx, cy = ky + dy, cz = kz + dz;
+        if (fabs(cx) > lim || fabs(cy) > lim || fabs(cz) > lim) continue;
+        const uint64_t key = ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
+                             ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) |
+                             (uint64_t)((int64_t)cz + kKeyBias);
+        const int c = lookup(g.tkey, g.tcell, g.nslots, key);
+        if (c < 0) continue;
+        const int e = g.coff[c] + g.ccnt[c];
+        for (int j = g.coff[c]; j < e; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < kGroup; o <<= 1) {
+      const float ov = __shfl_xor(best, o, 64);
+      const int ok = __shfl_xor(bk, o, 64);
+      take_min(ov, ok, &best, &bk);
+    }
+    if (!done) {
+      // distance from the point to the faces of the visited cube of cells
+      const double lo = (double)r, hi = (double)(r + 1);
+      double lb = (double)x - (kx - lo) * g.h;
+      lb = fmin(lb, (kx + hi) * g.h - (double)x);
+      lb = fmin(lb, (double)y - (ky - lo) * g.h);
+      lb = fmin(lb, (ky + hi) * g.h - (double)y);
+      lb = fmin(lb, (double)z - (kz - lo) * g.h);
+      lb = fmin(lb, (kz + hi) * g.h - (double)z);
+      // margin: float rounding of the values compared (a few ulps of the distances and scales involved)
+      const double margin = 1e-5 * (fabs(lb) + fabs(smax) + fabs((double)best)) + 1e-7 * g.h;
+      if (bk != INT_MAX && lb - smax > (double)best + margin) {
+        done = true;
+        if (gl == 0) {
+          val[i] = best;
+          arg[i] = bk;
         }
       }
     }
-    // distance from the point to the faces of the visited cube of cells
-    const double lo = (double)r, hi = (double)(r + 1);
-    double lb = (double)x - (kx - lo) * g.h;
-    lb = fmin(lb, (kx + hi) * g.h - (double)x);
-    lb = fmin(lb, (double)y - (ky - lo) * g.h);
-    lb = fmin(lb, (ky + hi) * g.h - (double)y);
-    lb = fmin(lb, (double)z - (kz - lo) * g.h);
-    lb = fmin(lb, (kz + hi) * g.h - (double)z);
-    // margin: float rounding of the values compared (a few ulps of the distances and scales involved)
-    const double margin = 1e-5 * (fabs(lb) + fabs(smax) + fabs((double)best)) + 1e-7 * g.h;
-    if (bk != INT_MAX && lb - smax > (double)best + margin) done = true;
+    if (__ballot(!done) == 0ull) break;
   }
-  if (done) {
-    val[i] = best;
-    arg[i] = bk;
-  } else {
+  if (!done && gl == 0) {  // still open after kRingMax rings: the brute-force pass resolves it,
+    // starting from the best value the rings found
     const uint32_t slot = atomicAdd(fb_n, 1u);
     fb[slot] = (int32_t)i;
+    bbest[slot] = bk == INT_MAX ? ~0ull : pack_best(best, bk);
   }
+}
+
+// Bounding box and extreme mean scales of each brute-force chunk (the Gaussians
+// are in cell order, so a chunk covers a compact region): (min x, y, z, max S),
+// (max x, y, z, min S).
+__global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict__ G, int64_t nvalid,
+                                                        float4* __restrict__ box) {
+  const int64_t g0 = (int64_t)blockIdx.x * kBruteChunk;
+  const int cnt = (int)min((int64_t)kBruteChunk, nvalid - g0);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, sm = -INFINITY,
+        sn = INFINITY;
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const float4 q = G[g0 + t];
+    lo[0] = fminf(lo[0], q.x);
+    lo[1] = fminf(lo[1], q.y);
+    lo[2] = fminf(lo[2], q.z);
+    hi[0] = fmaxf(hi[0], q.x);
+    hi[1] = fmaxf(hi[1], q.y);
+    hi[2] = fmaxf(hi[2], q.z);
+    sm = fmaxf(sm, q.w);
+    sn = fminf(sn, q.w);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+    sm = fmaxf(sm, __shfl_xor(sm, o, 64));
+    sn = fminf(sn, __shfl_xor(sn, o, 64));
+  }
+  __shared__ float red[4][8];
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[w][0] = lo[0], red[w][1] = lo[1], red[w][2] = lo[2];
+    red[w][3] = hi[0], red[w][4] = hi[1], red[w][5] = hi[2], red[w][6] = sm, red[w][7] = sn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        red[0][a] = fminf(red[0][a], red[k][a]);
+        red[0][3 + a] = fmaxf(red[0][3 + a], red[k][3 + a]);
+      }
+      red[0][6] = fmaxf(red[0][6], red[k][6]);
+      red[0][7] = fminf(red[0][7], red[k][7]);
+    }
+    box[2 * blockIdx.x] = make_float4(red[0][0], red[0][1], red[0][2], red[0][6]);
+    box[2 * blockIdx.x + 1] = make_float4(red[0][3], red[0][4], red[0][5], red[0][7]);
+  }
+}
+
+// Upper bound of each open point's best value before any chunk is evaluated:
+// every Gaussian of a chunk lies within the distance to the box's farthest
+// corner, so the chunk's minimum is at most that distance minus its smallest
+// mean scale (rounded up by the margin).
+__global__ void __launch_bounds__(256) bound_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
+                                                    uint32_t n_open, const float4* __restrict__ box, int nchunk,
+                                                    float* __restrict__ ub) {
+  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_open) return;
+  const int i = fb[o];
+  const double x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+  double u = INFINITY;
+  for (int c = 0; c < nchunk; ++c) {
+    const float4 lo = box[2 * c], hi = box[2 * c + 1];
+    const double fx = fmax(fabs(x - lo.x), fabs(x - hi.x)), fy = fmax(fabs(y - lo.y), fabs(y - hi.y)),
+                 fz = fmax(fabs(z - lo.z), fabs(z - hi.z));
+    const double d = sqrt(fx * fx + fy * fy + fz * fz) - (double)hi.w;
+    u = fmin(u, d + 1e-5 * (fabs(d) + fabs((double)hi.w)) + 1e-7);
+  }
+  ub[o] = (float)u + 1e-6f * fabsf((float)u);  // rounded up past the float conversion
 }
 
 // Tiled brute force for the open points: workgroup (bx, by) stages Gaussians
 // [bx * kBruteChunk, ...) in LDS and takes the open points by = by, by + gy,
 // ... in strides of 256; each point's minimum over the chunk merges into
 // best[o] as (ordered value bits << 32 | index), so atomicMin keeps the lowest
-// value and, among equal values, the lowest index.
+// value and, among equal values, the lowest index. A point skips a chunk whose
+// box distance minus its largest mean scale exceeds the point's current best
+// by more than the rounding margin (no value in the chunk can reach it).
 __global__ void __launch_bounds__(256) brute_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
                                                     uint32_t n_open, const float4* __restrict__ G,
                                                     const int32_t* __restrict__ gi, int64_t nvalid,
+                                                    const float4* __restrict__ box, const float* __restrict__ ub,
                                                     unsigned long long* __restrict__ best) {
   __shared__ float4 sg[kBruteChunk];
   __shared__ int32_t sk[kBruteChunk];
@@ -222,14 +324,22 @@ __global__ void __launch_bounds__(256) brute_kernel(const float* __restrict__ pt
     sk[t] = gi[g0 + t];
   }
   __syncthreads();
+  const float4 blo = box[2 * blockIdx.x], bhi = box[2 * blockIdx.x + 1];
   for (uint32_t o = blockIdx.y * blockDim.x + threadIdx.x; o < n_open; o += gridDim.y * blockDim.x) {
     const int i = fb[o];
     const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+    const unsigned long long cur = __hip_atomic_load(&best[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double cv = (double)ub[o];
+    if (cur != ~0ull) cv = fmin(cv, (double)float_unorder((uint32_t)(cur >> 32)));
+    const double ex = fmax(fmax((double)blo.x - x, (double)x - bhi.x), 0.0);
+    const double ey = fmax(fmax((double)blo.y - y, (double)y - bhi.y), 0.0);
+    const double ez = fmax(fmax((double)blo.z - z, (double)z - bhi.z), 0.0);
+    const double lb = sqrt(ex * ex + ey * ey + ez * ez) - (double)blo.w;
+    if (lb > cv + 1e-5 * (fabs(lb) + fabs(cv) + fabs((double)blo.w)) + 1e-7) continue;
     float b = INFINITY;
     int bk = INT_MAX;
     for (int t = 0; t < cnt; ++t) take_min(gauss_value(x, y, z, sg[t]), sk[t], &b, &bk);
-    if (bk != INT_MAX)
-      atomicMin(&best[o], ((unsigned long long)float_order(b) << 32) | (unsigned long long)(uint32_t)bk);
+    if (bk != INT_MAX) atomicMin(&best[o], pack_best(b, bk));
   }
 }
 
@@ -341,6 +451,7 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
                o_co = sub(4 * (size_t)ng + 16), o_cc = sub(4 * (size_t)ng + 16), o_pm = sub(4 * (size_t)ng + 16),
                o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
                o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
+               o_box = sub(32 * (size_t)((ng + kBruteChunk - 1) / kBruteChunk) + 32), o_ub = sub(4 * (size_t)n),
                o_val = sub(d_value ? 0 : 4 * (size_t)n),
                o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
                o_misc = sub(64);
@@ -362,6 +473,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   int32_t* tcell = reinterpret_cast<int32_t*>(w + o_tc);
   int32_t* fb = reinterpret_cast<int32_t*>(w + o_fb);
   unsigned long long* bbest = reinterpret_cast<unsigned long long*>(w + o_bb);
+  float4* cbox = reinterpret_cast<float4*>(w + o_box);
+  float* ubound = reinterpret_cast<float*>(w + o_ub);
   float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
   int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
   double* tsum = reinterpret_cast<double*>(w + o_ts);
@@ -393,8 +506,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   Grid grid{G, gi, tkey, tcell, ns, coff, ccnt, inv_h, (double)cell_size, misc};
   {
     ProfScope ps(ctx, "structure_loss");
-    hipLaunchKernelGGL(query_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, d_pts, n, grid,
-                       has_cand ? 1 : 0, val, arg, fb, misc + 1);
+    hipLaunchKernelGGL(query_kernel, dim3((unsigned)((n * kGroup + 255) / 256)), dim3(256), 0, ctx->stream, d_pts, n, grid,
+                       has_cand ? 1 : 0, val, arg, fb, misc + 1, bbest);
     VGPR_HIP(ctx, hipGetLastError());
   }
   // the voxelizer may have grown the pinned staging area: take its address only now
@@ -404,11 +517,13 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   const uint32_t n_open = static_cast<uint32_t*>(hp)[1];
   if (n_open > 0) {
     ProfScope ps(ctx, "structure_loss_brute");
-    VGPR_HIP(ctx, hipMemsetAsync(bbest, 0xFF, 8 * (size_t)n_open, ctx->stream));
     const unsigned gx = (unsigned)((nvalid + kBruteChunk - 1) / kBruteChunk);
+    hipLaunchKernelGGL(chunk_box_kernel, dim3(gx), dim3(256), 0, ctx->stream, G, nvalid, cbox);
+    hipLaunchKernelGGL(bound_kernel, dim3((n_open + 255) / 256), dim3(256), 0, ctx->stream, d_pts, fb, n_open, cbox,
+                       (int)gx, ubound);
     const unsigned gy = (unsigned)std::min<int64_t>((n_open + 255) / 256, 16);
     hipLaunchKernelGGL(brute_kernel, dim3(gx, gy), dim3(256), 0, ctx->stream, d_pts, fb, n_open, G, gi, nvalid,
-                       bbest);
+                       cbox, ubound, bbest);
     hipLaunchKernelGGL(brute_finish, dim3((n_open + 255) / 256), dim3(256), 0, ctx->stream, fb, n_open, bbest, val,
                        arg);
     VGPR_HIP(ctx, hipGetLastError());
