@@ -352,10 +352,12 @@ def test_map_update_matches_oracle_state_machine(env):
         assert st["points"] == sum(len(v) for v in om.points.values())
 
 
-def _compare_map_frame(o_ref, keys, out, axis, status, sf2, eta):
+def _compare_map_frame(o_ref, keys, out, axis, status, sf2, eta, rotated=False):
     """One frame of map updates: keys exact, SOLVED / CAPPED / BELOW_TAU equal,
     CONVERGED equal unless the oracle's max variance is within tolerance of eta,
-    rows within the fit tolerances where both took the same value axis."""
+    rows within the fit tolerances where both took the same value axis (frame
+    mode 1: all three coordinates within MEAN_TOL, frames flagged as near ties
+    skipped, as in the rotated fit tests)."""
     assert np.array_equal(parity.as_u64(keys), o_ref["keys"])
     o = out.cpu().numpy().astype(np.float64)
     ax = axis.cpu().numpy()
@@ -367,8 +369,16 @@ def _compare_map_frame(o_ref, keys, out, axis, status, sf2, eta):
         if not o_ref["status"][i] & O.ST_SOLVED:
             continue
         a = o_ref["axis"][i]
+        tie = (stt[i] & O.ST_AXIS_TIE) or (o_ref["status"][i] & O.ST_AXIS_TIE)
         if ax[i] != a:
-            assert (stt[i] & O.ST_AXIS_TIE) or (o_ref["status"][i] & O.ST_AXIS_TIE), i
+            assert tie, i
+            continue
+        if rotated:
+            if tie:
+                continue
+            assert np.abs(o[i][:, :3] - o_ref["out"][i][:, :3]).max() <= parity.MEAN_TOL, i
+            assert np.abs(o[i][:, 3] - o_ref["out"][i][:, 3]).max() <= parity.VAR_TOL_REL * sf2, i
+            n_cmp += 1
             continue
         u, wv = O.PARAM_AXES[a]
         assert np.array_equal(o[i][:, u].astype(np.float32), o_ref["out"][i][:, u].astype(np.float32))
@@ -382,14 +392,14 @@ def _compare_map_frame(o_ref, keys, out, axis, status, sf2, eta):
     return o, stt, n_cmp
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_map_feedback_matches_oracle(env, prec):
+@pytest.mark.parametrize("prec,frame_mode", [("fp32", 0), ("fp64", 0), ("fp32", 1), ("fp64", 1)])
+def test_map_feedback_matches_oracle(env, prec, frame_mode):
     """Update mode 1 (covariance-centred update of type (c) voxels): each frame is
     compared with the oracle's feedback map on the same carried state (after a
     frame the oracle takes the GPU's float32 rows and converged flags, so every
     re-solve of the next frame starts from identical inputs)."""
     torch, vgpr, ctx = env
-    w = dict(configs.params_for("paper_stream"), max_pts=48, converge_var=2e-4)
+    w = dict(configs.params_for("paper_stream"), max_pts=48, converge_var=2e-4, frame_mode=frame_mode)
     prm = parity.oracle_params(w)
     p = parity.gpu_params(vgpr, w, precision=vgpr.PREC_FP32 if prec == "fp32" else vgpr.PREC_FP64)
     om = O.VoxelMap(prm, feedback=True)
@@ -398,11 +408,18 @@ def test_map_feedback_matches_oracle(env, prec):
     for k in range(5):
         xyz = synth.spin_scan(synth.frame_seed(5, k), n_beams=32, n_az=1024, position=(0.05 * k, 0.02 * k),
                               yaw=0.05 * k)
-        say("feedback map", prec, "frame", k, len(xyz))
+        say("feedback map", prec, "frame mode", frame_mode, "frame", k, len(xyz))
         before = set(om.pred)
         keys, out, axis, status = gm.update(dev(torch, xyz))
         ref = om.update(xyz)
-        o, stt, n_cmp = _compare_map_frame(ref, keys, out, axis, status, prm.signal_var, prm.converge_var)
+        o, stt, n_cmp = _compare_map_frame(ref, keys, out, axis, status, prm.signal_var, prm.converge_var,
+                                           rotated=frame_mode == 1)
+        solved_rows = o[(stt & O.ST_SOLVED) != 0]
+        if len(solved_rows):
+            # axis-aligned grids take grid_side distinct values per parameter coordinate, rotated ones more
+            distinct = np.median([min(len(np.unique(r[:, c].astype(np.float32))) for c in range(3))
+                                  for r in solved_rows[:200]])
+            assert (distinct > prm.grid_side) == (frame_mode == 1), distinct
         n_cmp_total += n_cmp
         for i, key in enumerate(ref["keys"].tolist()):
             n_resolved += key in before
