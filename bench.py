@@ -73,7 +73,7 @@ def log(*a):
 
 
 def voxel_flops(n: np.ndarray, m: int) -> np.ndarray:
-    """Algorithmic FP operations of one voxel solve (see the design notes).
+    """Algorithmic FP operations of one voxel solve.
 
     n^3/3 (factorisation) + n^2 m (L^-1 K*) + 2 n^2 (solve of f) + 4 n m
     (mean and variance) + 6 (n^2/2 + n m) (kernel entries, exp not counted).
@@ -204,8 +204,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(voxels shard by key with one all-to-all; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(voxels would shard by key with one all-to-all exchange of points)", file=sys.stderr)
         sys.exit(2)
 
     import torch

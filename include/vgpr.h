@@ -7,12 +7,18 @@
  *
  *   vgpr_voxelize    - Alg. S1 (STORE): voxel key per point, the visited-voxel
  *                      list S_updated, each voxel's points in arrival order.
- *   vgpr_fit_predict - Alg. 1 lines after STORE: per-voxel PCA and value-axis
- *                      switch, kernel matrices K, K*, K**, and the posterior
- *                      mean and variance of Eq. (3) on a query grid.
+ *   vgpr_fit_predict - the rest of Alg. 1 after STORE: per-voxel PCA and
+ *                      value-axis switch, kernel matrices K, K*, K**, and the
+ *                      posterior mean and variance of Eq. (3) on a query grid
+ *                      (also captured as a HIP graph: vgpr_fit_graph_*).
  *   vgpr_map_update  - the voxel-map update of Sec. 3.3: points stacked into
  *                      a persistent map, voxels of types (b)/(c) re-solved,
- *                      types (a)/(d) skipped.
+ *                      types (a)/(d) skipped; with update mode 1 the
+ *                      covariance-centred update of type (c) voxels
+ *                      (vgpr_map_create_ex); vgpr_map_export / _import
+ *                      checkpoint and resume a map.
+ *   vgpr_gauss_init  - the initial 3D Gaussians of Sec. 3.2 from the grids.
+ *   vgpr_structure_loss - the structure similarity loss L_p of Eq. (9).
  *
  * Conventions shared by every call
  * - Pointers named d_* are device pointers (HIP global memory on the
@@ -57,7 +63,7 @@ typedef enum {
   VGPR_E_RANGE = 4,       /* a finite point's voxel index is outside +-(2^20 - 1) */
   VGPR_E_BUDGET = 5,      /* the work does not fit the context's HBM budget */
   VGPR_E_DEVICE = 6,      /* a HIP runtime call failed */
-  VGPR_E_UNSUPPORTED = 7  /* parameter combination this build does not implement */
+  VGPR_E_UNSUPPORTED = 7  /* parameter combination the library does not implement */
 } vgpr_status;
 
 /* Per-voxel status bits (uint8 per voxel). */

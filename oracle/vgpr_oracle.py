@@ -33,12 +33,14 @@ Library primitives used as single steps: ``numpy.argsort`` (stable sort),
 ``numpy.linalg.eigh`` (symmetric eigensolver), ``scipy.linalg.cho_factor`` /
 ``cho_solve`` / ``solve_triangular`` (the SPD solve of Eq. (3)).
 
-Readings of points the paper leaves open (each is listed with its reason in
-the design notes): the key packing, half-open voxels, stable point order, the
-cap policy, smallest-eigenvalue eigenvector, |v| for the angle, cyclic
-parameter axes, a constant prior mean equal to the sample mean of f, the
-kernel scale s_f^2 and length scale l in place of lambda, the grid of interval
-centres, output of the diagonal of Sigma*, and convergence as max var <= eta.
+Readings of points the paper leaves open: the key packing, half-open voxels,
+stable point order, the cap policy, smallest-eigenvalue eigenvector, |v| for
+the angle, cyclic parameter axes, a constant prior mean equal to the sample
+mean of f, the kernel scale s_f^2 and length scale l in place of lambda, the
+grid of interval centres, output of the diagonal of Sigma*, convergence as
+max var <= eta, the axis convention of the rotated frame (frame_mode 1), the
+carried rows and noise of the covariance-centred type (c) update, and for
+Eq. (9) the mean over the n points with S-bar the mean of the three scales.
 
 Parity status: every function here is pinned by closed forms, invariants,
 brute force or an independent library routine in tests/test_oracle_pins.py,

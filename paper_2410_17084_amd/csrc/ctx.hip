@@ -109,11 +109,11 @@ vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
     return fail(ctx, VGPR_E_INVALID, "voxel_size must be a positive finite number");
   if (p->max_pts < 1) return fail(ctx, VGPR_E_INVALID, "max_pts must be >= 1");
   if (p->max_pts > kMaxPtsLimit)
-    return fail(ctx, VGPR_E_UNSUPPORTED, "max_pts above 512 is not supported by this build");
+    return fail(ctx, VGPR_E_UNSUPPORTED, "max_pts above 512 is not supported by the library");
   if (p->min_pts < 1) return fail(ctx, VGPR_E_INVALID, "min_pts must be >= 1");
   if (p->grid_side < 1) return fail(ctx, VGPR_E_INVALID, "grid_side must be >= 1");
   if (p->grid_side > kMaxGridSide)
-    return fail(ctx, VGPR_E_UNSUPPORTED, "grid_side above 16 is not supported by this build");
+    return fail(ctx, VGPR_E_UNSUPPORTED, "grid_side above 16 is not supported by the library");
   if (!(p->signal_var > 0.f) || !(p->length_scale > 0.f) || !(p->noise_var >= 0.f))
     return fail(ctx, VGPR_E_INVALID, "signal_var and length_scale must be > 0, noise_var >= 0");
   if (p->ls_mode != 0 && p->ls_mode != 1) return fail(ctx, VGPR_E_INVALID, "ls_mode must be 0 or 1");

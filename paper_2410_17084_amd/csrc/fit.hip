@@ -1833,8 +1833,9 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
                        ctx->stream, P, a.out, L);
     VGPR_HIP(ctx, hipGetLastError());
   }
-  // Buckets run concurrently: the two largest on side stream 0, the middle two
-  // on side stream 1, the smallest (and its FP64 re-solve) on the caller's
+  // Buckets run concurrently: the 96/128-point buckets on side stream 0, the
+  // 32/64-point buckets on side stream 1, the 256/512-point buckets on side
+  // stream 2, the 16-point bucket (and its FP64 re-solve) on the caller's
   // stream, joined back before the call returns. Many small voxels fill the
   // CUs that the few long large-voxel solves leave idle.
   st = ensure_aux(ctx);
