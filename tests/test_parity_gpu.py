@@ -479,6 +479,41 @@ def test_map_feedback_argument_errors(env):
     vgpr.Map(ctx, big, max_voxels=100).close()  # mode 0 accepts it
 
 
+def test_map_update_output_capacity_reports_required_size(env):
+    """cap_upd below the number of re-solved voxels: E_CAPACITY with *h_n_upd = the
+    required count (the oracle map's), the first cap_upd outputs equal to those of
+    a call with room for all, and the frame applied to the map."""
+    torch, vgpr, ctx = env
+    C = vgpr.C
+    w = dict(configs.params_for("paper_stream"), max_pts=48)
+    p = parity.gpu_params(vgpr, w)
+    xyz = synth.spin_scan(synth.frame_seed(7, 3), n_beams=32, n_az=1024)
+    ref = O.VoxelMap(parity.oracle_params(w)).update(xyz)
+    full = vgpr.Map(ctx, p, max_voxels=100000)
+    k_full, o_full, a_full, s_full = [t.cpu().numpy() for t in full.update(dev(torch, xyz))]
+    small = vgpr.Map(ctx, p, max_voxels=100000)
+    cap = 5
+    m = p.grid_side ** 2
+    keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+    out = torch.empty((cap, m, 4), dtype=torch.float32, device="cuda")
+    axis = torch.empty(cap, dtype=torch.int8, device="cuda")
+    status = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    nu = C.c_int64()
+    x = dev(torch, xyz)
+    say("map update output capacity", cap)
+    st = ctx.lib.vgpr_map_update(small.h, C.c_void_p(x.data_ptr()), len(xyz), C.c_void_p(keys.data_ptr()),
+                                 C.c_void_p(out.data_ptr()), C.c_void_p(axis.data_ptr()),
+                                 C.c_void_p(status.data_ptr()), cap, C.byref(nu))
+    torch.cuda.synchronize()
+    assert st == vgpr.E_CAPACITY and nu.value == len(ref["keys"]) == len(k_full) > cap
+    assert np.array_equal(keys.cpu().numpy(), k_full[:cap])
+    assert np.array_equal(out.cpu().numpy(), o_full[:cap], equal_nan=True)
+    assert np.array_equal(status.cpu().numpy(), s_full[:cap])
+    assert small.stats()["voxels"] == full.stats()["voxels"]
+    small.close()
+    full.close()
+
+
 def test_map_capacity_rejects_frame(env):
     torch, vgpr, ctx = env
     p = parity.gpu_params(vgpr, configs.params_for("paper_stream"))
