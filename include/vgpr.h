@@ -376,8 +376,8 @@ VGPR_API vgpr_status vgpr_graph_launch(vgpr_graph* graph);
 VGPR_API vgpr_status vgpr_graph_destroy(vgpr_graph* graph);
 
 /*
- * Launch choices of vgpr_fit_predict. streams and grid_scale change only
- * timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
+ * Launch choices of vgpr_fit_predict. streams, grid_scale and tiled_first
+ * change only timing (results are bit-identical); fp32_last_bucket and wave_last_bucket
  * change the rounding (which arithmetic and which solver a voxel gets), and
  * every choice stays within the stated tolerances. Buckets hold voxels of up to
  * 16, 32, 64, 96, 128, 256 and 512 kept points (index 0..6); buckets from
@@ -397,6 +397,10 @@ typedef struct {
   int32_t tile_first_bucket;  /* buckets from this one on (2..5) run a tiled solver on the
                                  matrix cores (FP64, or the mixed form in MIXED mode); buckets
                                  5 and 6 always do */
+  int32_t tiled_first;        /* with streams = 3: 1 runs the tiled buckets first, alone on the
+                                 context's stream (their workgroups need whole CUs, which other
+                                 buckets' workgroups would hold), and forks the others after
+                                 them; 0 forks every bucket at once */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);

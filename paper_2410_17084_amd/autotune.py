@@ -98,9 +98,12 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
     log(f"[autotune] baseline {base:.3f} ms {cur}")
     fp32_opts = [-1, 0, 1, 2] if params.precision in (vgpr.PREC_FP32, vgpr.PREC_MIXED) else [cur["fp32_last_bucket"]]
     space = [("streams", [1, 3]), ("wave_last_bucket", [0, 1, 2]), ("fp32_last_bucket", fp32_opts)]
+    space.append(("tiled_first", [0, 1]))
     if params.max_pts > 32:
-        space.append(("tile_first_bucket", [b for b in (2, 3, 4, 5) if params.max_pts > (16, 32, 64, 96, 128)[b - 1]]
-                      or [5]))
+        tiles = [b for b in (2, 3, 4, 5) if params.max_pts > (16, 32, 64, 96, 128)[b - 1]] or [5]
+        space.append(("tile_first_bucket", tiles))
+        # which buckets are tiled and whether they run before the fork interact: search them together
+        space.append((("joint", "tile_first_bucket", "tiled_first"), [(b, f) for b in tiles for f in (0, 1)]))
     caps = (0, 16, 32, 64, 96, 128, 256)  # lower bound of each bucket
     space += [(("grid_scale", b), [2, 4, 8, 16]) for b in range(7) if params.max_pts > caps[b]]
     t0 = time.perf_counter()
@@ -109,7 +112,12 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
         for key, options in space:
             for opt in options:
                 cand = json.loads(json.dumps(cur))
-                if isinstance(key, tuple):
+                if isinstance(key, tuple) and key[0] == "joint":
+                    if all(cand[k] == o for k, o in zip(key[1:], opt)):
+                        continue
+                    for k, o in zip(key[1:], opt):
+                        cand[k] = o
+                elif isinstance(key, tuple):
                     if cand["grid_scale"][key[1]] == opt:
                         continue
                     cand["grid_scale"][key[1]] = opt

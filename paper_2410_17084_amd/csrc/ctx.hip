@@ -240,6 +240,7 @@ vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
     if (t->grid_scale[b] < 1 || t->grid_scale[b] > 64) return fail(ctx, VGPR_E_INVALID, "grid_scale must be in [1, 64]");
   if (t->tile_first_bucket < 2 || t->tile_first_bucket > 5)
     return fail(ctx, VGPR_E_INVALID, "tile_first_bucket must be in [2, 5]");
+  if (t->tiled_first != 0 && t->tiled_first != 1) return fail(ctx, VGPR_E_INVALID, "tiled_first must be 0 or 1");
   ctx->tune = *t;
   return VGPR_OK;
 }

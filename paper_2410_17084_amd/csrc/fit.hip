@@ -1836,21 +1836,22 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   // Buckets run concurrently: the 96/128-point buckets on side stream 0, the
   // 32/64-point buckets on side stream 1, the 256/512-point buckets on side
   // stream 2, the 16-point bucket (and its FP64 re-solve) on the caller's
-  // stream, joined back before the call returns. Many small voxels fill the
-  // CUs that the few long large-voxel solves leave idle.
+  // stream, joined back before the call returns (with tiled_first, the tiled
+  // buckets run before the fork instead). Many small voxels fill the CUs that
+  // the few long large-voxel solves leave idle.
   st = ensure_aux(ctx);
   if (st != VGPR_OK) return st;
-  VGPR_HIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
-  for (int i = 0; i < vgpr_ctx::kAux; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
   const vgpr_tuning& tu = ctx->tune;
+  // tiled_first: the tiled buckets run alone on the caller's stream before the
+  // fork (their workgroups need whole CUs, which concurrent buckets would hold)
+  const bool tiles_first = tu.streams != 1 && tu.tiled_first != 0;
   auto stream_of = [&](int b) {
-    if (tu.streams == 1) return ctx->stream;
+    if (tu.streams == 1 || (tiles_first && b >= first_tile_bucket(ctx))) return ctx->stream;
     // 256/512-point buckets on their own stream: their workgroups need whole CUs of LDS, so even an
     // empty launch waits for CUs to drain and would hold back the buckets queued behind it
     return b >= 5 ? ctx->aux[2] : (b >= 3 ? ctx->aux[0] : (b >= 1 ? ctx->aux[1] : ctx->stream));
   };
-  for (int b = kNumBuckets - 1; b >= 0; --b) {
-    if (p->max_pts <= (b ? P.bcap[b - 1] : 0)) continue;
+  auto launch_b = [&](int b) -> vgpr_status {
     const bool tiled = b >= first_tile_bucket(ctx);
     const bool wave = wave_ok(b) && b <= tu.wave_last_bucket;
     const bool in_fp32 = fp32 && b <= tu.fp32_last_bucket && !tiled;
@@ -1861,22 +1862,27 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     if (tiled) {
       if (mixed) l.fam = kFamMixed[b];
-      st = launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
-      if (st != VGPR_OK) return st;
-      continue;
+      return launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
     }
-    st = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
-                 : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
-    if (st != VGPR_OK) return st;
-    if (in_fp32) {
-      // FP64 re-solve of this bucket's flagged voxels, on the same stream right after it
-      FitParams R = P;
-      R.mode = 1;
-      Launch lr{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rb_, rlists + (size_t)b * a.n_vox,
-                ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
-      st = launch_bucket<double>(ctx, b, wave, R, a, staged, lr);
-      if (st != VGPR_OK) return st;
-    }
+    vgpr_status s2 = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
+                             : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
+    if (s2 != VGPR_OK || !in_fp32) return s2;
+    // FP64 re-solve of this bucket's flagged voxels, on the same stream right after it
+    FitParams R = P;
+    R.mode = 1;
+    Launch lr{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rb_, rlists + (size_t)b * a.n_vox,
+              ctr + 16 + b, ctr + 24 + b, nullptr, nullptr, a.n_vox, kFam[1][b]};
+    return launch_bucket<double>(ctx, b, wave, R, a, staged, lr);
+  };
+  auto launched = [&](int b) { return p->max_pts > (b ? P.bcap[b - 1] : 0); };
+  if (tiles_first)
+    for (int b = kNumBuckets - 1; b >= first_tile_bucket(ctx); --b)
+      if (launched(b) && (st = launch_b(b)) != VGPR_OK) return st;
+  VGPR_HIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int i = 0; i < vgpr_ctx::kAux; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+  for (int b = kNumBuckets - 1; b >= 0; --b) {
+    if (!launched(b) || (tiles_first && b >= first_tile_bucket(ctx))) continue;
+    if ((st = launch_b(b)) != VGPR_OK) return st;
   }
   for (int i = 0; i < vgpr_ctx::kAux; ++i) {
     VGPR_HIP(ctx, hipEventRecord(ctx->join_ev[i], ctx->aux[i]));

@@ -49,12 +49,12 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
-                ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32)]
+                ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32), ("tiled_first", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,
                 "streams": self.streams, "grid_scale": list(self.grid_scale),
-                "tile_first_bucket": self.tile_first_bucket}
+                "tile_first_bucket": self.tile_first_bucket, "tiled_first": self.tiled_first}
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tuning":
@@ -67,6 +67,7 @@ class Tuning(C.Structure):
         for i in range(7):
             t.grid_scale[i] = gs[i] if i < len(gs) else 4
         t.tile_first_bucket = d.get("tile_first_bucket", 5)
+        t.tiled_first = d.get("tiled_first", 0)
         return t
 
 

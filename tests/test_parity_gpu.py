@@ -550,7 +550,8 @@ def test_tuning_choices(env):
     ov = O.voxelize(xyz, w["voxel_size"])
     prm = parity.oracle_params(w)
     try:
-        for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3, 2, 1]), dict(streams=1, grid_scale=[64] * 7)]:
+        for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3, 2, 1]), dict(streams=1, grid_scale=[64] * 7),
+                       dict(tiled_first=1), dict(tiled_first=1, streams=1)]:
             say("tuning (bit-identical)", change)
             t = dict(default)
             t.update(change)
@@ -568,7 +569,17 @@ def test_tuning_choices(env):
             ctx.set_tuning(vgpr.Tuning.from_dict(t))
             out = ctx.fit_predict(x, gv, p.replace(precision=prec))
             parity.compare_fit(xyz, ov, prm, *out)
-        for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3)):
+        # tiled buckets before the fork or with the others: bit-identical (only the schedule differs)
+        outs = []
+        for tf in (0, 1):
+            say("tuning tiled_first", tf)
+            t = dict(default)
+            t.update(tile_first_bucket=4, tiled_first=tf)
+            ctx.set_tuning(vgpr.Tuning.from_dict(t))
+            outs.append([t_.cpu().numpy() for t_ in ctx.fit_predict(x, gv, p)])
+        for g, r in zip(outs[1], outs[0]):
+            assert np.array_equal(g, r, equal_nan=True)
+        for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3), ("tiled_first", 2)):
             with pytest.raises(vgpr.VgprError):
                 bad = dict(default)
                 bad[key] = val
