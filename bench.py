@@ -253,6 +253,9 @@ def main():
     log(f"device key for cached tuning: {dev_name}")
     tuned = None
     if args.autotune:
+        prior = autotune.load_cached(p, dev_name)
+        if prior:  # refine the cached choices rather than start from the library defaults
+            ctx.set_tuning(vgpr.Tuning.from_dict(prior["tuning"]))
         tuned = autotune.tune(ctx, xyz, vgpr.Voxels(vox.keys, vox.offsets, vox.counts, vox.perm, V, [], 0), p,
                               log=log)
         autotune.save_cached(p, dev_name, tuned)

@@ -96,7 +96,7 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
     base = _time_fit(ctx, xyz, vox, params, out, reps)
     best_ms = base
     log(f"[autotune] baseline {base:.3f} ms {cur}")
-    fp32_opts = [-1, 0, 1, 2] if params.precision in (vgpr.PREC_FP32, vgpr.PREC_MIXED) else [cur["fp32_last_bucket"]]
+    fp32_opts = [-1, 0, 1, 2, 3, 4] if params.precision in (vgpr.PREC_FP32, vgpr.PREC_MIXED) else [cur["fp32_last_bucket"]]
     space = [("streams", [1, 3]), ("wave_last_bucket", [0, 1, 2]), ("fp32_last_bucket", fp32_opts)]
     space.append(("tiled_first", [0, 1]))
     if params.max_pts > 32:
