@@ -20,6 +20,9 @@
 // raised to kPredNoiseFloor s_f^2) with the frame's first max_pts new points
 // (sensor noise) in a staging area of m + max_pts slots per voxel, re-solves
 // Alg. 1 on that set, and the new rows replace the carried ones.
+#include <algorithm>
+#include <vector>
+
 #include "scan.cuh"
 #include "vgpr_internal.h"
 
@@ -689,6 +692,13 @@ vgpr_status vgpr_map_import(vgpr_ctx* ctx, const void* h_buf, size_t buf_bytes, 
     int32_t stored;
     std::memcpy(&stored, b + L.stored + 4 * (size_t)v, 4);
     if (stored < 0 || stored > cap) return bad("a stored point count is outside [0, max_pts]");
+  }
+  {  // the hash table is rebuilt from the keys: they must be distinct and not the empty-slot sentinel
+    std::vector<uint64_t> k((size_t)nv);
+    if (nv > 0) std::memcpy(k.data(), b + L.keys, 8 * (size_t)nv);
+    std::sort(k.begin(), k.end());
+    for (size_t v = 0; v < k.size(); ++v)
+      if (k[v] == kKeySentinel || (v > 0 && k[v] == k[v - 1])) return bad("voxel keys are repeated or invalid");
   }
   auto copy_in = [&](void* dst, size_t off, size_t bytes) {
     return hipMemcpy(dst, b + off, bytes, hipMemcpyHostToDevice) == hipSuccess;

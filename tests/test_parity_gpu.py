@@ -730,7 +730,9 @@ def test_map_export_import_resumes_identically(env, feedback):
     with pytest.raises(vgpr.VgprError) as ei:
         vgpr.Map.load(ctx, data, max_voxels=st["voxels"] - 1)
     assert ei.value.status == vgpr.E_INVALID
-    for bad in (b"XGPRMAP1" + data[8:], data[:len(data) - 5], data[:40]):
+    dup = bytearray(data)
+    dup[88:96] = dup[80:88]  # the second voxel key repeats the first
+    for bad in (b"XGPRMAP1" + data[8:], data[:len(data) - 5], data[:40], bytes(dup)):
         with pytest.raises(vgpr.VgprError) as ei:
             vgpr.Map.load(ctx, bad, max_voxels=160000)
         assert ei.value.status == vgpr.E_INVALID
