@@ -144,6 +144,14 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _f32_dev(t, name: str):
+    """The library reads raw device pointers: inputs must be contiguous float32 GPU tensors."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
 @dataclass
 class Voxels:
     keys: object      # (V,) int64 tensor holding the uint64 key bits
@@ -203,7 +211,7 @@ class Context:
     # -- vgpr_voxelize -------------------------------------------------------
     def voxelize(self, xyz, params: Params, frame_offsets=None, cap_vox: int | None = None) -> Voxels:
         torch = self.torch
-        assert xyz.is_cuda and xyz.dtype == torch.float32 and xyz.is_contiguous()
+        _f32_dev(xyz, "xyz")
         n = xyz.numel() // 3
         dev = xyz.device
         cap = n if cap_vox is None else int(cap_vox)
@@ -225,6 +233,9 @@ class Context:
     # -- vgpr_fit_predict ----------------------------------------------------
     def fit_predict(self, xyz, vox: Voxels, params: Params, noise_var=None, out=None):
         torch = self.torch
+        _f32_dev(xyz, "xyz")
+        if noise_var is not None:
+            _f32_dev(noise_var, "noise_var")
         m = params.grid_side * params.grid_side
         dev = xyz.device
         v = vox.n_vox
@@ -247,6 +258,9 @@ class Context:
         to every tensor it reads or writes; replays read their current contents.
         """
         torch = self.torch
+        _f32_dev(xyz, "xyz")
+        if noise_var is not None:
+            _f32_dev(noise_var, "noise_var")
         m = params.grid_side * params.grid_side
         dev = xyz.device
         v = vox.n_vox
@@ -268,6 +282,7 @@ class Context:
     def gauss_init(self, out, status, grid_side: int, n_r: int, var_floor: float = 1e-8, gauss=None):
         """Initial 3D Gaussians of each n_r x n_r subgrid: (V, n_s^2, 8) float32."""
         torch = self.torch
+        _f32_dev(out, "out")
         v = int(status.shape[0])
         ns = grid_side // n_r if n_r > 0 else 0
         if gauss is None:
@@ -281,6 +296,8 @@ class Context:
         """L_p of Eq. (9) for the scan points against Gaussians in the gauss_init
         layout: (loss, n_valid, value (n,) float32, index (n,) int32)."""
         torch = self.torch
+        _f32_dev(pts, "pts")
+        _f32_dev(gauss, "gauss")
         n = pts.numel() // 3
         g = gauss.reshape(-1, 8) if gauss.numel() else gauss
         ng = gauss.numel() // 8
@@ -386,6 +403,7 @@ class Map:
 
     def update(self, xyz, cap_upd: int | None = None, out=None):
         torch = self.ctx.torch
+        _f32_dev(xyz, "xyz")
         n = xyz.numel() // 3
         m = self.params.grid_side ** 2
         cap = n if cap_upd is None else int(cap_upd)

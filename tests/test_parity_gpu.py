@@ -738,3 +738,18 @@ def test_map_export_import_resumes_identically(env, feedback):
         assert ei.value.status == vgpr.E_INVALID
     a.close()
     b.close()
+
+
+def test_binding_rejects_unsuitable_tensors(env):
+    """The binding hands raw device pointers to the library: non-contiguous,
+    non-float32 or host tensors are refused before any GPU work."""
+    torch, vgpr, ctx = env
+    p = vgpr.default_params(voxel_size=0.5)
+    good = torch.zeros((100, 3), dtype=torch.float32, device="cuda")
+    say("binding input checks")
+    for bad in (good.double(), good.cpu(), good.t().contiguous().t(), good[:, :2]):
+        with pytest.raises(ValueError):
+            ctx.voxelize(bad, p)
+    g = torch.zeros((4, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.structure_loss(good, g.double(), cell_size=1.0)
