@@ -66,7 +66,7 @@ __device__ __forceinline__ void take_min(float v, int k, float* best, int* bk) {
 // it), mean scales, and the largest mean scale among candidates.
 __global__ void __launch_bounds__(256) prepare_kernel(const float4* __restrict__ rows, int64_t ng, int scale_mode,
                                                       float* __restrict__ cen, float* __restrict__ sb,
-                                                      uint32_t* __restrict__ smax) {
+                                                      uint32_t* __restrict__ bmax) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t m = 0u;
   if (k < ng) {
@@ -83,9 +83,24 @@ __global__ void __launch_bounds__(256) prepare_kernel(const float4* __restrict__
     sb[k] = s;
     if (ok) m = float_order(s);
   }
-  // wave max, then one atomic per wave
+  // workgroup max into bmax[block] (a device-wide atomic per wavefront on one address serialised)
   for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-  if (lane_id() == 0 && m) atomicMax(smax, m);
+  __shared__ uint32_t wm[4];
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+}
+
+// The largest mean scale (ordered bits) over the workgroup maxima.
+__global__ void __launch_bounds__(256) max_kernel(const uint32_t* __restrict__ bmax, int64_t nb,
+                                                  uint32_t* __restrict__ smax) {
+  uint32_t m = 0u;
+  for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) m = max(m, bmax[i]);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+  __shared__ uint32_t wm[4];
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *smax = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
 }
 
 // Gaussians in cell order as (x, y, z, S) with their original index, and the
@@ -288,19 +303,22 @@ __global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict
 __global__ void __launch_bounds__(256) bound_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
                                                     uint32_t n_open, const float4* __restrict__ box, int nchunk,
                                                     float* __restrict__ ub) {
-  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_open) return;
+  // one wavefront per open point, its lanes sharing out the chunk boxes
+  const uint32_t o = (uint32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (o >= n_open) return;  // whole wavefronts: o is uniform in a wavefront
+  const int lane = lane_id();
   const int i = fb[o];
   const double x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
   double u = INFINITY;
-  for (int c = 0; c < nchunk; ++c) {
+  for (int c = lane; c < nchunk; c += 64) {
     const float4 lo = box[2 * c], hi = box[2 * c + 1];
     const double fx = fmax(fabs(x - lo.x), fabs(x - hi.x)), fy = fmax(fabs(y - lo.y), fabs(y - hi.y)),
                  fz = fmax(fabs(z - lo.z), fabs(z - hi.z));
     const double d = sqrt(fx * fx + fy * fy + fz * fz) - (double)hi.w;
     u = fmin(u, d + 1e-5 * (fabs(d) + fabs((double)hi.w)) + 1e-7);
   }
-  ub[o] = (float)u + 1e-6f * fabsf((float)u);  // rounded up past the float conversion
+  for (int off = 32; off > 0; off >>= 1) u = fmin(u, __shfl_xor(u, off, 64));
+  if (lane == 0) ub[o] = (float)u + 1e-6f * fabsf((float)u);  // rounded up past the float conversion
 }
 
 // Tiled brute force for the open points: workgroup (bx, by) stages Gaussians
@@ -452,6 +470,7 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
                o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
                o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
                o_box = sub(32 * (size_t)((ng + kBruteChunk - 1) / kBruteChunk) + 32), o_ub = sub(4 * (size_t)n),
+               o_bmax = sub(4 * (size_t)((ng + 255) / 256) + 16),
                o_val = sub(d_value ? 0 : 4 * (size_t)n),
                o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
                o_misc = sub(64);
@@ -475,6 +494,7 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   unsigned long long* bbest = reinterpret_cast<unsigned long long*>(w + o_bb);
   float4* cbox = reinterpret_cast<float4*>(w + o_box);
   float* ubound = reinterpret_cast<float*>(w + o_ub);
+  uint32_t* bmax = reinterpret_cast<uint32_t*>(w + o_bmax);
   float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
   int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
   double* tsum = reinterpret_cast<double*>(w + o_ts);
@@ -485,8 +505,10 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   VGPR_HIP(ctx, hipMemsetAsync(misc, 0, 64, ctx->stream));
   int64_t nc = 0, n_bad = 0;
   if (ng > 0) {
-    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, ctx->stream,
-                       reinterpret_cast<const float4*>(d_gauss), ng, scale_mode, cen, sb, misc);
+    const int64_t nb = (ng + 255) / 256;
+    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const float4*>(d_gauss), ng, scale_mode, cen, sb, bmax);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, ctx->stream, bmax, nb, misc);
     VGPR_HIP(ctx, hipGetLastError());
     st = voxelize_impl(ctx, cen, ng, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, ng, &nc, nullptr, &n_bad, head);
     if (st != VGPR_OK) return st;
@@ -519,8 +541,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
     ProfScope ps(ctx, "structure_loss_brute");
     const unsigned gx = (unsigned)((nvalid + kBruteChunk - 1) / kBruteChunk);
     hipLaunchKernelGGL(chunk_box_kernel, dim3(gx), dim3(256), 0, ctx->stream, G, nvalid, cbox);
-    hipLaunchKernelGGL(bound_kernel, dim3((n_open + 255) / 256), dim3(256), 0, ctx->stream, d_pts, fb, n_open, cbox,
-                       (int)gx, ubound);
+    hipLaunchKernelGGL(bound_kernel, dim3((unsigned)(((int64_t)n_open * 64 + 255) / 256)), dim3(256), 0,
+                       ctx->stream, d_pts, fb, n_open, cbox, (int)gx, ubound);
     const unsigned gy = (unsigned)std::min<int64_t>((n_open + 255) / 256, 16);
     hipLaunchKernelGGL(brute_kernel, dim3(gx, gy), dim3(256), 0, ctx->stream, d_pts, fb, n_open, G, gi, nvalid,
                        cbox, ubound, bbest);
