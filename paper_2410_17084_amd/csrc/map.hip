@@ -6,8 +6,9 @@
 // at dense voxel records: key, stored point count, total arrived count and a
 // converged flag, plus a point pool with max_pts float3 slots per voxel.
 //
-// One frame: voxelize (Alg. S1) -> probe the table to count new voxels (the
-// frame is rejected when they would overflow the map) -> insert and append
+// One frame: voxelize (Alg. S1) -> when the frame's voxels could overflow the
+// map, probe the table to count the new ones (the frame is rejected when they
+// would) -> insert and append
 // points in arrival order up to the cap -> collect the touched voxels that
 // hold >= tau points and are not converged (types (b), (c)) in ascending key
 // order -> solve them from the pool with the per-voxel solver -> mark those
@@ -46,6 +47,7 @@ struct vgpr_map {
   uint8_t* vpred = nullptr;  // mode 1: the voxel holds a prediction (it is in the map)
   void* stage = nullptr;     // mode 1: stacked points, noise, per-update records, fit scratch
   size_t stage_bytes = 0;
+  int64_t host_voxels = 0;   // voxels held, as read back after the last update (host copy)
 };
 
 namespace vgpr {
@@ -525,18 +527,22 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   if (nv == 0) return VGPR_OK;
   if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during map update");
 
-  // count new voxels and reject the frame if they would overflow the map
   st = reserve_pinned(ctx, 64);
   if (st != VGPR_OK) return st;
   unsigned long long* hc = static_cast<unsigned long long*>(ctx->pinned);
-  VGPR_HIP(ctx, hipMemsetAsync(M->counters + 1, 0, sizeof(unsigned long long), ctx->stream));
-  hipLaunchKernelGGL(probe_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, ctx->stream, fkeys, nv,
-                     M->slot_key, M->nslots, M->counters);
-  VGPR_HIP(ctx, hipGetLastError());
-  VGPR_HIP(ctx, hipMemcpyAsync(hc, M->counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
-  VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if ((int64_t)(hc[0] + hc[1]) > M->max_voxels)
-    return fail(ctx, VGPR_E_CAPACITY, "frame would exceed the map's voxel capacity");
+  if (M->host_voxels + nv > M->max_voxels) {
+    // the frame might overflow the map: count its new voxels and reject it if they would
+    // (otherwise even all nv voxels being new fits, and the count is not needed)
+    VGPR_HIP(ctx, hipMemsetAsync(M->counters + 1, 0, sizeof(unsigned long long), ctx->stream));
+    hipLaunchKernelGGL(probe_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, ctx->stream, fkeys, nv,
+                       M->slot_key, M->nslots, M->counters);
+    VGPR_HIP(ctx, hipGetLastError());
+    VGPR_HIP(ctx, hipMemcpyAsync(hc, M->counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if ((int64_t)(hc[0] + hc[1]) > M->max_voxels)
+      return fail(ctx, VGPR_E_CAPACITY, "frame would exceed the map's voxel capacity");
+  }
 
   const int64_t nvb = (nv + kCompactTile - 1) / kCompactTile;
   hipLaunchKernelGGL(insert_kernel, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, ctx->stream, *M, d_xyz, fkeys,
@@ -547,7 +553,9 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
                      uoff, ucnt, uid, ufv);
   VGPR_HIP(ctx, hipGetLastError());
   VGPR_HIP(ctx, hipMemcpyAsync(hc, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipMemcpyAsync(hc + 1, M->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  M->host_voxels = (int64_t)hc[1];
   const int64_t nu = (int64_t)hc[0];
   *h_n_upd = nu;
   if (nu == 0) return VGPR_OK;
@@ -722,6 +730,7 @@ vgpr_status vgpr_map_import(vgpr_ctx* ctx, const void* h_buf, size_t buf_bytes, 
     vgpr_map_destroy(M);
     return fail(ctx, VGPR_E_DEVICE, "copying the serialised map to the device failed");
   }
+  M->host_voxels = nv;
   *out = M;
   return VGPR_OK;
 }
