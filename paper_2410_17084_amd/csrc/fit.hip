@@ -104,9 +104,17 @@ __device__ __forceinline__ float k_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double k_exp(double x) { return exp(x); }
 
 // Pivot reciprocal: the hardware estimate (1 ulp) in FP32, whose elimination error
-// is far above it; IEEE division in FP64.
+// is far above it. In FP64 the hardware estimate refined by two Newton steps
+// (each doubles the correct bits), within an ulp or two of 1/x for a normal
+// positive pivot; a zero or non-finite pivot gives NaN and the voxel fails.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -769,7 +777,7 @@ __global__ void __launch_bounds__(kBlockThreads) fit_block_kernel(FitParams P, F
         __syncthreads();
         const T d = piv[b][0];
         const T yj = piv[b][1];
-        const T inv = (T)1 / d;
+        const T inv = recip(d);
         const T t = a[0] * inv;
         minpiv = d < minpiv ? d : minpiv;
         score += (yj < 0 ? -yj : yj) * inv;
