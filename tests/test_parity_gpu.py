@@ -139,6 +139,45 @@ def test_fit_workloads(env, name, prec):
     assert stats["solved"] > 1000
 
 
+def test_fit_bench_batch_sampled(env):
+    """The timed step at full size: the 64-scan spinning batch (2.55M points) voxelized and fitted in
+    one call each, in FP32 mode, under the launch choices taken from the tuning cache for this
+    device (as the bench does). The voxel arrays are compared in full; outputs for a seeded sample
+    (40 voxels of every scan, and every voxel with more than 64 kept points) against the oracle
+    voxel by voxel."""
+    torch, vgpr, ctx = env
+    from paper_2410_17084_amd import autotune
+    w = configs.WORKLOADS["spin32"]
+    xyz, offs = synth.scan_batch(2, 64, n_beams=w["n_beams"], n_az=w["n_az"])
+    p = parity.gpu_params(vgpr, w, precision=vgpr.PREC_FP32)
+    props = torch.cuda.get_device_properties(0)
+    dev_name = f"{getattr(props, 'gcnArchName', 'gpu').split(':')[0]}x{props.multi_processor_count}cu"
+    default = ctx.tuning().as_dict()
+    tuned = autotune.load_cached(p, dev_name)
+    say("fit 64-scan batch", xyz.shape, tuned["tuning"] if tuned else "library defaults")
+    try:
+        if tuned:
+            ctx.set_tuning(vgpr.Tuning.from_dict(tuned["tuning"]))
+        x = dev(torch, xyz)
+        gv = ctx.voxelize(x, p, frame_offsets=offs)
+        out, axis, status = ctx.fit_predict(x, gv, p)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tuning(vgpr.Tuning.from_dict(default))
+    ov = O.voxelize(xyz, w["voxel_size"], offs)
+    parity.compare_voxelize(ov, gv)
+    r = rng(64)
+    fv = ov["frame_vox"]
+    sample = set()
+    for f in range(len(offs) - 1):
+        lo, hi = int(fv[f]), int(fv[f + 1])
+        sample.update(r.choice(np.arange(lo, hi), size=min(40, hi - lo), replace=False).tolist())
+    sample.update(np.nonzero(np.minimum(ov["counts"], w["max_pts"]) > 64)[0].tolist())
+    stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status, voxels=sorted(sample))
+    print("64-scan batch", len(sample), stats)
+    assert stats["solved"] > 2000
+
+
 def _ragged_voxels(seed, sizes, s=0.5, noise=0.01, tilt=True):
     """One voxel per requested point count, on a noisy (tilted) plane, scattered in space."""
     r = rng(seed)
