@@ -43,11 +43,12 @@ carried rows and noise of the covariance-centred type (c) update, and for
 Eq. (9) the mean over the n points with S-bar the mean of the three scales.
 
 Parity status: every function here is pinned by closed forms, invariants,
-brute force or an independent library routine in tests/test_oracle_pins.py,
-except the per-voxel length-scale rule ``pca_length_scale`` (an extension for
-the large aggregated-map workload that the paper does not define): its
-parity is unpinned against the paper and only checked for the uniform-square
-special case.
+brute force or an independent library routine in tests/test_oracle_pins.py.
+The per-voxel length-scale rule ``pca_length_scale`` (ls_mode 1, for the large
+aggregated-map workload) is not defined by the paper: the rule is a reading of
+this implementation, and what is pinned is that the oracle computes that rule
+(closed forms on lattice rectangles with distinct in-plane variances, the
+uniform square, both clamp edges).
 """
 from __future__ import annotations
 
@@ -278,8 +279,10 @@ def pca_length_scale(eigvals: np.ndarray, voxel_size: float) -> float:
     """Per-voxel length scale for the aggregated-map workload (ls_mode 1).
 
     l = sqrt(3) * sqrt((lambda_mid + lambda_max) / 2), clamped to
-    [0.05 s, 2 s]. For points uniform on a face of side s the in-plane
-    variances are s^2/12, so l = s/2. Not defined by the paper: parity unpinned.
+    [0.05 s, 2 s]. For points uniform on an a x b rectangle the in-plane
+    variances are a^2/12 and b^2/12, so l = sqrt((a^2 + b^2) / 8); for a face of
+    side s that is s/2. Not defined by the paper (a reading of this
+    implementation); the pins check the oracle against that rule.
     """
     s = float(np.float32(voxel_size))
     ell = math.sqrt(3.0) * math.sqrt(max((eigvals[1] + eigvals[2]) / 2.0, 0.0))

@@ -453,3 +453,53 @@ def test_structure_loss_pins_green_on_unmodified_oracle():
 def test_structure_loss_pins_catch_mutant(monkeypatch, name, target, mutant):
     monkeypatch.setattr(O, target, mutant)
     assert _sloss_caught(), f"no pin caught the mutant: {name}"
+
+
+# ---------------------------------------------------------------------------
+# Per-voxel length scale (ls_mode 1): mutants of pca_length_scale
+# ---------------------------------------------------------------------------
+def _ls_variant(mix="midmax", root3=True, lo=0.05, hi=2.0):
+    def f(eigvals, voxel_size):
+        s = float(np.float32(voxel_size))
+        w = np.asarray(eigvals, dtype=np.float64)
+        v = {"midmax": (w[1] + w[2]) / 2.0, "max": w[2], "minmid": (w[0] + w[1]) / 2.0,
+             "sum": w[1] + w[2]}[mix]
+        ell = (np.sqrt(3.0) if root3 else 1.0) * np.sqrt(max(v, 0.0))
+        return min(max(ell, lo * s), hi * s)
+    return f
+
+
+LS_PINS = [
+    lambda: pins.test_pca_length_scale_uniform_square(),
+    lambda: [pins.test_pca_length_scale_rectangle_closed_form(*c) for c in
+             [(0.06, 0.1, 12, 20), (0.1, 0.02, 25, 5), (0.03, 0.09, 7, 40)]],
+    lambda: [pins.test_pca_length_scale_clamp_edges(s) for s in (0.1, 0.2, 1.0)],
+]
+
+
+def _ls_caught():
+    for t in LS_PINS:
+        try:
+            t()
+        except AssertionError:
+            return True
+    return False
+
+
+def test_length_scale_pins_green_on_unmodified_oracle():
+    assert not _ls_caught()
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("largest eigenvalue alone", _ls_variant(mix="max")),
+    ("smallest and middle eigenvalues", _ls_variant(mix="minmid")),
+    ("sum instead of the mean", _ls_variant(mix="sum")),
+    ("sqrt(3) missing", _ls_variant(root3=False)),
+    ("lower clamp edge 0.1 s", _ls_variant(lo=0.1)),
+    ("lower clamp edge 0.01 s", _ls_variant(lo=0.01)),
+    ("upper clamp edge s", _ls_variant(hi=1.0)),
+    ("upper clamp edge 4 s", _ls_variant(hi=4.0)),
+])
+def test_length_scale_pins_catch_mutant(monkeypatch, name, mutant):
+    monkeypatch.setattr(O, "pca_length_scale", mutant)
+    assert _ls_caught(), f"no pin caught the mutant: {name}"

@@ -467,6 +467,75 @@ def test_pca_length_scale_uniform_square():
     assert O.pca_length_scale(fr.eigvals, s) == pytest.approx(s / 2, rel=5e-3)
 
 
+def _lattice_rectangle(a, b, ka, kb, tilt):
+    """ka x kb points at the interval centres of an a x b rectangle, rotated by the
+    orthonormal matrix `tilt` (columns: the two in-plane axes and the normal)."""
+    ia = (np.arange(ka) + 0.5) / ka * a
+    ib = (np.arange(kb) + 0.5) / kb * b
+    U, W = np.meshgrid(ia, ib, indexing="ij")
+    local = np.stack([U.ravel(), W.ravel(), np.zeros(U.size)], 1)
+    return local @ tilt.T + np.array([0.3, -0.2, 0.05])
+
+
+def _rotation(seed):
+    q, _ = np.linalg.qr(rng(seed).normal(size=(3, 3)))
+    return q
+
+
+@pytest.mark.parametrize("a,b,ka,kb", [(0.06, 0.1, 12, 20), (0.1, 0.02, 25, 5), (0.03, 0.09, 7, 40)])
+def test_pca_length_scale_rectangle_closed_form(a, b, ka, kb):
+    """Points on a ka x kb lattice of interval centres of an a x b rectangle (any
+    orientation): the discrete uniform law gives in-plane variances
+    a^2 (1 - 1/ka^2) / 12 and b^2 (1 - 1/kb^2) / 12 and a zero normal variance, so the
+    rule's l = sqrt(3) sqrt((lambda_mid + lambda_max) / 2) is
+    sqrt((a^2 (1 - 1/ka^2) + b^2 (1 - 1/kb^2)) / 8), which tends to sqrt((a^2 + b^2) / 8)
+    for a dense rectangle. a != b separates lambda_mid from lambda_max; the same value
+    reaches the posterior through Alg. 1 with ls_mode 1."""
+    s = 0.1
+    va = a * a * (1.0 - 1.0 / ka ** 2) / 12.0
+    vb = b * b * (1.0 - 1.0 / kb ** 2) / 12.0
+    expect = math.sqrt((a * a * (1.0 - 1.0 / ka ** 2) + b * b * (1.0 - 1.0 / kb ** 2)) / 8.0)
+    assert expect == pytest.approx(math.sqrt(3.0) * math.sqrt((va + vb) / 2.0), rel=1e-14)
+    P = _lattice_rectangle(a, b, ka, kb, _rotation(int(1000 * a + kb)))
+    fr = O.local_frame(P)
+    assert np.sort(fr.eigvals) == pytest.approx(sorted([0.0, va, vb]), abs=1e-15)
+    assert O.pca_length_scale(fr.eigvals, s) == pytest.approx(expect, rel=1e-10)
+    # dense limit of the same rectangle
+    Pd = _lattice_rectangle(a, b, 400, 400, _rotation(5))
+    assert O.pca_length_scale(O.local_frame(Pd).eigvals, s) == pytest.approx(math.sqrt((a * a + b * b) / 8.0),
+                                                                           rel=2e-5)
+    # end to end: the length scale Alg. 1 uses under ls_mode 1
+    prm = O.Params(voxel_size=s, max_pts=10 ** 6, min_pts=3, grid_side=3, ls_mode=1)
+    k = np.floor(P[0] / s).astype(np.int64)
+    res = O.fit_predict_voxel(P[:64].astype(np.float32), O.pack_keys(k[None])[0], prm)
+    ev = O.local_frame(P[:64].astype(np.float32).astype(np.float64)).eigvals
+    assert res["length_scale"] == pytest.approx(math.sqrt(1.5 * (ev[1] + ev[2])), rel=1e-12)
+
+
+@pytest.mark.parametrize("s", [0.1, 0.2, 1.0])
+def test_pca_length_scale_clamp_edges(s):
+    """The clamp [0.05 s, 2 s], s the float32 voxel size: values inside pass unchanged,
+    values outside take the nearer edge, and the edges themselves are reached exactly.
+    The eigenvalues are chosen so that (lambda_mid + lambda_max) / 2 = l^2 / 3 exactly
+    in the rule's formula; lambda_min must not enter."""
+    sf = float(np.float32(s))
+
+    def ell_for(target, lam_min=0.0):
+        half = target * target / 3.0
+        return O.pca_length_scale(np.array([lam_min, 0.5 * half, 1.5 * half]), s)
+
+    for frac in (0.051, 0.3, 0.5, 1.0, 1.99):
+        assert ell_for(frac * sf) == pytest.approx(frac * sf, rel=1e-12)
+        assert ell_for(frac * sf, lam_min=0.25 * (frac * sf) ** 2 / 3.0) == pytest.approx(frac * sf, rel=1e-12)
+    for frac in (1e-4, 0.01, 0.049):
+        assert ell_for(frac * sf) == 0.05 * sf
+    for frac in (2.01, 3.0, 50.0):
+        assert ell_for(frac * sf) == 2.0 * sf
+    assert O.pca_length_scale(np.zeros(3), s) == 0.05 * sf          # a single repeated point
+    # a line segment: lambda_mid = 0
+    assert O.pca_length_scale(np.array([0.0, 0.0, 1.5 * sf * sf]), s) == pytest.approx(1.5 * sf, rel=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Voxel state machine (Sec. 3.3)
 # ---------------------------------------------------------------------------
