@@ -42,7 +42,7 @@ def source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2410_17084_amd", "csrc")
-    files = [os.path.join(csrc, f) for f in ("ctx.hip", "fit.hip", "scan.cuh", "vgpr_internal.h")] + \
+    files = [os.path.join(csrc, f) for f in ("ctx.hip", "fit.hip", "scan.h", "vgpr_internal.h")] + \
         [os.path.join(HERE, "include", "vgpr.h")]
     for f in files:
         h.update(os.path.basename(f).encode())

@@ -37,7 +37,7 @@
 #include <algorithm>
 #include <cfloat>
 
-#include "scan.cuh"
+#include "scan.h"
 #include "vgpr_internal.h"
 
 namespace vgpr {

@@ -24,7 +24,7 @@
 #include <climits>
 #include <cmath>
 
-#include "scan.cuh"
+#include "scan.h"
 #include "vgpr_internal.h"
 
 namespace vgpr {

@@ -24,7 +24,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "scan.cuh"
+#include "scan.h"
 #include "vgpr_internal.h"
 
 struct vgpr_map {

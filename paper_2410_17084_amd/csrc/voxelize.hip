@@ -18,7 +18,7 @@
 #include <algorithm>
 #include <climits>
 
-#include "scan.cuh"
+#include "scan.h"
 #include "vgpr_internal.h"
 
 namespace vgpr {
