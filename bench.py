@@ -32,7 +32,8 @@ from paper_2410_17084_amd import configs, synth  # noqa: E402
 PEAK = {"f32": 157.3, "f64": 78.6}  # TFLOP/s, MI355X vector FP32 / FP64
 HBM_PEAK = 8000.0                   # GB/s
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_spin32_batch64.json")
+TRAFFIC_FILES = {"spin32": os.path.join(HERE, "profiles", "hbm_traffic_spin32_batch64.json"),
+                 "aggregated": os.path.join(HERE, "profiles", "hbm_traffic_aggregated.json")}
 
 
 def source_hash() -> str:
@@ -51,15 +52,16 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(family: str, tuning: dict, precision: str):
+def measured_traffic(workload: str, family: str, tuning: dict, precision: str):
     """HBM bytes per launch of `family` from the stored FETCH_SIZE / WRITE_SIZE readings.
 
     None unless the readings were taken on the current sources with the same
     launch choices and precision.
     """
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(workload)
+    if path is None or not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         d = json.load(fh)
     if d.get("source_hash") != source_hash() or d.get("tuning") != tuning or d.get("precision") != precision:
         return None
@@ -94,6 +96,33 @@ def bucket_of(n: np.ndarray) -> np.ndarray:
     return b
 
 
+def precision_split(n_kept: np.ndarray, solved: np.ndarray, m: int, tuning: dict, precision: str) -> dict:
+    """Share of the step's algorithmic FLOPs computed in each arithmetic type, from
+    the launch choices that ran: in FP32 and MIXED mode the buckets up to
+    fp32_last_bucket that are not tiled run in float (their voxels flagged for
+    re-solve again in double), tiled buckets run FP64 tiles (MIXED: FP32 tiles
+    with split-BF16 query products); everything else runs in double."""
+    b_of = bucket_of(n_kept)
+    fl = voxel_flops(n_kept, m)
+    share = {}
+    for b in range(len(BUCKETS)):
+        sel = solved & (b_of == b)
+        if not sel.any():
+            continue
+        tiled = b >= tuning["tile_first_bucket"]
+        if precision == "fp64":
+            kind = "f64"
+        elif tiled:
+            kind = "f32+bf16" if precision == "mixed" else "f64"
+        else:
+            kind = "f32" if b <= tuning["fp32_last_bucket"] else "f64"
+        share[kind] = share.get(kind, 0.0) + float(fl[sel].sum())
+    tot = sum(share.values()) or 1.0
+    frac = {k: v / tot for k, v in sorted(share.items(), key=lambda kv: -kv[1])}
+    label = " + ".join(f"{k} {100 * v:.0f}%" for k, v in frac.items())
+    return {"dtype": next(iter(frac), "f64"), "flop_share": frac, "label": label}
+
+
 def cpu_baseline(xyz_np: np.ndarray, fo, frame_vox, w: dict, gpu_out, budget_s: float) -> dict:
     """FP64 oracle on the batch's frames in order: voxelize a frame, fit its voxels, until the budget.
 
@@ -109,7 +138,8 @@ def cpu_baseline(xyz_np: np.ndarray, fo, frame_vox, w: dict, gpu_out, budget_s: 
     prm = parity.oracle_params(w)
     solved = reached = frames = points = 0
     spent = 0.0
-    max_mean = max_var = 0.0
+    max_mean = max_var = max_rel = 0.0
+    rel_in = rel_tot = 0
     with threadpool_limits(limits=1):
         for f in range(len(fo) - 1):
             xf = xyz_np[int(fo[f]):int(fo[f + 1])]
@@ -128,6 +158,9 @@ def cpu_baseline(xyz_np: np.ndarray, fo, frame_vox, w: dict, gpu_out, budget_s: 
                                        voxels=range(done))
             max_mean = max(max_mean, stats["max_mean_err"])
             max_var = max(max_var, stats["max_var_err"])
+            max_rel = max(max_rel, stats["max_var_rel_own"])
+            rel_in += stats["queries_var_rel_own_within_tol"]
+            rel_tot += stats["queries_var_rel_own"]
             reached += done
             frames += 1
             points += len(xf)
@@ -139,6 +172,10 @@ def cpu_baseline(xyz_np: np.ndarray, fo, frame_vox, w: dict, gpu_out, budget_s: 
                   f"{reached} voxels ({solved} solved) in {spent:.1f} s, BLAS limited to 1 thread",
         "accuracy": {"voxels_checked": reached, "solved_checked": solved, "max_mean_err_m": max_mean,
                      "max_var_err": max_var, "mean_tol_m": parity.MEAN_TOL, "var_tol": parity.VAR_TOL_REL,
+                     "var_err_reading": "|gpu - oracle| <= var_tol * s_f^2 (prior-normalised), asserted",
+                     "max_var_rel_own": max_rel,
+                     "frac_queries_var_rel_own_within_tol": rel_in / rel_tot if rel_tot else 1.0,
+                     "var_rel_own_reading": "|gpu - oracle| / oracle (own value), reported, not asserted",
                      "pass": True},
     }
 
@@ -155,9 +192,10 @@ def cpu_pool(xyz_np: np.ndarray, fo, w: dict, workers: int, timeout_s: float = 2
         np.save(fp, np.asarray(fo, dtype=np.int64))
         prm = {k: v for k, v in w.items() if isinstance(v, (int, float))}
         try:
+            split = ["--split-voxels"] if len(fo) - 1 < workers else []
             r = subprocess.run([sys.executable, "-m", "oracle.run_frames", "--xyz", xp, "--fo", fp, "--params",
-                                json.dumps(prm), "--workers", str(workers)], cwd=HERE, capture_output=True, text=True,
-                               timeout=timeout_s)
+                                json.dumps(prm), "--workers", str(workers), *split], cwd=HERE, capture_output=True,
+                               text=True, timeout=timeout_s)
         except subprocess.TimeoutExpired:
             log(f"cpu pool exceeded {timeout_s} s; skipped")
             return None
@@ -165,9 +203,11 @@ def cpu_pool(xyz_np: np.ndarray, fo, w: dict, workers: int, timeout_s: float = 2
         log(f"cpu pool failed: {r.stderr[-500:]}")
         return None
     d = json.loads(r.stdout.strip().splitlines()[-1])
+    how = ("the frames voxelized in one process, then interleaved slices of their voxels fitted"
+           if "voxelize_s" in d else "one frame per task, voxelized and fitted")
     return {"value": d["solved"] / d["wall_s"], "unit": "voxel solves/s", "cores": workers, "kind": "oracle",
             "sample": f"all {d['frames']} frames of the batch ({len(xyz_np)} points): oracle voxelize + FP64 fit of "
-                      f"{d['voxels']} voxels ({d['solved']} solved) on {workers} worker processes in "
+                      f"{d['voxels']} voxels ({d['solved']} solved) on {workers} worker processes ({how}) in "
                       f"{d['wall_s']:.1f} s wall ({d['worker_s']:.1f} s of worker time), BLAS limited to 1 thread "
                       "per worker"}
 
@@ -177,9 +217,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["spin32", "batched", "aggregated"], default="spin32",
-                    help="spin32: 32-beam scans (the default step); batched: 128-beam and rosette scans at 1 m "
-                         "voxels, cap 256; aggregated: 10-scan 128-beam map updates at 0.1 m voxels, cap 512, 16x16")
+    ap.add_argument("--workload", choices=["spin32", "batched", "aggregated"], default="aggregated",
+                    help="aggregated: 10-scan 128-beam map updates at 0.1 m voxels, cap 512, 16x16 (the default "
+                         "step); spin32: batches of 32-beam scans; batched: 128-beam and rosette scans at 1 m "
+                         "voxels, cap 256")
+    ap.add_argument("--extra-steps", type=int, default=10,
+                    help="timed steps of each other workload reported beside the headline (0 skips them)")
     ap.add_argument("--frames", type=int, default=None, help="frames per step (default 64 / 16 / 1 by workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default="fp32")
     ap.add_argument("--latency-frames", type=int, default=60)
@@ -332,8 +375,9 @@ def main():
                     "voxels_per_launch": int(sel.sum() / launches_per_step),
                     "algorithmic_bytes_per_launch": float(by[sel].sum() / launches_per_step),
                     "hbm_frac": float(by[sel].sum() / launches_per_step) / per_launch_s / 1e9 / HBM_PEAK}
-            roof["traffic"] = (measured_traffic(dom, ctx.tuning().as_dict(), args.precision)
-                               if args.workload == "spin32" and args.frames == 64 else None)
+            default_frames = {"spin32": 64, "batched": 16, "aggregated": 1}[args.workload]
+            roof["traffic"] = (measured_traffic(args.workload, dom, ctx.tuning().as_dict(), args.precision)
+                               if args.frames == default_frames else None)
         tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
@@ -519,15 +563,25 @@ def main():
         serving = serve_leg(args, vgpr)
         log(f"serving: {serving}")
 
+    split = precision_split(n_kept, solved, m, ctx.tuning().as_dict(), args.precision)
+    extra = {}
+    if args.extra_steps > 0:
+        for name in ("spin32", "batched"):
+            if name != args.workload:
+                extra[name] = extra_leg(args, vgpr, name)
+                log(f"{name}: {extra[name]}")
     rec = {
         "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+bf16"}[args.precision], "data": "synthetic",
+        "vs_baseline": None, "dtype": split["dtype"], "data": "synthetic",
         "config": {"workload": f"{args.workload} batch: {args.frames} frames, {WORKLOAD_DESC[args.workload]} "
                                f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step)",
-                   "frames": args.frames, "precision": args.precision + ("+fp64-resolve" if prec != 2 else ""),
+                   "frames": args.frames, "precision": args.precision,
+                   "arithmetic": split["label"] + " of the algorithmic FLOPs" +
+                                 (", voxels flagged in float re-solved in double" if prec == vgpr.PREC_FP32 else ""),
                    "parallelism": "1 GPU"},
+        "flop_share": split["flop_share"],
         "dense_pts_per_s": dense,
         "tuning": ctx.tuning().as_dict(),
         "solved_per_step": n_solved, "refined_per_step": int(refined.sum()),
@@ -541,9 +595,62 @@ def main():
         "gauss_init": gauss,
         "structure_loss": sloss,
         "roofline": roof, "roofline_isolated": isolated, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
+        "other_workloads": extra,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def extra_leg(args, vgpr, name: str) -> dict:
+    """Throughput of another workload under its cached launch choices (same
+    precision): voxelize + fit_predict of its batch per step, K timed steps."""
+    import torch
+
+    from paper_2410_17084_amd import autotune
+    w = configs.params_for(name)
+    frames = {"spin32": 64, "batched": 16, "aggregated": 1}[name]
+    m = w["grid_side"] ** 2
+    xyz_np, fo = workload_frames(name, frames)
+    prec = {"fp32": vgpr.PREC_FP32, "fp64": vgpr.PREC_FP64, "mixed": vgpr.PREC_MIXED}[args.precision]
+    p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
+    p.precision = prec
+    ctx = vgpr.Context(0)
+    props = torch.cuda.get_device_properties(0)
+    dev_name = f"{getattr(props, 'gcnArchName', 'gpu').split(':')[0]}x{props.multi_processor_count}cu"
+    tuned = autotune.load_cached(p, dev_name)
+    if tuned:
+        ctx.set_tuning(vgpr.Tuning.from_dict(tuned["tuning"]))
+    xyz = torch.from_numpy(xyz_np).cuda()
+    vox = ctx.voxelize(xyz, p, frame_offsets=fo)
+    V = vox.n_vox
+    out = (torch.empty((V, m, 4), dtype=torch.float32, device="cuda"),
+           torch.empty(V, dtype=torch.int8, device="cuda"), torch.empty(V, dtype=torch.uint8, device="cuda"))
+    keys = torch.empty(len(xyz_np), dtype=torch.int64, device="cuda")
+    offs = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+    cnts = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+    perm = torch.empty(len(xyz_np), dtype=torch.int32, device="cuda")
+
+    def step():
+        n = ctypes_voxelize(ctx, vgpr, xyz, p, fo, keys, offs, cnts, perm)
+        ctx.fit_predict(xyz, vgpr.Voxels(keys[:n], offs[:n], cnts[:n], perm, n, [], 0), p, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.extra_steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.extra_steps
+    st = out[2].cpu().numpy()
+    n_kept = np.minimum(cnts[:V].cpu().numpy().astype(np.int64), w["max_pts"])
+    solved = (st & vgpr.ST_SOLVED) != 0
+    ns = int(solved.sum())
+    sp = precision_split(n_kept, solved, m, ctx.tuning().as_dict(), args.precision)
+    ctx.close()
+    return {"solves_per_s": ns / el, "ms_per_step": el * 1e3, "dense_pts_per_s": ns * m / el,
+            "solved_per_step": ns, "points": int(len(xyz_np)), "frames": frames, "steps": args.extra_steps,
+            "arithmetic": sp["label"], "workload": WORKLOAD_DESC[name]}
 
 
 def serve_leg(args, vgpr) -> dict:
@@ -608,8 +715,9 @@ WORKLOAD_DESC = {
               "noise 1e-3",
     "batched": "alternating seeded 128-beam x 1024-azimuth spinning scans and 100k-ray rosette scans (17/23 Hz "
                "petals), voxel 1 m, cap 256, tau 3, 8x8 grid, l 0.5 m, noise 1e-3",
-    "aggregated": "each 10 seeded 128-beam x 1024-azimuth scans along a path with N(0, 0.01 m) pose noise, voxel "
-                  "0.1 m, cap 512, tau 3, 16x16 grid, length scale from PCA, noise 1e-3",
+    "aggregated": "each 10 seeded 128-beam x 1024-azimuth scans 0.05 m apart along a path with N(0, 0.01 m) pose "
+                  "noise, box scene cleared within 2 m (about 1M points, voxels up to the 512 cap), voxel 0.1 m, "
+                  "cap 512, tau 3, 16x16 grid, length scale from PCA, noise 1e-3",
 }
 
 
@@ -625,7 +733,7 @@ def workload_frames(name: str, n_frames: int):
             frames.append(synth.spin_scan(synth.frame_seed(3, k), n_beams=128, n_az=1024, scene=scene) if k % 2 == 0
                           else synth.rosette_scan(synth.frame_seed(3, k), n_pts=100000, frame_index=k, scene=scene))
         else:
-            frames.append(synth.aggregated_scans(synth.frame_seed(5, k), scene=scene))
+            frames.append(synth.aggregated_scans(synth.frame_seed(5, k)))
     offs = np.zeros(n_frames + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(f) for f in frames])
     return np.ascontiguousarray(np.concatenate(frames)), offs

@@ -37,8 +37,9 @@ WORKLOADS = {
     # large aggregated map update: 10 scans of 128 x 1024 with pose noise,
     # voxel 0.1 m, up to 512 points per voxel, length scale from PCA, 16x16 grid.
     "aggregated": dict(
-        desc="aggregated: 10 scans of 128 beams x 1024 azimuths along a path with N(0, 0.01 m) pose noise "
-             "(about 0.9M points), voxel 0.1 m, cap 512, tau 3, 16x16 grid, length scale from PCA",
+        desc="aggregated: 10 scans of 128 beams x 1024 azimuths 0.05 m apart along a path with N(0, 0.01 m) "
+             "pose noise, scene cleared within 2 m (about 1M points, voxels up to the 512 cap), voxel 0.1 m, "
+             "cap 512, tau 3, 16x16 grid, length scale from PCA",
         voxel_size=0.1, max_pts=512, min_pts=3, grid_side=16, signal_var=1.0, length_scale=0.05, noise_var=1e-3,
         converge_var=0.3, ls_mode=1, n_beams=128, n_az=1024),
 }

@@ -600,9 +600,10 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       if (c < n) {
 #pragma unroll
         for (int r = 0; r < QR; ++r) A[r][c] = sf2 * tu[c * nq + qi[r]] * tw[c * nq + qj[r]];
-        T kb;
+        T kb = 0;
         if constexpr (kKInLds) {
-          kb = s_K[wid][c * NMAX + lane];
+          // only data lanes (lane < n <= NMAX) read, so the index stays inside this wavefront's region
+          if (dlane) kb = s_K[wid][c * NMAX + lane];
         } else {
           const T eu = xu - su[c], ew = xw - sw[c];
           kb = sf2 * k_exp(-(eu * eu + ew * ew) * lam);

@@ -297,16 +297,21 @@ def scan_batch(config: int, n_frames: int, first: int = 0, **kw):
     return np.ascontiguousarray(np.concatenate(frames)), offs
 
 
-def aggregated_scans(seed: int, n_scans: int = 10, n_beams: int = 128, n_az: int = 1024, spacing: float = 0.3,
-                     pose_noise: float = 0.01, scene: BoxScene | None = None) -> np.ndarray:
+def aggregated_scans(seed: int, n_scans: int = 10, n_beams: int = 128, n_az: int = 1024, spacing: float = 0.05,
+                     pose_noise: float = 0.01, scene: BoxScene | None = None, clear_radius: float = 2.0) -> np.ndarray:
     """A map-update frame: `n_scans` scans taken along a straight path, concatenated.
 
-    Scan k is taken at start + k * spacing along a seeded heading, with the
-    position perturbed by N(0, pose_noise) m per axis (a registration error),
-    and the same heading as yaw. Seeds: path `seed`, scan k seed + 1 + k.
+    Scan k is taken at start + k * spacing along a seeded heading (0.05 m: a
+    platform at 0.5 m/s scanning at 10 Hz), with the position perturbed by
+    N(0, pose_noise) m per axis (a registration error), and the same heading as
+    yaw. Without an explicit scene the box world is cleared only within
+    `clear_radius` of the origin, so that surfaces 2-3 m from the sensor are hit
+    by every scan and their 0.1 m voxels fill to several hundred points (about
+    1M points per frame, voxels up to and beyond a 512-point cap). Seeds: path
+    `seed`, scan k seed + 1 + k.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
-    scene = scene if scene is not None else box_scene()
+    scene = scene if scene is not None else box_scene(clear_radius=clear_radius)
     heading = rng.uniform(0, 2 * np.pi)
     start = rng.uniform(-1.0, 1.0, size=2) - 0.5 * (n_scans - 1) * spacing * np.array([math.cos(heading),
                                                                                         math.sin(heading)])

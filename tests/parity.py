@@ -7,6 +7,10 @@ Tolerances (stated per output):
   float32 grid);
 - predicted coordinate (the posterior mean): |gpu - oracle| <= 1e-4 m;
 - predicted variance: |gpu - oracle| <= 1e-3 * s_f^2 (the prior variance);
+  the error relative to the variance's own value, |gpu - oracle| / oracle, is
+  reported beside it (maximum, and the share of queries within 1e-3) but not
+  asserted: near the data the posterior variance approaches the noise floor,
+  where FP32 rounding alone exceeds 1e-3 of it;
 - value axis: equal unless the oracle or the GPU flags the decision as a
   near-tie, where the oracle is re-evaluated with the GPU's axis;
 - status bits SOLVED / BELOW_TAU / CAPPED: equal; CONVERGED: equal unless the
@@ -39,6 +43,33 @@ def as_u64(t) -> np.ndarray:
     return t.cpu().numpy().view(np.uint64)
 
 
+class OwnRel:
+    """Variance error relative to the oracle's own value, |gpu - oracle| / oracle,
+    accumulated over queries (queries whose oracle variance is not positive are
+    counted apart: their relative error is undefined)."""
+
+    def __init__(self):
+        self.max = 0.0
+        self.within = 0
+        self.total = 0
+        self.nonpos = 0
+
+    def add(self, g: np.ndarray, e: np.ndarray) -> None:
+        pos = e > 0
+        self.nonpos += int((~pos).sum())
+        if pos.any():
+            rel = np.abs(g[pos] - e[pos]) / e[pos]
+            self.max = max(self.max, float(rel.max()))
+            self.within += int((rel <= VAR_TOL_REL).sum())
+            self.total += int(pos.sum())
+
+    def stats(self) -> dict:
+        return {"max_var_rel_own": self.max,
+                "frac_var_rel_own_within_tol": (self.within / self.total) if self.total else 1.0,
+                "queries_var_rel_own": self.total, "queries_var_rel_own_within_tol": self.within,
+                "queries_var_nonpositive": self.nonpos}
+
+
 def compare_voxelize(ov: dict, gv) -> None:
     V = len(ov["keys"])
     assert gv.n_vox == V, (gv.n_vox, V)
@@ -60,6 +91,7 @@ def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, vox
     idx = range(V) if voxels is None else voxels
     max_mean = 0.0
     max_var = 0.0
+    own = OwnRel()
     n_solved = 0
     n_refined = 0
     n_tie = 0
@@ -93,13 +125,14 @@ def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, vox
         ev = np.abs(g[:, 3] - e[:, 3]).max()
         max_mean = max(max_mean, em)
         max_var = max(max_var, ev)
+        own.add(g[:, 3], e[:, 3])
         assert em <= MEAN_TOL, (v, em, r["n"])
         assert ev <= VAR_TOL_REL * prm.signal_var, (v, ev, r["n"])
         mv = e[:, 3].max()
         if abs(mv - prm.converge_var) > VAR_TOL_REL * prm.signal_var:
             assert bool(st & O.ST_CONVERGED) == bool(mv <= prm.converge_var), (v, mv)
-    return {"max_mean_err": max_mean, "max_var_err": max_var, "solved": n_solved, "refined": n_refined,
-            "axis_ties": n_tie}
+    return {"max_mean_err": max_mean, "max_var_err": max_var, **own.stats(), "solved": n_solved,
+            "refined": n_refined, "axis_ties": n_tie}
 
 
 def compare_fit_rotated(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, voxels=None) -> dict:

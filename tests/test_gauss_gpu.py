@@ -76,7 +76,18 @@ def test_gauss_paper_grid_end_to_end(env):
     g, _ = _same_inputs(ctx, out, status, 9, 3, 1e-8)
     ov = O.voxelize(xyz, w["voxel_size"])
     prm = parity.oracle_params(w)
-    of = O.fit_predict(xyz, ov, prm, axes=axis.cpu().numpy())
+    of = O.fit_predict(xyz, ov, prm)
+    # the GPU's value axis replaces the oracle's only where the decision is a flagged near tie
+    gax = axis.cpu().numpy().astype(np.int64)
+    gst = status.cpu().numpy().astype(np.int64)
+    differ = np.flatnonzero((of["status"] & O.ST_SOLVED).astype(bool) & (gax != of["axis"]))
+    for v in differ:
+        assert of["ambiguous"][v] or (gst[v] & O.ST_AXIS_TIE), (v, gax[v], of["axis"][v])
+    if len(differ):
+        fix = O.fit_predict(xyz, ov, prm, voxels=differ, axes=gax)
+        of["out"][differ] = fix["out"][differ]
+        of["status"][differ] = fix["status"][differ]
+    say("gauss end to end: GPU axis taken on", len(differ), "flagged near-tie voxels")
     ref = O.gauss_init(of["out"], of["status"], 9, 3, float(np.float32(1e-8)))
     nan = np.isnan(ref)
     assert np.array_equal(np.isnan(g), nan)

@@ -379,20 +379,12 @@ def test_map_update_matches_oracle_state_machine(env):
         say("map frame", k, len(xyz))
         keys, out, axis, status = gm.update(dev(torch, xyz))
         ref = om.update(xyz)
-        assert np.array_equal(parity.as_u64(keys), ref["keys"])
-        o = out.cpu().numpy().astype(np.float64)
-        ax = axis.cpu().numpy()
-        stt = status.cpu().numpy()
-        for i, key in enumerate(ref["keys"]):
-            a = ref["axis"][i]
-            for bit in (O.ST_SOLVED, O.ST_CAPPED):
-                assert bool(stt[i] & bit) == bool(ref["status"][i] & bit)
-            if ax[i] != a:
-                continue  # near-tie axis: covered by the fit tests
-            u, wv = O.PARAM_AXES[a]
-            assert np.array_equal(o[i][:, u].astype(np.float32), ref["out"][i][:, u].astype(np.float32))
-            assert np.abs(o[i][:, a] - ref["out"][i][:, a]).max() <= parity.MEAN_TOL
-            assert np.abs(o[i][:, 3] - ref["out"][i][:, 3]).max() <= parity.VAR_TOL_REL
+        # keys exact; SOLVED / CAPPED / BELOW_TAU / CONVERGED equal; an axis mismatch only on a
+        # flagged near tie; rows within the fit tolerances
+        _, stt, n_cmp = _compare_map_frame(ref, keys, out, axis, status, prm.signal_var, prm.converge_var)
+        say("map frame", k, "compared", n_cmp, "of", len(ref["keys"]), "converged",
+            int(((stt & O.ST_CONVERGED) != 0).sum()))
+        assert n_cmp >= 0.9 * int(((ref["status"] & O.ST_SOLVED) != 0).sum())
         st = gm.stats()
         assert st["voxels"] == len(om.points)
         assert st["points"] == sum(len(v) for v in om.points.values())
@@ -478,6 +470,81 @@ def test_map_feedback_matches_oracle(env, prec, frame_mode):
         assert st["converged"] == sum(om.converged.values())
     say("feedback map", prec, "compared", n_cmp_total, "type (c) re-solves", n_resolved)
     assert n_resolved >= 200
+
+
+def test_map_feedback_multiframe_no_resync_fp64(env):
+    """Update mode 1 over five frames with no re-synchronisation: the GPU map and the
+    oracle's feedback map each carry their own float32 rows from frame to frame.
+
+    Drift bound: in FP64 each re-solve agrees to ~1e-7 m, but the carried rows are
+    rounded to float32 on both sides, and world coordinates of tens of metres have an
+    ulp of up to 3.8e-6 m, so a carried row may differ by one ulp; the carried rows
+    enter with their posterior variance as noise (floored at 1e-6 s_f^2), so the
+    re-solve nearly interpolates them and passes such a difference on with a gain
+    of about one. Five frames therefore stay within 5 x 3.8e-6 m, far inside the
+    1e-4 m mean tolerance (and the variances, which depend on coordinates only
+    through the kernel, within 1e-3 s_f^2). A voxel whose value axis was a flagged
+    near tie, or whose CONVERGED decision fell within the tolerance of eta, may take
+    a different branch on the two sides; it is followed no further."""
+    torch, vgpr, ctx = env
+    w = dict(configs.params_for("paper_stream"), max_pts=48, converge_var=2e-4)
+    prm = parity.oracle_params(w)
+    p = parity.gpu_params(vgpr, w, precision=vgpr.PREC_FP64)
+    om = O.VoxelMap(prm, feedback=True)
+    gm = vgpr.Map(ctx, p, max_voxels=200000, feedback=True)
+    diverged = set()
+    n_resolved = n_cmp = 0
+    max_mean = max_var = 0.0
+    for k in range(5):
+        xyz = synth.spin_scan(synth.frame_seed(5, k), n_beams=32, n_az=1024, position=(0.05 * k, 0.02 * k),
+                              yaw=0.05 * k)
+        say("feedback map without re-sync, FP64, frame", k, len(xyz))
+        before = set(om.pred)
+        keys, out, axis, status = gm.update(dev(torch, xyz))
+        ref = om.update(xyz)
+        gkeys = parity.as_u64(keys).tolist()
+        o = out.cpu().numpy().astype(np.float64)
+        ax = axis.cpu().numpy()
+        stt = status.cpu().numpy()
+        gi = {key: i for i, key in enumerate(gkeys)}
+        ri = {key: i for i, key in enumerate(ref["keys"].tolist())}
+        # a key updated on one side only must belong to a voxel that already diverged
+        for key in set(gi) ^ set(ri):
+            assert key in diverged, key
+        for key, i in ri.items():
+            if key in diverged or key not in gi:
+                continue
+            j = gi[key]
+            rs = int(ref["status"][i])
+            for bit in (O.ST_SOLVED, O.ST_CAPPED, O.ST_BELOW_TAU):
+                assert bool(stt[j] & bit) == bool(rs & bit), (k, key, stt[j], rs)
+            if not rs & O.ST_SOLVED:
+                continue
+            a = int(ref["axis"][i])
+            if ax[j] != a:
+                assert (stt[j] & O.ST_AXIS_TIE) or (rs & O.ST_AXIS_TIE), (k, key)
+                diverged.add(key)
+                continue
+            u, wv = O.PARAM_AXES[a]
+            e = ref["out"][i]
+            assert np.array_equal(o[j][:, u].astype(np.float32), e[:, u].astype(np.float32)), (k, key)
+            assert np.array_equal(o[j][:, wv].astype(np.float32), e[:, wv].astype(np.float32)), (k, key)
+            em = np.abs(o[j][:, a] - e[:, a]).max()
+            ev = np.abs(o[j][:, 3] - e[:, 3]).max()
+            assert em <= parity.MEAN_TOL and ev <= parity.VAR_TOL_REL * prm.signal_var, (k, key, em, ev)
+            max_mean, max_var = max(max_mean, em), max(max_var, ev)
+            mv = e[:, 3].max()
+            if bool(stt[j] & O.ST_CONVERGED) != bool(rs & O.ST_CONVERGED):
+                assert abs(mv - prm.converge_var) <= parity.VAR_TOL_REL * prm.signal_var, (k, key, mv)
+                diverged.add(key)
+            n_cmp += 1
+            n_resolved += key in before
+    say("no re-sync: compared", n_cmp, "type (c) re-solves", n_resolved, "diverged", len(diverged),
+        "max mean err", max_mean, "max var err", max_var)
+    assert n_resolved >= 200
+    assert len(diverged) <= 0.02 * n_cmp
+    # the drift bound above: five frames of one-ulp differences in the carried rows
+    assert max_mean <= 5 * (3.9e-6 + 1e-6), max_mean
 
 
 def test_map_feedback_closed_form_frames(env):
