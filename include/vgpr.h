@@ -215,6 +215,29 @@ VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t
                              uint8_t* d_status);
 
 /*
+ * vgpr_fit_predict_noalloc - vgpr_fit_predict for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, outputs and results as
+ * vgpr_fit_predict (the same kernels run), but its scratch comes from a fixed
+ * device array of 64 MiB, one per GPU, held until the process ends; the call
+ * itself allocates nothing (no hipMalloc / hipFree, no stream or event
+ * creation: the context made its side streams at vgpr_create). The caller
+ * still owns every input and output buffer.
+ * Limit: the call's scratch (about 480 bytes per voxel + 16 bytes per point,
+ * plus the tiled solvers' areas when max_pts > 128 or in MIXED mode) must fit
+ * in the 64 MiB; otherwise it returns VGPR_E_CAPACITY and enqueues nothing.
+ * Concurrency: every call on one GPU (from any context) shares that GPU's
+ * array, which keeps the last call's contents; calls whose work overlaps on
+ * one GPU race, so callers serialise them (one stream, or events).
+ * Asynchronous like vgpr_fit_predict.
+ */
+VGPR_API vgpr_status vgpr_fit_predict_noalloc(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts,
+                                              const uint64_t* d_keys, const int32_t* d_offsets,
+                                              const int32_t* d_counts, const int32_t* d_perm, int64_t n_vox,
+                                              const float* d_noise_var, const vgpr_params* params,
+                                              float* d_out, int8_t* d_axis, uint8_t* d_status);
+
+/*
  * Device-resident voxel map (the global map C of Alg. S1 with the voxel
  * states of Sec. 3.3). Holds up to max_voxels voxels, each with up to
  * params.max_pts points stored in arrival order; later points of a full voxel

@@ -1,10 +1,41 @@
 // Context, workspace, error reporting and launch timing of the Voxel-GPR library.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "vgpr_internal.h"
 
 namespace vgpr {
+
+// Fixed device scratch of vgpr_fit_predict_noalloc: a file-scope device array,
+// one copy per GPU, held until the process ends. Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): vgpr_create looks up each device's address once, with that device
+// current, and every use goes through that address.
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+// Address of this device's fixed scratch (the current device must be `device`).
+static hipError_t fixed_scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 vgpr_status fail(vgpr_ctx* ctx, vgpr_status s, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -183,12 +214,24 @@ vgpr_status vgpr_create(int device, void* hip_stream, size_t hbm_budget_bytes, v
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return create_fail(VGPR_E_DEVICE, "hipDeviceGetAttribute(multiprocessor count)", e);
+  void* fixed = nullptr;
+  e = fixed_scratch_address(device, &fixed);
+  if (e != hipSuccess) return create_fail(VGPR_E_DEVICE, "hipGetSymbolAddress(fixed scratch)", e);
   vgpr_ctx* c = new (std::nothrow) vgpr_ctx();
   if (!c) return create_fail(VGPR_E_NOMEM, "out of host memory", hipSuccess);
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = hbm_budget_bytes;
   c->cu_count = cus;
+  c->fixed_scratch = fixed;
+  // the side streams exist from the start, so that a call of the no-allocation
+  // entry point never creates them
+  if (ensure_aux(c) != VGPR_OK) {
+    const std::string msg = c->last_error;
+    vgpr_destroy(c);
+    create_error = msg;
+    return VGPR_E_DEVICE;
+  }
   *out = c;
   return VGPR_OK;
 }

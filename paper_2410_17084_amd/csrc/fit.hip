@@ -1914,6 +1914,35 @@ extern "C" vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64
   return vgpr::fit_predict_impl(ctx, a, params, 0);
 }
 
+// No-allocation variant: the same launches, with the scratch carved from the
+// context device's fixed scratch array (its address looked up at vgpr_create).
+extern "C" vgpr_status vgpr_fit_predict_noalloc(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts,
+                                                const uint64_t* d_keys, const int32_t* d_offsets,
+                                                const int32_t* d_counts, const int32_t* d_perm, int64_t n_vox,
+                                                const float* d_noise_var, const vgpr_params* params, float* d_out,
+                                                int8_t* d_axis, uint8_t* d_status) {
+  using namespace vgpr;
+  if (!ctx) return VGPR_E_INVALID;
+  vgpr_status st = check_params(ctx, params);
+  if (st != VGPR_OK) return st;
+  if (!ctx->fixed_scratch || !ctx->aux[0]) return fail(ctx, VGPR_E_DEVICE, "context has no fixed scratch");
+  if (n_vox < 0 || n_vox >= (int64_t(1) << 31) || n_pts < 0 || n_pts >= (int64_t(1) << 31))
+    return fail(ctx, VGPR_E_INVALID, "n_vox and n_pts must be in [0, 2^31)");
+  const size_t need = fit_work_bytes(ctx, n_vox, n_pts, params);
+  if (need > kFixedScratchBytes)
+    return fail(ctx, VGPR_E_CAPACITY,
+                "scratch of " + std::to_string(need) + " bytes exceeds the fixed scratch of " +
+                    std::to_string(kFixedScratchBytes) + " bytes (fewer voxels or points, or max_pts <= 128 "
+                    "outside MIXED mode, keep it within)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
+  FitArgs a{d_xyz, n_pts, d_keys, d_offsets, d_counts, d_perm, d_noise_var, n_vox, d_out, d_axis, d_status};
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;  // timing events would be created on demand
+  st = fit_predict_impl(ctx, a, params, 0, static_cast<char*>(ctx->fixed_scratch));
+  ctx->profiling = prof;
+  return st;
+}
+
 // ---------------------------------------------------------------------------
 // Captured fit_predict: the same launches recorded once as a HIP graph and
 // replayed. The graph owns its scratch, so later calls that grow the context

@@ -19,6 +19,8 @@ constexpr int64_t kKeyBias = int64_t(1) << 20;
 constexpr int64_t kKeyAxisLimit = (int64_t(1) << 20) - 1;
 constexpr uint64_t kKeySentinel = ~uint64_t(0);
 constexpr int kMaxPtsLimit = 512;   // largest cap the tiled solver supports
+// Size of the fixed device scratch of vgpr_fit_predict_noalloc (one array per GPU).
+constexpr size_t kFixedScratchBytes = size_t(64) << 20;
 constexpr int kMaxGridSide = 16;
 
 // Size buckets of the per-voxel solver: a voxel with n kept points runs in the
@@ -68,6 +70,7 @@ struct vgpr_ctx {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kAux] = {nullptr, nullptr, nullptr};
   bool profiling = false;
+  void* fixed_scratch = nullptr;  // this device's copy of the fixed scratch array (kFixedScratchBytes)
   std::map<std::string, vgpr::ProfFamily> prof;
   std::vector<hipEvent_t> event_pool;
 };

@@ -21,7 +21,7 @@ PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
 # every entry point include/vgpr.h declares
 SYMBOLS = [
     "vgpr_params_default", "vgpr_status_str", "vgpr_create", "vgpr_destroy", "vgpr_set_stream",
-    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_map_create", "vgpr_map_create_ex", "vgpr_map_export", "vgpr_map_import",
+    "vgpr_last_error", "vgpr_workspace_bytes", "vgpr_voxelize", "vgpr_fit_predict", "vgpr_fit_predict_noalloc", "vgpr_map_create", "vgpr_map_create_ex", "vgpr_map_export", "vgpr_map_import",
     "vgpr_map_destroy", "vgpr_map_update", "vgpr_map_stats", "vgpr_profile_enable", "vgpr_profile_read",
     "vgpr_set_tuning", "vgpr_get_tuning", "vgpr_fit_graph_create", "vgpr_graph_launch", "vgpr_graph_destroy",
     "vgpr_gauss_init", "vgpr_structure_loss",
@@ -106,6 +106,7 @@ def load():
         "vgpr_voxelize": (C.c_int, [vp, vp, i64, P(i64), i32, P(Params), vp, vp, vp, vp, i64, P(i64), P(i64),
                                     P(i64)]),
         "vgpr_fit_predict": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
+        "vgpr_fit_predict_noalloc": (C.c_int, [vp, vp, i64, vp, vp, vp, vp, i64, vp, P(Params), vp, vp, vp]),
         "vgpr_map_create": (C.c_int, [vp, P(Params), i64, P(vp)]),
         "vgpr_map_create_ex": (C.c_int, [vp, P(Params), i64, C.c_int, P(vp)]),
         "vgpr_map_export": (C.c_int, [vp, vp, sz, P(sz)]),
@@ -249,6 +250,23 @@ class Context:
                                        _ptr(vox.perm), v, _ptr(noise_var), C.byref(params), _ptr(o), _ptr(ax),
                                        _ptr(stt))
         self._check(st, "vgpr_fit_predict")
+        return o[:v], ax[:v], stt[:v]
+
+    def fit_predict_noalloc(self, xyz, vox: Voxels, params: Params, out, noise_var=None):
+        """vgpr_fit_predict_noalloc: the same call on the fixed device scratch. `out` is
+        the caller's (out, axis, status) tensors, at least n_vox rows each."""
+        _f32_dev(xyz, "xyz")
+        if noise_var is not None:
+            _f32_dev(noise_var, "noise_var")
+        o, ax, stt = out
+        v = vox.n_vox
+        m = params.grid_side * params.grid_side
+        if o.shape[0] < v or ax.shape[0] < v or stt.shape[0] < v or o.shape[1] != m:
+            raise ValueError("out tensors hold fewer than n_vox rows or the wrong grid size")
+        st = self.lib.vgpr_fit_predict_noalloc(self.h, _ptr(xyz), xyz.numel() // 3, _ptr(vox.keys),
+                                               _ptr(vox.offsets), _ptr(vox.counts), _ptr(vox.perm), v,
+                                               _ptr(noise_var), C.byref(params), _ptr(o), _ptr(ax), _ptr(stt))
+        self._check(st, "vgpr_fit_predict_noalloc")
         return o[:v], ax[:v], stt[:v]
 
     def fit_graph(self, xyz, vox: Voxels, params: Params, noise_var=None, out=None) -> "Graph":
