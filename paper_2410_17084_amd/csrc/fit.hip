@@ -358,6 +358,33 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0u;
 }
 
+// Longest-first order of one tiled bucket's slots: a counting sort by kept point count,
+// descending, in one workgroup. The tiled solvers hand out voxels in this order, so the
+// largest solves start first and the last ones to start are the shortest (list
+// scheduling by longest processing time). Slots with equal counts may come in any order;
+// every voxel is solved the same way whatever its position.
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) order_kernel(const SlotRec* __restrict__ recs,
+                                                              const uint32_t* __restrict__ count,
+                                                              int32_t* __restrict__ order) {
+  __shared__ uint32_t start[kMaxPtsLimit + 1];
+  const int items = (int)*count;
+  for (int i = threadIdx.x; i <= kMaxPtsLimit; i += kOrderThreads) start[i] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < items; i += kOrderThreads) atomicAdd(&start[recs[i].fr.n], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = kMaxPtsLimit; k >= 0; --k) {
+      const uint32_t h = start[k];
+      start[k] = run;
+      run += h;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < items; i += kOrderThreads) order[atomicAdd(&start[recs[i].fr.n], 1u)] = i;
+}
+
 // ---------------------------------------------------------------------------
 // 3. NaN rows of voxels below tau (one wavefront per voxel, coalesced rows)
 // ---------------------------------------------------------------------------
@@ -881,6 +908,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
                                                                 const float4* __restrict__ staged,
                                                                 const uint32_t* __restrict__ count,
                                                                 uint32_t* __restrict__ next,
+                                                                const int32_t* __restrict__ order,
                                                                 double* __restrict__ scratch) {
   constexpr int NB = NPAD / kTile;
   constexpr int LD = NPAD + 2;  // row stride of the row block, in doubles
@@ -915,8 +943,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
       s_maxvar = 0u;
     }
     __syncthreads();
-    const int item = s_item;
-    if (item >= cnt_items) break;
+    if (s_item >= cnt_items) break;
+    const int item = order ? order[s_item] : s_item;  // slot of the voxel
     const SlotRec r = recs[item];
     const FrameRec& fr = r.fr;
     const RotRec* rot = rots ? rots + item : nullptr;
@@ -1218,6 +1246,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
                                                                       const float4* __restrict__ staged,
                                                                       const uint32_t* __restrict__ count,
                                                                       uint32_t* __restrict__ next,
+                                                                      const int32_t* __restrict__ order,
                                                                       double* __restrict__ scratch) {
   constexpr int NB = NPAD / kTile;
   constexpr int NT = NB * (NB + 1) / 2;  // lower data tiles
@@ -1266,8 +1295,8 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
       s_maxvar = 0u;
     }
     __syncthreads();
-    const int item = s_item;
-    if (item >= cnt_items) break;
+    if (s_item >= cnt_items) break;
+    const int item = order ? order[s_item] : s_item;  // slot of the voxel
     const SlotRec r = recs[item];
     const FrameRec& fr = r.fr;
     const RotRec* rot = rots ? rots + item : nullptr;
@@ -1714,9 +1743,10 @@ void launch_tile_kernel(int npad, dim3 g, dim3 t, hipStream_t s, const FitParams
   case NP:                                                                                                   \
     if (MIXED)                                                                                               \
       hipLaunchKernelGGL(fit_tile_mixed_kernel<NP>, g, t, 0, s, P, io, l.recs, l.rots, staged, l.count, l.next,     \
-                         scratch);                                                                            \
+                         l.slots, scratch);                                                                   \
     else                                                                                                     \
-      hipLaunchKernelGGL(fit_tile_kernel<NP>, g, t, 0, s, P, io, l.recs, l.rots, staged, l.count, l.next, scratch); \
+      hipLaunchKernelGGL(fit_tile_kernel<NP>, g, t, 0, s, P, io, l.recs, l.rots, staged, l.count, l.next, l.slots,  \
+                         scratch);                                                                            \
     break;
   switch (npad) {
     VGPR_TILE_CASE(64)
@@ -1871,6 +1901,11 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     if (tiled) {
       if (mixed) l.fam = kFamMixed[b];
+      // largest voxels first: the bucket's (otherwise unused) re-solve list holds the order
+      int32_t* order = rlists + (size_t)b * a.n_vox;
+      hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, l.count, order);
+      VGPR_HIP(ctx, hipGetLastError());
+      l.slots = order;
       return launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
     }
     vgpr_status s2 = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
