@@ -579,7 +579,8 @@ def main():
                                f"({len(xyz_np)} points, {V} voxels, {n_solved} solved per step)",
                    "frames": args.frames, "precision": args.precision,
                    "arithmetic": split["label"] + " of the algorithmic FLOPs" +
-                                 (", voxels flagged in float re-solved in double" if prec == vgpr.PREC_FP32 else ""),
+                                 (", float voxels with small pivots refined by one FP64 step of alpha"
+                                  if prec == vgpr.PREC_FP32 else ""),
                    "parallelism": "1 GPU"},
         "flop_share": split["flop_share"],
         "dense_pts_per_s": dense,
@@ -707,6 +708,7 @@ def serve_leg(args, vgpr) -> dict:
 
 FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
     [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS] + \
+    ["refine_f32_n16"] + \
     [f"fit_mix_n{c}" for c in BUCKETS] + ["gauss_init"]
 
 

@@ -71,7 +71,8 @@ enum {
   VGPR_ST_SOLVED = 1,       /* fitted and predicted */
   VGPR_ST_BELOW_TAU = 2,    /* fewer than min_pts kept points: not solved (Sec. 3.3 type (a)) */
   VGPR_ST_CAPPED = 4,       /* more than max_pts points; the first max_pts in order were kept */
-  VGPR_ST_REFINED = 8,      /* FP32 solve flagged by the refinement score, re-solved in FP64 */
+  VGPR_ST_REFINED = 8,      /* an FP32 solve whose alpha took one FP64 refinement step (small
+                               pivots or amplified rounding), or which was re-solved in FP64 */
   VGPR_ST_FACTOR_FAIL = 16, /* a non-positive pivot in the FP32 factorisation (then re-solved in
                                FP64); in FP64 mode, the FP64 factorisation failed (rows are NaN) */
   VGPR_ST_CONVERGED = 32,   /* max predicted variance <= converge_var (Sec. 3.3 type (d)) */
@@ -80,9 +81,14 @@ enum {
 
 /* Arithmetic of the posterior (kernel entries and factorisation). */
 enum {
-  VGPR_PREC_FP32 = 0,  /* voxels of up to 16 points: FP32 build and LDL^T, and those whose
-                          refinement score exceeds refine_threshold are re-solved in FP64;
-                          larger voxels run in FP64 directly */
+  VGPR_PREC_FP32 = 0,  /* buckets up to the tuning's fp32_last_bucket (by default voxels of up
+                          to 16 points): FP32 build and LDL^T; a voxel whose n s_f^2 / min
+                          pivot exceeds cond_threshold, or whose refinement score
+                          sum_j |y_j| / d_j exceeds refine_threshold, takes one FP64 residual
+                          refinement step of alpha = (K + S)^-1 f~ with the FP32 factor and
+                          its mean from K*^T alpha in FP64 (16-point shape; larger FP32
+                          shapes re-solve such voxels in FP64), a failed FP32 factor is
+                          re-solved in FP64 (status REFINED); larger voxels run in FP64 */
   VGPR_PREC_MIXED = 1, /* buckets below tile_first_bucket as in FP32 mode; larger voxels: FP32
                           kernel build and tiled Cholesky on the FP32 matrix cores, the query
                           (cross-covariance) tile products in split BF16 (hi x hi + hi x lo +
@@ -119,9 +125,9 @@ typedef struct {
                              centroid + u e1 + w e2 + mean v (noiseless planes are reproduced
                              exactly in any orientation) */
   int32_t precision;      /* VGPR_PREC_* */
-  float refine_threshold; /* FP32 mode: re-solve in FP64 when sum_j |y_j| / d_j exceeds this */
+  float refine_threshold; /* FP32 / MIXED: refine in FP64 when sum_j |y_j| / d_j exceeds this */
   float converge_var;     /* eta: converged when the max predicted variance <= eta */
-  float cond_threshold;   /* MIXED mode: refine alpha in FP64 when n s_f^2 / min pivot exceeds this */
+  float cond_threshold;   /* FP32 / MIXED: refine alpha in FP64 when n s_f^2 / min pivot exceeds this */
 } vgpr_params;
 
 /* Fill *p with the paper's defaults (see above), FP32 precision. */
@@ -223,7 +229,7 @@ VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t
  * itself allocates nothing (no hipMalloc / hipFree, no stream or event
  * creation: the context made its side streams at vgpr_create). The caller
  * still owns every input and output buffer.
- * Limit: the call's scratch (about 480 bytes per voxel + 16 bytes per point,
+ * Limit: the call's scratch (about 510 bytes per voxel + 16 bytes per point,
  * plus the tiled solvers' areas when max_pts > 128 or in MIXED mode) must fit
  * in the 64 MiB; otherwise it returns VGPR_E_CAPACITY and enqueues nothing.
  * Concurrency: every call on one GPU (from any context) shares that GPU's

@@ -151,7 +151,7 @@ vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p) {
   if (p->frame_mode != 0 && p->frame_mode != 1) return fail(ctx, VGPR_E_INVALID, "frame_mode must be 0 or 1");
   if (p->precision != VGPR_PREC_FP32 && p->precision != VGPR_PREC_FP64 && p->precision != VGPR_PREC_MIXED)
     return fail(ctx, VGPR_E_INVALID, "unknown precision");
-  if (p->precision == VGPR_PREC_MIXED && !(p->cond_threshold > 0.f))
+  if (p->precision != VGPR_PREC_FP64 && !(p->cond_threshold > 0.f))
     return fail(ctx, VGPR_E_INVALID, "cond_threshold must be > 0");
   return VGPR_OK;
 }

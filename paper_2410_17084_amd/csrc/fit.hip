@@ -55,7 +55,8 @@ struct FitParams {
   int m;            // nq * nq
   int ls_mode;
   int frame_mode;   // 0 world value axis, 1 PCA-rotated frame
-  int mode;         // 0 = FP32 first pass (flags), 1 = FP64 re-solve pass, 2 = FP64 only
+  int mode;         // 0 = FP32 first pass (flags), 1 = FP64 re-solve pass, 2 = FP64 only,
+                    // 3 = FP32 pass with one FP64 refinement of alpha (flagged voxels)
   int bcap[kNumBuckets];  // bucket capacities
   float sf2;
   float noise;
@@ -404,8 +405,8 @@ __global__ void __launch_bounds__(256) nan_kernel(FitParams P, float* __restrict
 // Status of a solved (or flagged) voxel; lane / thread 0 only.
 __device__ __forceinline__ void finish_voxel(const FitParams& P, const FitArgs& io, int v, int slot, int cnt,
                                              int axes, bool failed, bool flag, float maxvar, int32_t* rlist,
-                                             uint32_t* rcount) {
-  uint8_t st = VGPR_ST_SOLVED;
+                                             uint32_t* rcount, bool refined = false) {
+  uint8_t st = VGPR_ST_SOLVED | (refined ? VGPR_ST_REFINED : 0);
   if (cnt > P.cap) st |= VGPR_ST_CAPPED;
   if ((axes >> 6) & 1) st |= VGPR_ST_AXIS_TIE;
   if (flag) {
@@ -483,10 +484,71 @@ __device__ __forceinline__ float4 make_row(const FitParams& P, const FrameRec& f
   return out_row(fr.axes & 3, (fr.axes >> 2) & 3, (float)fhat, gu, gw, vv);
 }
 
+// One FP64 refinement step of alpha = (K + S)^-1 f~ with the FP32 factor K + S = L D L^T
+// of the wave solver (lane i holds d_i and y_i = (L^-1 f~)_i, column j of the unit lower L
+// is sL[j * NMAX + i], the data points in double are xd[0 | NMAX | 2 NMAX + i]):
+//   alpha0 = L^-T D^-1 y,  r = f~ - (K + S) alpha0 (kernel entries in double),
+//   alpha = alpha0 + L^-T D^-1 L^-1 r,
+// then mean_q - mu = k*_q^T alpha in double for this lane's query rows (Eq. (3)).
+template <int NMAX, int QR>
+__device__ __forceinline__ void refine_mean(const FitParams& P, const FrameRec& fr, const double* __restrict__ xd,
+                            const float* __restrict__ sL, int n, int lane, double dl, double yl, double nzl,
+                            const float* gu, const float* gw, double* meanr) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool dl_ = lane < n;
+  const double sf2 = (double)P.sf2, lam = fr.lam;
+  // back substitution x = L^-T v for v held one value per lane
+  auto back = [&](double v) {
+    double acc = 0.0, x = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      const double xk = bcast(v - acc, k);  // lane k's sum over rows below k is complete
+      if (lane == k) x = xk;
+      if (lane < k) acc += (double)sL[lane * NMAX + k] * xk;
+    }
+    return x;
+  };
+  double alpha = back(dl_ ? yl / dl : 0.0);
+  // residual of (K + S) alpha = f~ in double
+  double rr = 0.0;
+  if (dl_) {
+    const double ui = xd[lane], wi = xd[NMAX + lane];
+    rr = xd[2 * NMAX + lane] - nzl * alpha;
+    for (int c = 0; c < n; ++c) {
+      const double ac = bcast(alpha, c);
+      const double du = ui - xd[c], dw = wi - xd[NMAX + c];
+      rr -= sf2 * exp(-(du * du + dw * dw) * lam) * ac;
+    }
+  } else {
+    for (int c = 0; c < n; ++c) (void)bcast(alpha, c);  // every lane takes part in the broadcasts
+  }
+  // forward substitution w = L^-1 r, then D^-1 and the back substitution
+  double w = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double wj = bcast(rr, j);  // lane j's value is final at step j
+    if (lane == j) w = wj;
+    if (lane > j && lane < n) rr -= (double)sL[j * NMAX + lane] * wj;
+  }
+  alpha += back(dl_ ? w / dl : 0.0);
+  // mean of this lane's query rows from alpha (one row at a time: few registers on this rare path)
+#pragma unroll
+  for (int r = 0; r < QR; ++r) {
+    const double qu = (double)gu[r] - fr.anc_u, qw = (double)gw[r] - fr.anc_w;
+    double acc = 0.0;
+    for (int c = 0; c < n; ++c) {
+      const double ac = bcast(alpha, c);
+      const double du = qu - xd[c], dw = qw - xd[NMAX + c];
+      acc += sf2 * exp(-(du * du + dw * dw) * lam) * ac;
+    }
+    meanr[r] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2a. wave solver: one voxel per wavefront, n <= min(NMAX, 64), m <= 64
 // ---------------------------------------------------------------------------
-template <typename T, int NMAX, int QR>
+template <typename T, int NMAX, int QR, bool REF = false>
 __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, FitArgs io,
                                                                 const SlotRec* __restrict__ recs,
                                                                 const RotRec* __restrict__ rots,
@@ -494,13 +556,23 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
                                                                 const int32_t* __restrict__ slots,
                                                                 const uint32_t* __restrict__ count,
                                                                 int32_t* __restrict__ rlist,
-                                                                uint32_t* __restrict__ rcount) {
+                                                                uint32_t* __restrict__ rcount,
+                                                                int32_t* __restrict__ flist,
+                                                                uint32_t* __restrict__ fcount) {
   constexpr bool kKInLds = NMAX <= 32;       // K from its upper triangle through LDS
   constexpr int kWaves = kWaveThreads / 64;
   constexpr int NQ = QR == 1 ? 8 : (QR == 2 ? 12 : 16);  // largest grid side for QR query rows per lane
+  // REF: the FP32 pass over flagged voxels with one FP64 refinement step of alpha, which
+  // keeps the float factor in the kernel-matrix region once K has been read. The first
+  // FP32 pass of the 16-point shape hands those voxels to it and keeps its registers
+  // (larger shapes re-solve them in FP64: their refinement would spill).
+  static_assert(!REF || (sizeof(T) == 4 && NMAX == 16), "refinement pass: FP32, up to 16 points");
+  constexpr bool kRefine = REF;
+  constexpr bool kHandOff = sizeof(T) == 4 && NMAX == 16 && !REF;
   __shared__ T s_xu[kWaves][NMAX + NQ], s_xw[kWaves][NMAX + NQ];
   __shared__ T s_tab[kWaves][2 * NQ * NMAX];
   __shared__ T s_K[kWaves][kKInLds ? NMAX * NMAX : 1];
+  __shared__ double s_xd[kWaves][kRefine ? 3 * NMAX : 1];  // data points (u, w, f~) in double
   const int wid = threadIdx.x >> 6;
   const int lane = lane_id();
   // wavefront-uniform indices (scalar registers): record loads become scalar loads
@@ -555,6 +627,11 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       xw = (T)dw;
       fv = (T)df;
       nz = (T)pt.w;
+      if constexpr (kRefine) {
+        s_xd[wid][lane] = du;
+        s_xd[wid][NMAX + lane] = dw;
+        s_xd[wid][2 * NMAX + lane] = df;
+      }
     }
     // this lane's query points q = lane + 64 r (r < QR, q < m): row i, column j of the grid
     float gu[QR], gwv[QR];
@@ -653,12 +730,21 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       mean[r] = 0;
     }
     T minpiv = (T)FLT_MAX, score = 0;
+    T dself = 1, yself = 0;  // this lane's pivot d_l and y_l
+    T* __restrict__ sL = s_K[wid];  // FP32 pass: column j of the unit factor L at sL[j * NMAX + i]
     for (int j = 0; j < n; ++j) {
       const T cjB = B[0];
       const T d = bcast(cjB, j);
       const T y = bcast(fy, j);  // y_j = (L^-1 f~)_j, final once step j is reached
       const T inv = recip(d);
       const T tB = cjB * inv;
+      if constexpr (kRefine) {
+        if (lane == j) {
+          dself = d;
+          yself = y;
+        }
+        if (lane > j && lane < n) sL[j * NMAX + lane] = tB;  // K was read from this region before step 0
+      }
 #pragma unroll
       for (int r = 0; r < QR; ++r) {
         const T cjA = A[r][0];
@@ -687,21 +773,36 @@ __global__ void __launch_bounds__(kWaveThreads) fit_wave_kernel(FitParams P, Fit
       }
     }
     const bool failed = !(minpiv > (T)0) || !isfinite((double)score);
-    const bool flag = P.mode == 0 && (failed || score > (T)P.refine_thr);
+    // FP32 pass: a voxel whose smallest pivot is small against n s_f^2 (or whose rounding is
+    // amplified, score sum_j |y_j| / d_j) refines alpha in FP64 here; a failed factor, or a
+    // flagged voxel of a solver shape that keeps no factor, is re-solved in FP64 afterwards
+    const bool want = (P.mode == 0 || P.mode == 3) && !failed &&
+                      ((double)n * (double)P.sf2 > (double)P.cond_thr * (double)minpiv || score > (T)P.refine_thr);
+    const bool refine = kRefine && want;
+    const bool to_ref = P.mode == 0 && kHandOff && want;               // -> the refinement pass
+    const bool to_fp64 = P.mode == 0 && (failed || (want && !kHandOff));  // -> the FP64 re-solve
+    const bool flag = to_ref || to_fp64;
+    double meanr[QR];
+    if constexpr (kRefine) {
+      if (refine) refine_mean<NMAX, QR>(P, fr, s_xd[wid], sL, n, lane, (double)dself, (double)yself, (double)nz,
+                                        gu, gwv, meanr);
+    }
     float mv_lane = 0.f;
 #pragma unroll
     for (int r = 0; r < QR; ++r) {
       const int q = lane + 64 * r;
       if (!flag && q < P.m) {
         const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var[r] > (T)0 ? var[r] : (T)0);
-        const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + (double)mean[r];
+        const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + (refine ? meanr[r] : (double)mean[r]);
         reinterpret_cast<float4*>(io.out)[(size_t)v * P.m + q] = make_row(P, fr, rot, fh, gu[r], gwv[r], vv);
         mv_lane = fmaxf(mv_lane, failed ? 0.f : vv);
       }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mv_lane = fmaxf(mv_lane, __shfl_xor(mv_lane, d, 64));
-    if (lane == 0) finish_voxel(P, io, v, slots ? slots[it] : it, cnt, fr.axes, failed, flag, mv_lane, rlist, rcount);
+    if (lane == 0)
+      finish_voxel(P, io, v, slots ? slots[it] : it, cnt, fr.axes, failed, flag, mv_lane, to_ref ? flist : rlist,
+                   to_ref ? fcount : rcount, refine);
   }
 }
 
@@ -1002,18 +1103,26 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
       }
       __syncthreads();
       const int jend = data ? I : nbd;
+      // operand fragment of L(J,J)^-1 for this wavefront's quarter of X, fetched one step ahead
+      // (the fetch of step J + 1 is in flight during step J's updates and barriers)
+      double wfn[8];
+      if (wid < 4 && jend > 0) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) wfn[s] = Wt[(((wid & 1) * 8 + s) << 6) + lane];
+      }
       for (int J = 0; J < jend; ++J) {
         // finish tile J: X = A(I,J) L(J,J)^-T, one 16 x 16 quarter on each of
         // wavefronts 0-3, into the tile buffer (the row block is still being read)
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
         const int a = (wid >> 1) & 1, b = wid & 1;
         if (wid < 4) {
-          const double* __restrict__ W = Wt + (size_t)J * kTileDoubles;
-          double wf[8];
 #pragma unroll
-          for (int s = 0; s < 8; ++s) wf[s] = W[((b * 8 + s) << 6) + lane];
+          for (int s = 0; s < 8; ++s) acc = mfma_f64(rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4], wfn[s], acc);
+          if (J + 1 < jend) {
+            const double* __restrict__ W = Wt + (size_t)(J + 1) * kTileDoubles;
 #pragma unroll
-          for (int s = 0; s < 8; ++s) acc = mfma_f64(rb[(a * 16 + l16) * LD + J * kTile + 4 * s + l4], wf[s], acc);
+            for (int s = 0; s < 8; ++s) wfn[s] = W[((b * 8 + s) << 6) + lane];
+          }
 #pragma unroll
           for (int k = 0; k < 4; ++k) xb[(a * 16 + l4 + 4 * k) * kXS + b * 16 + l16] = acc[k];
         }
@@ -1650,6 +1759,7 @@ const char* const kFam[3][kNumBuckets] = {
     {"refine_f64_n16", "refine_f64_n32", "refine_f64_n64", "refine_f64_n96", "refine_f64_n128", "refine_f64_n256",
      "refine_f64_n512"},
     {"fit_f64_n16", "fit_f64_n32", "fit_f64_n64", "fit_f64_n96", "fit_f64_n128", "fit_f64_n256", "fit_f64_n512"}};
+const char* const kFamRefine = "refine_f32_n16";
 const char* const kFamMixed[kNumBuckets] = {"fit_mix_n16", "fit_mix_n32", "fit_mix_n64", "fit_mix_n96",
                                             "fit_mix_n128", "fit_mix_n256", "fit_mix_n512"};
 
@@ -1666,20 +1776,22 @@ struct Launch {
   uint32_t* rcount;
   int64_t max_items;
   const char* fam;
+  int32_t* flist = nullptr;   // FP32 pass: voxels for the refinement pass
+  uint32_t* fcount = nullptr;
 };
 
-template <typename T, int NMAX, int QR>
+template <typename T, int NMAX, int QR, bool REF = false>
 vgpr_status launch_wave(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const float4* staged,
                         const Launch& l) {
   static int per_cu = -1;
-  if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX, QR>, kWaveThreads);
+  if (per_cu < 0) per_cu = occupancy(fit_wave_kernel<T, NMAX, QR, REF>, kWaveThreads);
   int64_t grid = (int64_t)per_cu * ctx->cu_count * l.grid_scale / 4;
   const int64_t need = (l.max_items + kWaveThreads / 64 - 1) / (kWaveThreads / 64);
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   ProfScope ps(ctx, l.fam, l.stream);
-  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX, QR>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P, io,
-                     l.recs, l.rots, staged, l.slots, l.count, l.rlist, l.rcount);
+  hipLaunchKernelGGL((fit_wave_kernel<T, NMAX, QR, REF>), dim3((unsigned)grid), dim3(kWaveThreads), 0, l.stream, P,
+                     io, l.recs, l.rots, staged, l.slots, l.count, l.rlist, l.rcount, l.flist, l.fcount);
   VGPR_HIP(ctx, hipGetLastError());
   return VGPR_OK;
 }
@@ -1800,6 +1912,15 @@ vgpr_status launch_bucket(vgpr_ctx* ctx, int b, bool wave, const FitParams& P, c
   }
 }
 
+// The refinement pass of the FP32 16-point wave bucket over the voxels its first pass flagged.
+vgpr_status launch_refine(vgpr_ctx* ctx, const FitParams& P, const FitArgs& io, const float4* staged,
+                          const Launch& l) {
+  const int qr = P.m <= 64 ? 1 : (P.m <= 128 ? 2 : 4);
+  if (qr == 1) return launch_wave<float, 16, 1, true>(ctx, P, io, staged, l);
+  if (qr == 2) return launch_wave<float, 16, 2, true>(ctx, P, io, staged, l);
+  return launch_wave<float, 16, 4, true>(ctx, P, io, staged, l);
+}
+
 }  // namespace
 
 size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const vgpr_params* p) {
@@ -1809,7 +1930,7 @@ size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const v
     if (p->max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b, mixed));
   const size_t rot_bytes = p->frame_mode == 1 ? Carver::round(sizeof(RotRec) * (size_t)n_vox * kNumBuckets) : 0;
   return rot_bytes + Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
-         Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
+         Carver::round(sizeof(int32_t) * (size_t)n_vox) + 2 * Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
          Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
 }
 
@@ -1833,7 +1954,9 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   float4* staged = cv.take<float4>((size_t)a.n_pts);
   int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
-  uint32_t* ctr = cv.take<uint32_t>(64);  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch
+  int32_t* flists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
+  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch, [32,39) refinement counts, [40,47) fetch
+  uint32_t* ctr = cv.take<uint32_t>(64);
   double* tile_scratch[kNumBuckets] = {};
   const bool mixed = p->precision == VGPR_PREC_MIXED;
   for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b)
@@ -1908,9 +2031,22 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
       l.slots = order;
       return launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
     }
+    const bool refine_pass = in_fp32 && wave && b == 0;  // the wave shape that hands voxels to the refinement pass
+    if (refine_pass) {
+      l.flist = flists + (size_t)b * a.n_vox;
+      l.fcount = ctr + 32 + b;
+    }
     vgpr_status s2 = in_fp32 ? launch_bucket<float>(ctx, b, wave, Pb, a, staged, l)
                              : launch_bucket<double>(ctx, b, wave, Pb, a, staged, l);
     if (s2 != VGPR_OK || !in_fp32) return s2;
+    if (refine_pass) {
+      // FP32 again over the voxels with small pivots, each with one FP64 refinement step of alpha
+      FitParams F = P;
+      F.mode = 3;
+      Launch lf{stream_of(b), tu.grid_scale[b], recs + (size_t)b * a.n_vox, rb_, flists + (size_t)b * a.n_vox,
+                ctr + 32 + b, ctr + 40 + b, nullptr, nullptr, a.n_vox, kFamRefine};
+      if ((s2 = launch_refine(ctx, F, a, staged, lf)) != VGPR_OK) return s2;
+    }
     // FP64 re-solve of this bucket's flagged voxels, on the same stream right after it
     FitParams R = P;
     R.mode = 1;

@@ -296,6 +296,32 @@ def test_fit_aggregated_workload_sampled(env):
     assert (st & vgpr.ST_SOLVED).astype(bool).sum() == int((np.minimum(counts, 512) >= 3).sum())
 
 
+@pytest.mark.parametrize("nq", [8, 16])
+def test_fit_fp32_refinement_pass(env, nq):
+    """FP32 mode: the 16-point wave bucket hands voxels with small pivots to a second FP32 pass
+    that takes one FP64 refinement step of alpha with the float factor. With a conditioning
+    threshold of 1 every solved voxel of the bucket goes through it (REFINED set, outputs within
+    the tolerances); with both thresholds out of reach none does (unrefined FP32 means may then
+    exceed 1e-4 m, which is what the thresholds are for: only the bits are checked there)."""
+    torch, vgpr, ctx = env
+    w = dict(configs.params_for("spin32"), grid_side=nq)
+    xyz = synth.spin_scan(synth.frame_seed(2, 7))
+    ov = O.voxelize(xyz, w["voxel_size"])
+    small = np.flatnonzero((np.minimum(ov["counts"], w["max_pts"]) >= w["min_pts"]) &
+                           (np.minimum(ov["counts"], w["max_pts"]) <= 16))
+    for cond, thr, expect in ((1.0, 40.0, True), (1e30, 1e30, False)):
+        say("fp32 refinement pass, grid", nq, "cond threshold", cond, "refine threshold", thr)
+        gv, (out, axis, status) = run_fit(env, xyz, w, precision=vgpr.PREC_FP32, cond_threshold=cond,
+                                          refine_threshold=thr)
+        st = status.cpu().numpy()
+        ref_bits = (st[small] & vgpr.ST_REFINED) != 0
+        assert ref_bits.all() if expect else not ref_bits.any(), (int(ref_bits.sum()), len(small))
+        if expect:
+            stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status, voxels=small)
+            print("every small voxel refined, grid", nq, stats)
+            assert stats["solved"] >= 0.9 * len(small)
+
+
 @pytest.mark.parametrize("cap,tau,nq", [(20, 5, 3), (128, 10, 9), (64, 1, 16), (7, 7, 1)])
 def test_fit_cap_tau_grid(env, cap, tau, nq):
     xyz = synth.spin_scan(synth.frame_seed(2, 1), n_beams=16, n_az=1024)
