@@ -101,7 +101,7 @@ def precision_split(n_kept: np.ndarray, solved: np.ndarray, m: int, tuning: dict
     the launch choices that ran: in FP32 and MIXED mode the buckets up to
     fp32_last_bucket that are not tiled run in float (their voxels flagged for
     re-solve again in double), tiled buckets run FP64 tiles (MIXED: FP32 tiles
-    with split-BF16 query products); everything else runs in double."""
+    and FP32 query products); everything else runs in double."""
     b_of = bucket_of(n_kept)
     fl = voxel_flops(n_kept, m)
     share = {}
@@ -113,7 +113,7 @@ def precision_split(n_kept: np.ndarray, solved: np.ndarray, m: int, tuning: dict
         if precision == "fp64":
             kind = "f64"
         elif tiled:
-            kind = "f32+bf16" if precision == "mixed" else "f64"
+            kind = "f32" if precision == "mixed" else "f64"
         else:
             kind = "f32" if b <= tuning["fp32_last_bucket"] else "f64"
         share[kind] = share.get(kind, 0.0) + float(fl[sel].sum())
@@ -221,6 +221,8 @@ def main():
                     help="aggregated: 10-scan 128-beam map updates at 0.1 m voxels, cap 512, 16x16 (the default "
                          "step); spin32: batches of 32-beam scans; batched: 128-beam and rosette scans at 1 m "
                          "voxels, cap 256")
+    ap.add_argument("--no-precision-forms", dest="precision_forms", action="store_false",
+                    help="skip the FP32 / FP64 / MIXED comparison on the batched workload at 0.2, 0.5, 1.0 m")
     ap.add_argument("--extra-steps", type=int, default=10,
                     help="timed steps of each other workload reported beside the headline (0 skips them)")
     ap.add_argument("--frames", type=int, default=None, help="frames per step (default 64 / 16 / 1 by workload)")
@@ -570,6 +572,7 @@ def main():
             if name != args.workload:
                 extra[name] = extra_leg(args, vgpr, name)
                 log(f"{name}: {extra[name]}")
+    forms = precision_leg(args, vgpr) if args.precision_forms else None
     rec = {
         "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -597,6 +600,7 @@ def main():
         "structure_loss": sloss,
         "roofline": roof, "roofline_isolated": isolated, "kernels": kernels, "cpu_baseline": cpu, "serving": serving,
         "other_workloads": extra,
+        "precision_forms": forms,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
@@ -652,6 +656,76 @@ def extra_leg(args, vgpr, name: str) -> dict:
     return {"solves_per_s": ns / el, "ms_per_step": el * 1e3, "dense_pts_per_s": ns * m / el,
             "solved_per_step": ns, "points": int(len(xyz_np)), "frames": frames, "steps": args.extra_steps,
             "arithmetic": sp["label"], "workload": WORKLOAD_DESC[name]}
+
+
+def precision_leg(args, vgpr) -> dict:
+    """The three arithmetic forms on the batched workload (128-beam and rosette scans, cap 256,
+    8x8 grid) at voxel sizes 0.2, 0.5 and 1.0 m (length scale half a voxel): solves/s of
+    voxelize + fit_predict per step under each form's cached launch choices, and the largest
+    error of each output against the FP64 oracle on a seeded sample of voxels (every voxel
+    above 128 points, every refined voxel up to 100, and 150 others)."""
+    import torch
+
+    from oracle import vgpr_oracle as O
+    from paper_2410_17084_amd import autotune
+    from tests import parity
+    frames = 16
+    xyz_np, fo = workload_frames("batched", frames)
+    xyz = torch.from_numpy(xyz_np).cuda()
+    props = torch.cuda.get_device_properties(0)
+    dev_name = f"{getattr(props, 'gcnArchName', 'gpu').split(':')[0]}x{props.multi_processor_count}cu"
+    out = {"what": "batched workload (16 frames: 128x1024 spinning + 100k rosette scans), cap 256, tau 3, 8x8 "
+                   "grid, l = s/2; errors: max |mean - oracle| (m), max |var - oracle| / s_f^2, max "
+                   "|var - oracle| / oracle, on a seeded sample"}
+    rng = np.random.Generator(np.random.PCG64(2024))
+    for s in (0.2, 0.5, 1.0):
+        w = configs.params_for("batched", voxel_size=s, length_scale=s / 2)
+        m = w["grid_side"] ** 2
+        ov = O.voxelize(xyz_np, w["voxel_size"], fo)
+        row = {}
+        for prec_name, prec in (("fp32", vgpr.PREC_FP32), ("fp64", vgpr.PREC_FP64), ("mixed", vgpr.PREC_MIXED)):
+            p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
+            p.precision = prec
+            ctx = vgpr.Context(0)
+            tuned = autotune.load_cached(p, dev_name)
+            if tuned:
+                ctx.set_tuning(vgpr.Tuning.from_dict(tuned["tuning"]))
+            vox = ctx.voxelize(xyz, p, frame_offsets=fo)
+            V = vox.n_vox
+            res = (torch.empty((V, m, 4), dtype=torch.float32, device="cuda"),
+                   torch.empty(V, dtype=torch.int8, device="cuda"), torch.empty(V, dtype=torch.uint8, device="cuda"))
+            for _ in range(args.warmup):
+                ctx.voxelize(xyz, p, frame_offsets=fo)
+                ctx.fit_predict(xyz, vox, p, out=res)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps = max(args.extra_steps, 1)
+            for _ in range(steps):
+                v2 = ctx.voxelize(xyz, p, frame_offsets=fo)
+                ctx.fit_predict(xyz, v2, p, out=res)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            st = res[2].cpu().numpy()
+            cnt = vox.counts.cpu().numpy().astype(np.int64)
+            solved = (st & vgpr.ST_SOLVED) != 0
+            big = np.flatnonzero(solved & (np.minimum(cnt, w["max_pts"]) > 128))
+            refd = np.flatnonzero(solved & ((st & vgpr.ST_REFINED) != 0))[:100]
+            rest = np.flatnonzero(solved)
+            pick = np.union1d(np.union1d(big, refd), rng.choice(rest, size=min(150, len(rest)), replace=False))
+            stats = parity.compare_fit(xyz_np, ov, parity.oracle_params(w), *res, voxels=pick, strict=False)
+            ns = int(solved.sum())
+            row[prec_name] = {"solves_per_s": ns / el, "ms_per_step": el * 1e3, "solved_per_step": ns,
+                              "refined_per_step": int(((st & vgpr.ST_REFINED) != 0).sum()),
+                              "arithmetic": precision_split(np.minimum(cnt, w["max_pts"]), solved, m,
+                                                            ctx.tuning().as_dict(), prec_name)["label"],
+                              "sample_voxels": int(len(pick)), "max_mean_err_m": stats["max_mean_err"],
+                              "max_var_err_prior": stats["max_var_err"], "max_var_rel_own": stats["max_var_rel_own"],
+                              "sample_voxels_outside_tolerance": stats["outside_tolerance"],
+                              "within_tolerance": stats["outside_tolerance"] == 0}
+            ctx.close()
+            log(f"precision form s={s} {prec_name}: {row[prec_name]}")
+        out[f"s={s:g}"] = row
+    return out
 
 
 def serve_leg(args, vgpr) -> dict:

@@ -90,13 +90,13 @@ enum {
                           shapes re-solve such voxels in FP64), a failed FP32 factor is
                           re-solved in FP64 (status REFINED); larger voxels run in FP64 */
   VGPR_PREC_MIXED = 1, /* buckets below tile_first_bucket as in FP32 mode; larger voxels: FP32
-                          kernel build and tiled Cholesky on the FP32 matrix cores, the query
-                          (cross-covariance) tile products in split BF16 (hi x hi + hi x lo +
-                          lo x hi) with FP32 accumulation, the mean from K*^T alpha in FP64
-                          with alpha = (K + S)^-1 f~ from the FP32 factor and, when
-                          n s_f^2 / min pivot exceeds cond_threshold or the refinement score
-                          sum_j |y_j| / d_j exceeds refine_threshold, one FP64 residual
-                          refinement step of alpha (status REFINED) */
+                          kernel build and tiled Cholesky on the FP32 matrix cores, L^-1 formed
+                          from the FP32 factor, var = s_f^2 - |L^-1 k*_q|^2 as one FP32 matrix
+                          product, the mean from K*^T alpha in FP64 with alpha = (K + S)^-1 f~
+                          from the FP32 factor and, when n s_f^2 / min pivot exceeds
+                          cond_threshold or the refinement score sum_j |y_j| / d_j exceeds
+                          refine_threshold, two FP64 residual refinement steps of alpha
+                          (status REFINED) */
   VGPR_PREC_FP64 = 2   /* FP64 build and LDL^T for every voxel */
 };
 

@@ -35,6 +35,7 @@
 // threshold (the amplification of FP32 rounding in K^-1 f~) are re-solved in
 // double; in FP64 mode every voxel runs in double.
 #include <algorithm>
+#include <type_traits>
 #include <cfloat>
 
 #include "scan.h"
@@ -977,6 +978,9 @@ constexpr int kTileThreads = 512;
 constexpr int kTileWaves = kTileThreads / 64;
 constexpr int kTileDoubles = kTile * kTile;
 constexpr int kXS = kTile + 1;  // row stride of the finished-tile buffer
+constexpr int kQTiles = 8;             // 16-query column tiles per wavefront in the query product
+constexpr int kQGroup = 16 * kQTiles;  // queries per group of the query product
+constexpr int kQTabRows = 12;          // grid rows a group of 128 queries spans (at most 11 for n_q <= 16)
 
 __device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -994,6 +998,12 @@ __device__ __forceinline__ int frag_pos(int row, int col) {
 // Scratch doubles per workgroup: the lower data tiles and one inverse per diagonal tile.
 constexpr size_t tile_scratch_doubles(int npad) {
   return (size_t)((npad / kTile) * (npad / kTile + 1) / 2 + npad / kTile) * kTileDoubles;
+}
+
+// Scratch doubles per workgroup of the mixed solver: FP32 lower tiles of L, inverses of the
+// diagonal tiles, and the lower tiles of L^-1 twice (row-major, and in matrix-core operand order).
+constexpr size_t tile_scratch_doubles_mixed(int npad) {
+  return ((size_t)(3 * ((npad / kTile) * (npad / kTile + 1) / 2) + npad / kTile) * kTileDoubles + 1) / 2;
 }
 
 __device__ __forceinline__ double sum16(double v) {
@@ -1300,53 +1310,31 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
 
 // ---------------------------------------------------------------------------
 // 2d. mixed-precision tiled solver (n up to 512): the tiled solver's block
-//     structure with FP32 data tiles and split-BF16 query products
+//     structure in FP32, the query rows as one product with the formed inverse
 // ---------------------------------------------------------------------------
 // - K and its Cholesky factor in FP32: tile products on the FP32 matrix cores
 //   (16 x 16 x 4), diagonal tiles by LDL^T on one wavefront.
+// - L^-1 formed row block by row block as the factor is finished (FP32 matrix
+//   cores): L^-1(I,K) = -L(I,I)^-1 sum_{K <= J < I} L(I,J) L^-1(J,K).
 // - alpha = L^-T L^-1 f~ by block substitution from the FP32 factor,
 //   accumulated in double; when n s_f^2 / min pivot exceeds cond_threshold
 //   (small pivots) or the amplification score sum_j |y_j| / d_j exceeds
-//   refine_threshold, one refinement step alpha += (K + S)^-1 (f~ - (K + S) alpha)
+//   refine_threshold, two refinement steps alpha += (K + S)^-1 (f~ - (K + S) alpha)
 //   with the residual in FP64 (kernel entries recomputed in double).
 // - mean_q = mu + sum_c kappa(x*_q, x_c) alpha_c in FP64, so the mean does not
 //   depend on the reduced-precision products below.
-// - z_q = L^-1 k*_q through the same tile recurrences, every query tile
-//   product in BF16 split into high and low parts (hi x hi + hi x lo + lo x hi)
-//   on the 16 x 16 x 32 matrix cores with FP32 accumulation;
-//   var_q = s_f^2 - |z_q|^2.
-// Data tiles, diagonal inverses and their BF16 high/low parts go to the
-// workgroup's scratch area in row-major 32 x 32 tiles.
+// - z_q = L^-1 k*_q for every query as one product (FP32 matrix cores, no
+//   barrier inside a group of 128 queries), var_q = s_f^2 - |z_q|^2. Forming
+//   z through the triangular recurrence instead lets rounding compound from
+//   block to block; with split-BF16 tile products (hi x hi + hi x lo + lo x hi)
+//   that reached 1.3e-3 s_f^2 of variance error on 200-point voxels.
+// Data tiles, diagonal inverses and L^-1 go to the workgroup's scratch area.
 typedef float flt4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 __device__ __forceinline__ flt4 mfma_f32(float a, float b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ flt4 mfma_bf16(bf16x8 a, bf16x8 b, flt4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-// Accumulator layout of both FP32-accumulating 16 x 16 products: lane l,
-// register k holds element (4 (l / 16) + k, l % 16).
-
-// x = hi + lo with hi the nearest BF16 of x and lo the nearest BF16 of the remainder.
-__device__ __forceinline__ void split_bf16(const float* x, float sign, bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float v = sign * x[e];
-    const __bf16 h = (__bf16)v;
-    hi[e] = h;
-    lo[e] = (__bf16)(v - (float)h);
-  }
-}
-
-__device__ __forceinline__ flt4 mfma_split(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
-                                           flt4 c) {
-  c = mfma_bf16(ah, bh, c);
-  c = mfma_bf16(ah, bl, c);
-  c = mfma_bf16(al, bh, c);
-  return c;
-}
+// Operand and accumulator layout of the 16 x 16 x 4 FP32 product: lane l holds A(l % 16, l / 16)
+// and B(l / 16, l % 16); register k of the result holds element (4 (l / 16) + k, l % 16).
 
 template <int NPAD>
 __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams P, FitArgs io,
@@ -1360,16 +1348,24 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
   constexpr int NB = NPAD / kTile;
   constexpr int NT = NB * (NB + 1) / 2;  // lower data tiles
   constexpr int LD = NPAD + 4;           // row stride of the row block, in floats
-  __shared__ __attribute__((aligned(16))) float rb[kTile * LD];
-  __shared__ __attribute__((aligned(16))) float xb[kTile * (kTile + 4)];
+  constexpr int XS = kTile + 4;
+  // the row block and finished tile of the factorisation share LDS with the query product's
+  // kernel tables (rows of the group, columns) and its per-wavefront partial sums
+  constexpr int kTabRows = kQTabRows + 1;  // the group's grid rows and one zero row
+  constexpr int kRowBlock = kTile * LD + kTile * XS;
+  constexpr int kTables = NPAD * kTabRows + NPAD * kMaxGridSide + kTileWaves * kQGroup;
+  __shared__ __attribute__((aligned(16))) float s_bigf[kRowBlock > kTables ? kRowBlock : kTables];
+  float* const rb = s_bigf;
+  float* const xb = s_bigf + kTile * LD;
   __shared__ double pu[NPAD], pw[NPAD], pf[NPAD];
   __shared__ float pn[NPAD];
   __shared__ float sy[NPAD];
   __shared__ double sal[NPAD], sz[NPAD];
   __shared__ double sred[16][kTile];
-  __shared__ double smean[kTile];
+  __shared__ double smq[kMaxGridSide * kMaxGridSide];  // mean of each query
+  __shared__ float sT[kTileWaves][kTile * 16];         // per wavefront: a 32 x 16 strip while L^-1 is formed
+  __shared__ int s_qoff[kQGroup];                      // table offsets of the group's queries
   __shared__ float srhs[kTile];
-  __shared__ double squ[kTile], sqw[kTile];
   __shared__ float sdcf[2 * kTile + 8];
   __shared__ float srdf[kTile];
   __shared__ float sdyf;
@@ -1378,19 +1374,18 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
   __shared__ float s_minpiv;
   __shared__ float s_score;
   __shared__ unsigned s_maxvar;
-  constexpr int XS = kTile + 4;
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
-  // scratch of this workgroup: FP32 tiles, FP32 inverses, then BF16 high / low parts of both
-  float* __restrict__ Lf = reinterpret_cast<float*>(scratch + (size_t)blockIdx.x * tile_scratch_doubles(NPAD));
+  // scratch of this workgroup (FP32, 32 x 32 tiles): L row-major, the diagonal inverses, and L^-1
+  // row-major (right operand while L^-1 is formed) and in operand order (left operand of the
+  // query product); L^-1 tile (I, K) at tile I (I + 1) / 2 + K
+  float* __restrict__ Lf = reinterpret_cast<float*>(scratch + (size_t)blockIdx.x * tile_scratch_doubles_mixed(NPAD));
   float* __restrict__ Wf = Lf + (size_t)NT * kTileDoubles;
-  __bf16* __restrict__ Lh = reinterpret_cast<__bf16*>(Wf + (size_t)NB * kTileDoubles);
-  __bf16* __restrict__ Ll = Lh + (size_t)NT * kTileDoubles;
-  __bf16* __restrict__ Wh = Ll + (size_t)NT * kTileDoubles;
-  __bf16* __restrict__ Wl = Wh + (size_t)NB * kTileDoubles;
+  float* __restrict__ Vr = Wf + (size_t)NB * kTileDoubles;
+  float* __restrict__ Va = Vr + (size_t)NT * kTileDoubles;
   const int cnt_items = (int)*count;
   const double sf2 = (double)P.sf2;
   const float sf2f = P.sf2;
@@ -1465,10 +1460,7 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
             const int row = a * 16 + 4 * l4 + k, col = b * 16 + l16;
             const float v = acc[k];
             rb[row * LD + J * kTile + col] = v;
-            const __bf16 h = (__bf16)v;
             Lf[t + row * kTile + col] = v;
-            Lh[t + row * kTile + col] = h;
-            Ll[t + row * kTile + col] = (__bf16)(v - (float)h);
           }
         }
         const int units = (I - J) * 4;
@@ -1562,12 +1554,61 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
           }
           const size_t t = (size_t)I * kTileDoubles;
 #pragma unroll
-          for (int i = 0; i < kTile; ++i) {
-            const __bf16 h = (__bf16)x[i];
-            Wf[t + i * kTile + lane] = x[i];
-            Wh[t + i * kTile + lane] = h;
-            Wl[t + i * kTile + lane] = (__bf16)(x[i] - (float)h);
+          for (int i = 0; i < kTile; ++i) Wf[t + i * kTile + lane] = x[i];
+        }
+      }
+      __syncthreads();
+      // row block I of L^-1: the diagonal tile is L(I,I)^-1; for K < I,
+      //   L^-1(I,K) = -L(I,I)^-1 sum_{K <= J < I} L(I,J) L^-1(J,K),
+      // one 32 x 16 strip (K, column half b2) per unit on the FP32 matrix cores
+      {
+        const float* __restrict__ Wi = Wf + (size_t)I * kTileDoubles;
+        float* __restrict__ Vi = Vr + (size_t)(I * (I + 1) / 2 + I) * kTileDoubles;
+        float* __restrict__ Ai = Va + (size_t)(I * (I + 1) / 2 + I) * kTileDoubles;
+        for (int e = tid; e < kTileDoubles; e += kTileThreads) {
+          const int row = e >> 5, col = e & 31;
+          Vi[e] = Wi[e];
+          Ai[frag_pos(row, col)] = Wi[e];
+        }
+      }
+      for (int un = wid; un < 2 * I; un += kTileWaves) {
+        const int K = un >> 1, b2 = un & 1;
+        flt4 t0 = {0.f, 0.f, 0.f, 0.f}, t1 = {0.f, 0.f, 0.f, 0.f};
+        for (int J = K; J < I; ++J) {
+          const float* __restrict__ Vj = Vr + (size_t)(J * (J + 1) / 2 + K) * kTileDoubles + b2 * 16 + l16;
+#pragma unroll
+          for (int s8 = 0; s8 < 8; ++s8) {
+            const float bv = Vj[(4 * s8 + l4) * kTile];
+            t0 = mfma_f32(rb[l16 * LD + J * kTile + 4 * s8 + l4], bv, t0);
+            t1 = mfma_f32(rb[(16 + l16) * LD + J * kTile + 4 * s8 + l4], bv, t1);
           }
+        }
+        // the sum through this wavefront's LDS strip, then the product with L(I,I)^-1
+        float* __restrict__ st = sT[wid];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          st[(4 * l4 + k) * 16 + l16] = t0[k];
+          st[(16 + 4 * l4 + k) * 16 + l16] = t1[k];
+        }
+        wave_sync();
+        const float* __restrict__ Wi = Wf + (size_t)I * kTileDoubles;
+        flt4 o0 = {0.f, 0.f, 0.f, 0.f}, o1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          const float tb = st[(4 * s8 + l4) * 16 + l16];
+          if (s8 < 4) o0 = mfma_f32(Wi[l16 * kTile + 4 * s8 + l4], tb, o0);  // rows 0-15: zero right of 16
+          o1 = mfma_f32(Wi[(16 + l16) * kTile + 4 * s8 + l4], tb, o1);
+        }
+        wave_sync();  // the strip is rewritten by this wavefront's next unit
+        float* __restrict__ Vi = Vr + (size_t)(I * (I + 1) / 2 + K) * kTileDoubles;
+        float* __restrict__ Ai = Va + (size_t)(I * (I + 1) / 2 + K) * kTileDoubles;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int col = b2 * 16 + l16, r0 = 4 * l4 + k, r1 = 16 + 4 * l4 + k;
+          Vi[r0 * kTile + col] = -o0[k];
+          Vi[r1 * kTile + col] = -o1[k];
+          Ai[frag_pos(r0, col)] = -o0[k];
+          Ai[frag_pos(r1, col)] = -o1[k];
         }
       }
       __syncthreads();
@@ -1604,7 +1645,10 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
     back(sy, nullptr, sal);
     const bool refine = !s_fail && ((double)n * sf2 / (double)s_minpiv > (double)P.cond_thr ||
                                     !(s_score <= P.refine_thr));
-    if (refine) {
+    // Two steps: one step with an FP32 factor leaves about (kappa eps_32)^2 of alpha's relative
+    // error, and kappa = n s_f^2 / sigma^2 reaches 2.6e5 at 256 points (one step left 1.5e-4 m of
+    // mean error on such voxels); the second takes it to (kappa eps_32)^3.
+    for (int step = 0; refine && step < 2; ++step) {
       // residual f~ - (K + S) alpha in FP64, one row per thread
       for (int i = tid; i < nbd * kTile; i += kTileThreads) {
         double rsd = 0.0;
@@ -1649,92 +1693,142 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_mixed_kernel(FitParams 
       __syncthreads();
     }
 
-    // ---- query row blocks: K* in FP32 for z, the mean from alpha in FP64 ----
-    for (int E = 0; E < nbe; ++E) {
-      if (tid < kTile) {
-        const int q = E * kTile + tid;
-        float gu = 0.f, gw = 0.f;
-        if (q < P.m) query_coords(P, fr, q, &gu, &gw);
-        squ[tid] = (double)gu - fr.anc_u;
-        sqw[tid] = (double)gw - fr.anc_w;
+    // ---- queries: the mean from alpha in FP64, the variance from z = L^-1 K* ----
+    // mean_q = mu + k*_q^T alpha with kernel entries in double, four threads per query
+    for (int q0 = 0; q0 < P.m; q0 += kTileThreads / 4) {
+      const int q = q0 + (tid >> 2), sub = tid & 3;
+      double macc = 0.0;
+      if (q < P.m) {
+        float gu, gw;
+        query_coords(P, fr, q, &gu, &gw);
+        const double qu = (double)gu - fr.anc_u, qw = (double)gw - fr.anc_w;
+        for (int c = sub; c < n; c += 4) {
+          const double du = qu - pu[c], dw = qw - pw[c];
+          macc += sf2 * exp(-(du * du + dw * dw) * lam) * sal[c];
+        }
       }
-      __syncthreads();
-      {
-        const int rr = tid >> 4, sub = tid & 15;
-        const int q = E * kTile + rr;
-        double macc = 0.0;
-        for (int c = sub; c < nbd * kTile; c += 16) {
-          float val = 0.f;
-          if (q < P.m && c < n) {
-            const double du = squ[rr] - pu[c], dw = sqw[rr] - pw[c];
-            const double kd = sf2 * exp(-(du * du + dw * dw) * lam);
-            macc += kd * sal[c];
-            val = (float)kd;
+      macc += __shfl_xor(macc, 1, 64);
+      macc += __shfl_xor(macc, 2, 64);
+      if (q < P.m && sub == 0) smq[q] = macc;
+    }
+    // var_q = s_f^2 - |z_q|^2 with z_q = L^-1 k*_q as one product with the formed inverse on the
+    // FP32 matrix cores, 128 queries at a time: each wavefront takes whole 16-row strips of
+    // L^-1 (zig-zag order, pairing long and short strips) against all eight 16-query column
+    // tiles of the group, so one operand fragment of L^-1 feeds eight products; no barrier
+    // inside a group. The cross-covariance entries come from two tables (the grid is
+    // separable): k*(c, q) = [s_f^2 exp(-lam du_i^2)] [exp(-lam dw_j^2)], each rounded to
+    // float from double. Each product's error stays that of one FP32 matrix product (no
+    // recurrence through earlier blocks); partial sums combine across lanes by shuffles and
+    // across wavefronts in a fixed order.
+    {
+      float* const tu = s_bigf;                           // [c][kTabRows]: row factors of the group
+      float* const tw = s_bigf + NPAD * kTabRows;         // [c][16]: column factors
+      float* const part = tw + NPAD * kMaxGridSide;       // [wavefront][query of the group]
+      const int nq = P.nq;
+      const int ns = (n + 15) >> 4;  // strips holding data rows; the rest of z is zero
+      const int n4 = (n + 3) & ~3;   // table columns from n on are zero
+      for (int e = tid; e < NPAD * kMaxGridSide; e += kTileThreads) {
+        const int c = e >> 4, j = e & 15;
+        float v = 0.f;
+        if (c < n && j < nq) {
+          float gu, gw;
+          coords_from_frac(P, fr, grid_frac(P, 0), grid_frac(P, j), &gu, &gw);
+          const double dw = ((double)gw - fr.anc_w) - pw[c];
+          v = (float)exp(-(dw * dw) * lam);
+        }
+        tw[e] = v;
+      }
+      for (int q0 = 0; q0 < P.m; q0 += kQGroup) {
+        const int i0 = q0 / nq;
+        const int irows = ((q0 + kQGroup < P.m ? q0 + kQGroup : P.m) - 1) / nq - i0 + 1;
+        for (int e = tid; e < NPAD * kTabRows; e += kTileThreads) {
+          const int c = e / kTabRows, i = e - c * kTabRows;
+          float v = 0.f;
+          if (c < n && i < irows) {
+            float gu, gw;
+            coords_from_frac(P, fr, grid_frac(P, i0 + i), grid_frac(P, 0), &gu, &gw);
+            const double du = ((double)gu - fr.anc_u) - pu[c];
+            v = (float)(sf2 * exp(-(du * du) * lam));
           }
-          rb[rr * LD + c] = val;
+          tu[e] = v;
         }
-#pragma unroll
-        for (int d = 8; d >= 1; d >>= 1) macc += __shfl_xor(macc, d, 64);
-        if (sub == 0) smean[rr] = macc;
-      }
-      __syncthreads();
-      for (int J = 0; J < nbd; ++J) {
-        flt4 acc = {0.f, 0.f, 0.f, 0.f};
-        const int a = (wid >> 1) & 1, b = wid & 1;
-        if (wid < 4) {
-          bf16x8 ah, al;
-          split_bf16(rb + (a * 16 + l16) * LD + J * kTile + 8 * l4, 1.f, ah, al);
-          const size_t t = (size_t)J * kTileDoubles + (b * 16 + l16) * kTile + 8 * l4;
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Wh + t);
-          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Wl + t);
-          acc = mfma_split(ah, al, bh, bl, acc);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) xb[(a * 16 + 4 * l4 + k) * XS + b * 16 + l16] = acc[k];
+        // with n_q = 16 a group is eight whole grid rows: row factor t, column factor l % 16
+        const bool full16 = nq == kMaxGridSide;
+        if (!full16 && tid < kQGroup) {
+          const int q = q0 + tid;
+          s_qoff[tid] = q < P.m ? ((q / nq - i0) << 8) | (q % nq) : (kQTabRows << 8);  // past the grid: zero row
         }
         __syncthreads();
-        if (wid < 4) {
+        float zz[kQTiles];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) rb[(a * 16 + 4 * l4 + k) * LD + J * kTile + b * 16 + l16] = acc[k];
-        }
-        const int units = (nbd - 1 - J) * 4;
-        for (int un = wid; un < units; un += kTileWaves) {
-          const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
-          float* __restrict__ cp = rb + Jp * kTile + b2 * 16 + l16;
-          flt4 c4;
+        for (int t = 0; t < kQTiles; ++t) zz[t] = 0.f;
+        auto strips = [&](auto full16_tag) {
+          constexpr bool FULL16 = decltype(full16_tag)::value;
+          for (int rr = 0; kTileWaves * rr < ns; ++rr) {
+            const int sx = kTileWaves * rr + ((rr & 1) ? kTileWaves - 1 - wid : wid);
+            if (sx >= ns) continue;
+            const int I = sx >> 1;
+            const int kend = (16 * sx + 16 < n4 ? 16 * sx + 16 : n4) >> 2;  // steps of 4 columns
+            const float* __restrict__ A0 =
+                Va + (size_t)(I * (I + 1) / 2) * kTileDoubles + (((sx & 1) * 8) << 6) + lane;
+            auto afrag = [&](int ks) { return A0[(size_t)(ks >> 3) * kTileDoubles + ((ks & 7) << 6)]; };
+            flt4 acc[kQTiles];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) c4[k] = cp[(a2 * 16 + 4 * l4 + k) * LD];
-          bf16x8 ah, al;
-          split_bf16(xb + (a2 * 16 + l16) * XS + 8 * l4, -1.f, ah, al);
-          const size_t t = (size_t)(Jp * (Jp + 1) / 2 + J) * kTileDoubles + (b2 * 16 + l16) * kTile + 8 * l4;
-          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Lh + t);
-          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ll + t);
-          c4 = mfma_split(ah, al, bh, bl, c4);
+            for (int t = 0; t < kQTiles; ++t) acc[t] = flt4{0.f, 0.f, 0.f, 0.f};
+            float an1 = afrag(0);
+            float an2 = kend > 1 ? afrag(1) : 0.f;
+            for (int ks = 0; ks < kend; ++ks) {
+              const float a = an1;
+              an1 = an2;
+              an2 = ks + 2 < kend ? afrag(ks + 2) : 0.f;
+              const int c = 4 * ks + l4;
+              const float* __restrict__ tuc = tu + c * kTabRows;
+              const float* __restrict__ twc = tw + c * kMaxGridSide;
+              if constexpr (FULL16) {
+                const float wv = twc[l16];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cp[(a2 * 16 + 4 * l4 + k) * LD] = c4[k];
+                for (int t = 0; t < kQTiles; ++t) acc[t] = mfma_f32(a, tuc[t] * wv, acc[t]);
+              } else {
+#pragma unroll
+                for (int t = 0; t < kQTiles; ++t) {
+                  const int o = s_qoff[16 * t + l16];
+                  acc[t] = mfma_f32(a, tuc[o >> 8] * twc[o & 255], acc[t]);
+                }
+              }
+            }
+            // lane l, register k holds z of row 16 sx + 4 (l / 16) + k for query column l % 16 of tile t
+#pragma unroll
+            for (int t = 0; t < kQTiles; ++t)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) zz[t] += acc[t][k] * acc[t][k];
+          }
+        };
+        if (full16)
+          strips(std::integral_constant<bool, true>{});
+        else
+          strips(std::integral_constant<bool, false>{});
+#pragma unroll
+        for (int t = 0; t < kQTiles; ++t) {
+          zz[t] += __shfl_xor(zz[t], 16, 64);
+          zz[t] += __shfl_xor(zz[t], 32, 64);
+          if (l4 == 0) part[wid * kQGroup + 16 * t + l16] = zz[t];
         }
         __syncthreads();
-      }
-      {
-        const int rr = tid >> 4, sub = tid & 15;
-        float zz = 0.f;
-        for (int c = sub; c < nbd * kTile; c += 16) {
-          const float z = rb[rr * LD + c];
-          zz += z * z;
-        }
+        if (tid < kQGroup && q0 + tid < P.m) {
+          const int q = q0 + tid;
+          double zzs = 0.0;
 #pragma unroll
-        for (int d = 8; d >= 1; d >>= 1) zz += __shfl_xor(zz, d, 64);
-        const int q = E * kTile + rr;
-        if (sub == 0 && q < P.m) {
+          for (int w = 0; w < kTileWaves; ++w) zzs += (double)part[w * kQGroup + tid];
           float gu, gw;
           query_coords(P, fr, q, &gu, &gw);
           const bool failed = s_fail != 0;
-          const double var = sf2 - (double)zz;
+          const double var = sf2 - zzs;
           const float vv = failed ? __int_as_float(0x7fc00000) : (float)(var > 0.0 ? var : 0.0);
-          const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + smean[rr];
+          const double fh = failed ? (double)__int_as_float(0x7fc00000) : fr.mu + smq[q];
           reinterpret_cast<float4*>(io.out)[(size_t)r.v * P.m + q] = make_row(P, fr, rot, fh, gu, gw, vv);
           if (!failed) atomicMax(&s_maxvar, __float_as_uint(vv));
         }
-        __syncthreads();
+        __syncthreads();  // the tables and partial sums are rewritten for the next group
       }
     }
     if (tid == 0) {
@@ -1845,7 +1939,8 @@ int tile_grid(const vgpr_ctx* ctx, int b, bool mixed, int grid_scale) {
 
 size_t tile_bucket_bytes(const vgpr_ctx* ctx, int b, bool mixed) {
   if (!mixed && kBucketCap[b] <= 128) return 0;  // the FP64 tiled solver keeps these tiles in LDS
-  return (size_t)tile_per_cu_of(b, mixed) * ctx->cu_count * tile_scratch_doubles(kBucketCap[b]) * sizeof(double);
+  const size_t per = mixed ? tile_scratch_doubles_mixed(kBucketCap[b]) : tile_scratch_doubles(kBucketCap[b]);
+  return (size_t)tile_per_cu_of(b, mixed) * ctx->cu_count * per * sizeof(double);
 }
 
 template <bool MIXED>

@@ -82,8 +82,11 @@ def compare_voxelize(ov: dict, gv) -> None:
 
 
 def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, voxels=None,
-                noise=None) -> dict:
-    """Compare GPU outputs with the oracle voxel by voxel; returns error stats."""
+                noise=None, strict: bool = True) -> dict:
+    """Compare GPU outputs with the oracle voxel by voxel; returns error stats.
+
+    strict=False (measurement only) counts the voxels whose mean or variance is
+    outside the tolerances instead of failing on the first."""
     out = out.cpu().numpy().astype(np.float64)
     axis = axis.cpu().numpy().astype(np.int64)
     status = status.cpu().numpy().astype(np.int64)
@@ -95,6 +98,7 @@ def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, vox
     n_solved = 0
     n_refined = 0
     n_tie = 0
+    n_out = 0
     for v in idx:
         P = O.voxel_points(xyz, ov, v)
         nz = None
@@ -126,13 +130,16 @@ def compare_fit(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, vox
         max_mean = max(max_mean, em)
         max_var = max(max_var, ev)
         own.add(g[:, 3], e[:, 3])
+        if not strict:
+            n_out += not (em <= MEAN_TOL and ev <= VAR_TOL_REL * prm.signal_var)
+            continue
         assert em <= MEAN_TOL, (v, em, r["n"])
         assert ev <= VAR_TOL_REL * prm.signal_var, (v, ev, r["n"])
         mv = e[:, 3].max()
         if abs(mv - prm.converge_var) > VAR_TOL_REL * prm.signal_var:
             assert bool(st & O.ST_CONVERGED) == bool(mv <= prm.converge_var), (v, mv)
     return {"max_mean_err": max_mean, "max_var_err": max_var, **own.stats(), "solved": n_solved,
-            "refined": n_refined, "axis_ties": n_tie}
+            "refined": n_refined, "axis_ties": n_tie, "outside_tolerance": n_out}
 
 
 def compare_fit_rotated(xyz: np.ndarray, ov: dict, prm: O.Params, out, axis, status, voxels=None) -> dict:
