@@ -32,8 +32,7 @@ from paper_2410_17084_amd import configs, synth  # noqa: E402
 PEAK = {"f32": 157.3, "f64": 78.6}  # TFLOP/s, MI355X vector FP32 / FP64
 HBM_PEAK = 8000.0                   # GB/s
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILES = {"spin32": os.path.join(HERE, "profiles", "hbm_traffic_spin32_batch64.json"),
-                 "aggregated": os.path.join(HERE, "profiles", "hbm_traffic_aggregated.json")}
+TRAFFIC_FILES = {"aggregated": os.path.join(HERE, "profiles", "hbm_traffic_aggregated.json")}
 
 
 def source_hash() -> str:
@@ -380,6 +379,8 @@ def main():
             default_frames = {"spin32": 64, "batched": 16, "aggregated": 1}[args.workload]
             roof["traffic"] = (measured_traffic(args.workload, dom, ctx.tuning().as_dict(), args.precision)
                                if args.frames == default_frames else None)
+            if roof["traffic"]:
+                roof["traffic_vs_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
         tot_fit = sum(v[0] for f, v in fam_time.items() if f.startswith(("fit", "refine")))
         kernels["_fit_all"] = {"ms_per_step": tot_fit / args.steps,
                                "tflops": float(fl[solved].sum()) / (tot_fit / args.steps / 1e3) / 1e12}
