@@ -749,6 +749,16 @@ def serve_leg(args, vgpr) -> dict:
     st = serve.serve(be, sizes, rate_hz=10.0, duration_s=args.serve_seconds, workers=8, budget_bytes=8 << 30,
                      m=p.grid_side ** 2)
     out = st.summary()
+    out["arrivals"] = "sensors phase-shifted by 1/80 s"
+    be.close()
+    # the same streams with every sensor ticking at the same instant (synchronised sensors):
+    # eight frames arrive together each 100 ms, so admission and device overlap are exercised
+    be = serve.GpuBackend(p, frames, max_voxels=250000)
+    be.warmup()
+    sa = serve.serve(be, sizes, rate_hz=10.0, duration_s=max(args.serve_seconds / 2, 1.0), workers=8,
+                     budget_bytes=8 << 30, m=p.grid_side ** 2, offsets_s=[0.0] * len(frames)).summary()
+    sa["arrivals"] = "all sensors at the same instant"
+    out["synchronised"] = sa
     out["streams"] = [f"{b}x{a}" for b, a in synth.STREAM_SENSORS]
     out["points_per_tick"] = int(sum(s[0] for s in sizes))
     out["config"] = "voxel 0.2 m, tau 10, cap 64, 9x9 grid, eta 0.3; 10 frames per stream cycled"
