@@ -418,8 +418,7 @@ typedef struct {
   int32_t wave_last_bucket;   /* grids of up to 64 points: buckets 0..this use the one-voxel-per-
                                  wavefront solver (max 2), the others one voxel per workgroup */
   int32_t streams;            /* 1: every bucket on the context's stream; 3: buckets fork onto
-                                 side streams (96/128 points, 32/64 points, 256/512 points each
-                                 on one, 16 points on the context's stream) and join back */
+                                 the three side streams as bucket_stream says and join back */
   int32_t grid_scale[7];      /* persistent grid of bucket b = grid_scale[b] / 4 x the resident
                                  workgroups the device holds (1..64; buckets 5 and 6 use at
                                  most 4, one resident wave of workgroups) */
@@ -430,6 +429,11 @@ typedef struct {
                                  context's stream (their workgroups need whole CUs, which other
                                  buckets' workgroups would hold), and forks the others after
                                  them; 0 forks every bucket at once */
+  int32_t bucket_stream[7];   /* with streams = 3: stream of bucket b, 0 the context's stream,
+                                 1..3 the side streams; buckets on one stream run one after
+                                 another, largest first (default {0, 2, 2, 1, 1, 3, 3}: 16
+                                 points on the context's stream, 96/128, 32/64 and 256/512
+                                 points each on one side stream) */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);

@@ -2,8 +2,8 @@
 
 Searches the launch choices of `vgpr_tuning` (which buckets try FP32 first,
 which use the one-voxel-per-wavefront solver, which use the tiled
-matrix-core solver, one or three streams, the persistent grid size of each
-bucket) by coordinate descent, timing the real
+matrix-core solver, one or three streams and which stream each bucket takes,
+the persistent grid size of each bucket) by coordinate descent, timing the real
 workload on the device with HIP events. A candidate is accepted only if its
 outputs stay within the accuracy tolerances of an FP64 reference run of the
 same call (mean 1e-4 m, variance 1e-3 s_f^2, identical status and axis), so
@@ -104,6 +104,9 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
         space.append(("tile_first_bucket", tiles))
         # which buckets are tiled and whether they run before the fork interact: search them together
         space.append((("joint", "tile_first_bucket", "tiled_first"), [(b, f) for b in tiles for f in (0, 1)]))
+    # bucket -> stream maps (0: the context's stream, 1..3: side streams): the default, the
+    # 256-point bucket ahead of the 96/128-point ones, the 96-point bucket with the 32/64-point ones
+    space.append(("bucket_stream", [list(vgpr.DEFAULT_BUCKET_STREAM), [0, 2, 2, 1, 1, 1, 3], [0, 2, 2, 2, 1, 1, 3]]))
     caps = (0, 16, 32, 64, 96, 128, 256)  # lower bound of each bucket
     space += [(("grid_scale", b), [2, 4, 8, 16]) for b in range(7) if params.max_pts > caps[b]]
     t0 = time.perf_counter()

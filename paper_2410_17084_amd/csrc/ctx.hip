@@ -284,6 +284,9 @@ vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
   if (t->tile_first_bucket < 2 || t->tile_first_bucket > 5)
     return fail(ctx, VGPR_E_INVALID, "tile_first_bucket must be in [2, 5]");
   if (t->tiled_first != 0 && t->tiled_first != 1) return fail(ctx, VGPR_E_INVALID, "tiled_first must be 0 or 1");
+  for (int b = 0; b < kNumBuckets; ++b)
+    if (t->bucket_stream[b] < 0 || t->bucket_stream[b] > vgpr_ctx::kAux)
+      return fail(ctx, VGPR_E_INVALID, "bucket_stream entries must be in [0, 3]");
   ctx->tune = *t;
   return VGPR_OK;
 }

@@ -369,20 +369,20 @@ constexpr int kOrderThreads = 1024;
 __global__ void __launch_bounds__(kOrderThreads) order_kernel(const SlotRec* __restrict__ recs,
                                                               const uint32_t* __restrict__ count,
                                                               int32_t* __restrict__ order) {
+  static_assert(kMaxPtsLimit < kOrderThreads, "one count per thread in the scan");
   __shared__ uint32_t start[kMaxPtsLimit + 1];
+  __shared__ uint32_t part[kOrderThreads / 64 + 1];
   const int items = (int)*count;
   for (int i = threadIdx.x; i <= kMaxPtsLimit; i += kOrderThreads) start[i] = 0u;
   __syncthreads();
   for (int i = threadIdx.x; i < items; i += kOrderThreads) atomicAdd(&start[recs[i].fr.n], 1u);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int k = kMaxPtsLimit; k >= 0; --k) {
-      const uint32_t h = start[k];
-      start[k] = run;
-      run += h;
-    }
-  }
+  // first slot of each count, largest count first: thread t scans the count n = limit - t
+  const int k = kMaxPtsLimit - (int)threadIdx.x;
+  const uint32_t h = k >= 0 ? start[k] : 0u;
+  uint32_t total;
+  const uint32_t first = block_exclusive_sum<kOrderThreads>(h, part, &total);
+  if (k >= 0) start[k] = first;
   __syncthreads();
   for (int i = threadIdx.x; i < items; i += kOrderThreads) order[atomicAdd(&start[recs[i].fr.n], 1u)] = i;
 }
@@ -2090,10 +2090,11 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
                        ctx->stream, P, a.out, L);
     VGPR_HIP(ctx, hipGetLastError());
   }
-  // Buckets run concurrently: the 96/128-point buckets on side stream 0, the
-  // 32/64-point buckets on side stream 1, the 256/512-point buckets on side
-  // stream 2, the 16-point bucket (and its FP64 re-solve) on the caller's
-  // stream, joined back before the call returns (with tiled_first, the tiled
+  // Buckets run concurrently on the caller's stream and the three side streams
+  // (bucket_stream of the launch choices; by default the 96/128-point buckets on
+  // side stream 1, the 32/64-point buckets on side stream 2, the 256/512-point
+  // buckets on side stream 3, the 16-point bucket and its passes on the caller's
+  // stream), joined back before the call returns (with tiled_first, the tiled
   // buckets run before the fork instead). Many small voxels fill the CUs that
   // the few long large-voxel solves leave idle.
   st = ensure_aux(ctx);
@@ -2104,9 +2105,8 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   const bool tiles_first = tu.streams != 1 && tu.tiled_first != 0;
   auto stream_of = [&](int b) {
     if (tu.streams == 1 || (tiles_first && b >= first_tile_bucket(ctx))) return ctx->stream;
-    // 256/512-point buckets on their own stream: their workgroups need whole CUs of LDS, so even an
-    // empty launch waits for CUs to drain and would hold back the buckets queued behind it
-    return b >= 5 ? ctx->aux[2] : (b >= 3 ? ctx->aux[0] : (b >= 1 ? ctx->aux[1] : ctx->stream));
+    const int s = tu.bucket_stream[b];
+    return s == 0 ? ctx->stream : ctx->aux[s - 1];
   };
   auto launch_b = [&](int b) -> vgpr_status {
     const bool tiled = b >= first_tile_bucket(ctx);

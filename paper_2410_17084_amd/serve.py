@@ -90,6 +90,8 @@ class GpuBackend(Backend):
 
     def __init__(self, params, frames_by_stream, max_voxels: int, device: int = 0, feedback: bool = False):
         import torch
+        self.max_voxels = max_voxels
+        self.feedback = feedback
 
         from . import vgpr
         self.torch = torch
@@ -119,16 +121,25 @@ class GpuBackend(Backend):
         self.keep_results = False
 
     def warmup(self):
-        """Grow each context's scratch and set up its kernels on the stream's largest frame.
+        """Grow each context's scratch and load its kernels before anything is timed.
 
-        Runs voxelize + fit_predict outside the maps, so map state is untouched.
+        Runs voxelize + fit_predict on the stream's largest frame, then the
+        stream's first frames through a map of its own (the same update mode),
+        so that the map kernels and the fits of re-solved voxels (with the
+        feedback update: their carried rows stacked with the new points) have
+        run once and the workspace has grown to their size. The stream's own map
+        is untouched.
         """
         for s, frames in enumerate(self.frames):
             x = max(frames, key=lambda t: t.shape[0])
             ctx = self.ctxs[s]
             vox = ctx.voxelize(x, self.params)
             ctx.fit_predict(x, vox, self.params)
+            scratch_map = self.vgpr.Map(ctx, self.params, self.max_voxels, feedback=self.feedback)
+            for f in frames[:3]:
+                scratch_map.update(f, out=self.outs[s])
             self.streams[s].synchronize()
+            scratch_map.close()
 
     def update(self, stream: int, frame_index: int):
         frames = self.frames[stream]

@@ -47,14 +47,20 @@ class Params(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# stream of each size bucket when the buckets fork (0: the context's stream, 1..3: side streams)
+DEFAULT_BUCKET_STREAM = (0, 2, 2, 1, 1, 3, 3)
+
+
 class Tuning(C.Structure):
     _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
-                ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32), ("tiled_first", C.c_int32)]
+                ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32), ("tiled_first", C.c_int32),
+                ("bucket_stream", C.c_int32 * 7)]
 
     def as_dict(self) -> dict:
         return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,
                 "streams": self.streams, "grid_scale": list(self.grid_scale),
-                "tile_first_bucket": self.tile_first_bucket, "tiled_first": self.tiled_first}
+                "tile_first_bucket": self.tile_first_bucket, "tiled_first": self.tiled_first,
+                "bucket_stream": list(self.bucket_stream)}
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tuning":
@@ -68,6 +74,9 @@ class Tuning(C.Structure):
             t.grid_scale[i] = gs[i] if i < len(gs) else 4
         t.tile_first_bucket = d.get("tile_first_bucket", 5)
         t.tiled_first = d.get("tiled_first", 0)
+        bs = list(d.get("bucket_stream", DEFAULT_BUCKET_STREAM))
+        for i in range(7):
+            t.bucket_stream[i] = bs[i]
         return t
 
 

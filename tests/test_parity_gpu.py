@@ -730,7 +730,9 @@ def test_tuning_choices(env):
     prm = parity.oracle_params(w)
     try:
         for change in [dict(streams=1), dict(grid_scale=[1, 2, 16, 8, 3, 2, 1]), dict(streams=1, grid_scale=[64] * 7),
-                       dict(tiled_first=1), dict(tiled_first=1, streams=1)]:
+                       dict(tiled_first=1), dict(tiled_first=1, streams=1),
+                       dict(bucket_stream=[0, 1, 2, 3, 1, 2, 3]), dict(bucket_stream=[0] * 7),
+                       dict(bucket_stream=[3, 3, 2, 2, 1, 1, 0])]:
             say("tuning (bit-identical)", change)
             t = dict(default)
             t.update(change)
@@ -758,7 +760,8 @@ def test_tuning_choices(env):
             outs.append([t_.cpu().numpy() for t_ in ctx.fit_predict(x, gv, p)])
         for g, r in zip(outs[1], outs[0]):
             assert np.array_equal(g, r, equal_nan=True)
-        for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3), ("tiled_first", 2)):
+        for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3), ("tiled_first", 2),
+                         ("bucket_stream", [0, 1, 2, 4, 1, 2, 3]), ("bucket_stream", [-1] + [0] * 6)):
             with pytest.raises(vgpr.VgprError):
                 bad = dict(default)
                 bad[key] = val
