@@ -1077,10 +1077,37 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
     }
     const int nbd = (n + kTile - 1) / kTile;
     const int nbe = (P.m + kTile - 1) / kTile;
+    // entry (rr, c) of row block Ib of the augmented system: K + S for data blocks (identity
+    // rows and columns past n), K*^T for query blocks (zero past the grid and past n)
+    auto entry = [&](int Ib, int rr, int c) -> double {
+      if (Ib < nbd) {
+        const int i = Ib * kTile + rr;
+        if (i < n && c < n) {
+          const double du = pu[i] - pu[c], dw = pw[i] - pw[c];
+          return sf2 * exp(-(du * du + dw * dw) * lam) + (i == c ? (double)pn[i] : 0.0);
+        }
+        return i == c ? 1.0 : 0.0;
+      }
+      const int q = (Ib - nbd) * kTile + rr;
+      if (q < P.m && c < n) {
+        const double du = squ[rr] - pu[c], dw = sqw[rr] - pw[c];
+        return sf2 * exp(-(du * du + dw * dw) * lam);
+      }
+      return 0.0;
+    };
+    // query coordinates of the first query block now: its rows are built in part during the
+    // last data block's diagonal phase
+    if (tid < kTile) {
+      float gu = 0.f, gw = 0.f;
+      if (tid < P.m) query_coords(P, fr, tid, &gu, &gw);
+      squ[tid] = (double)gu - fr.anc_u;
+      sqw[tid] = (double)gw - fr.anc_w;
+    }
+    int c_pre = 0;  // columns [0, c_pre) of block I were built during the previous diagonal phase
     for (int I = 0; I < nbd + nbe; ++I) {
       const bool data = I < nbd;
       const int ncols = data ? (I + 1) * kTile : nbd * kTile;
-      if (!data && tid < kTile) {
+      if (I > nbd && tid < kTile) {
         const int q = (I - nbd) * kTile + tid;
         float gu = 0.f, gw = 0.f;
         if (q < P.m) query_coords(P, fr, q, &gu, &gw);
@@ -1088,29 +1115,13 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
         sqw[tid] = (double)gw - fr.anc_w;
       }
       __syncthreads();
-      // the block's rows of the augmented system
-      for (int e = tid; e < kTile * ncols; e += kTileThreads) {
-        const int rr = e / ncols, c = e - rr * ncols;
-        double val;
-        if (data) {
-          const int i = I * kTile + rr;
-          if (i < n && c < n) {
-            const double du = pu[i] - pu[c], dw = pw[i] - pw[c];
-            val = sf2 * exp(-(du * du + dw * dw) * lam) + (i == c ? (double)pn[i] : 0.0);
-          } else {
-            val = i == c ? 1.0 : 0.0;
-          }
-        } else {
-          const int q = (I - nbd) * kTile + rr;
-          if (q < P.m && c < n) {
-            const double du = squ[rr] - pu[c], dw = sqw[rr] - pw[c];
-            val = sf2 * exp(-(du * du + dw * dw) * lam);
-          } else {
-            val = 0.0;
-          }
-        }
-        rb[rr * LD + c] = val;
+      // the block's rows of the augmented system (the columns not built ahead)
+      {
+        // thread t fills row t % 32, every 16th column from c_pre + t / 32
+        const int rr = tid & (kTile - 1);
+        for (int c = c_pre + tid / kTile; c < ncols; c += kTileThreads / kTile) rb[rr * LD + c] = entry(I, rr, c);
       }
+      c_pre = 0;
       __syncthreads();
       const int jend = data ? I : nbd;
       // operand fragment of L(J,J)^-1 for this wavefront's quarter of X, fetched one step ahead
@@ -1275,7 +1286,16 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
 #pragma unroll
             for (int i = 0; i < kTile; ++i) Wi[frag_pos(i, lane)] = x[i];
           }
+        } else if (wid != kTileWaves / 2) {
+          // meanwhile six wavefronts (not the one sharing wavefront 0's SIMD) build columns
+          // [0, 32 I) of the next block, which no one reads any more in this block (the
+          // diagonal phase works on columns [32 I, 32 I + 32))
+          const int pc = I * kTile;
+          const int w6 = wid < kTileWaves / 2 ? wid - 1 : wid - 2;
+          const int rr = lane & (kTile - 1);
+          for (int c = 2 * w6 + lane / kTile; c < pc; c += 2 * (kTileWaves - 2)) rb[rr * LD + c] = entry(I + 1, rr, c);
         }
+        c_pre = I * kTile;
         __syncthreads();
       } else {
         // query rows of the block: variance and mean, sixteen lanes per row
