@@ -229,7 +229,7 @@ VGPR_API vgpr_status vgpr_fit_predict(vgpr_ctx* ctx, const float* d_xyz, int64_t
  * itself allocates nothing (no hipMalloc / hipFree, no stream or event
  * creation: the context made its side streams at vgpr_create). The caller
  * still owns every input and output buffer.
- * Limit: the call's scratch (about 510 bytes per voxel + 16 bytes per point,
+ * Limit: the call's scratch (about 525 bytes per voxel + 16 bytes per point,
  * plus the tiled solvers' areas when max_pts > 128 or in MIXED mode) must fit
  * in the 64 MiB; otherwise it returns VGPR_E_CAPACITY and enqueues nothing.
  * Concurrency: every call on one GPU (from any context) shares that GPU's

@@ -9,7 +9,9 @@
 //    cyclic parameter axes, near-tie flag, optional per-voxel length scale)
 //    written as a 64-byte slot record, and the kept points staged as float4
 //    (x, y, z, noise variance) at their sorted positions, so that the solvers
-//    read one record and one coalesced row of points per voxel.
+//    read one record and one coalesced row of points per voxel. Voxels of more
+//    than 64 points are staged and summed by a second kernel, one wavefront
+//    per voxel, so that no thread walks up to 512 points alone.
 // 2. solve: the posterior of Eq. (3) from an LDL^T elimination of the
 //    augmented system whose rows are
 //          [ K + S | f~ ]   n data rows      (S = noise variances on the diagonal)
@@ -100,7 +102,12 @@ struct Lists {
   uint32_t* count;       // kLists counters
   int64_t stride;
   RotRec* rots;          // frame_mode 1: one rotated frame per slot record, else null
+  int4* big;             // voxels of more than kPrepCoop points: (voxel, list, slot, 0)
+  uint32_t* big_count;
 };
+
+// Voxels of more than this many kept points are staged and summed by a whole wavefront.
+constexpr int kPrepCoop = 64;
 
 __device__ __forceinline__ float k_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double k_exp(double x) { return exp(x); }
@@ -172,96 +179,15 @@ __device__ void jacobi3(double A[3][3], double w[3], double V[3][3]) {
 
 __device__ __forceinline__ float pick(int axis, float x, float y, float z) { return axis == 0 ? x : (axis == 1 ? y : z); }
 
-// ---------------------------------------------------------------------------
-// 1. prep: tau test, PCA frame, bucketing (one thread per voxel)
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, float4* __restrict__ staged,
-                                                   Lists L) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = v < io.n_vox;
-  int lst = -1, n = 0, c = 0, off = 0;
-  if (valid) {
-    c = io.counts[v];
-    off = io.offsets[v];
-    n = c < P.cap ? c : P.cap;
-    if (n < P.tau || off < 0 || (int64_t)off + n > io.n_pts) {
-      // below tau (type (a)); a voxel whose points lie outside [0, n_pts) is not solved either
-      const bool in_range = off >= 0 && (int64_t)off + n <= io.n_pts;
-      io.status[v] = in_range ? (uint8_t)(VGPR_ST_BELOW_TAU | (c > P.cap ? VGPR_ST_CAPPED : 0)) : (uint8_t)0;
-      io.axis[v] = -1;
-      lst = kNanList;
-    } else {
-      lst = 0;
-      while (lst < kNumBuckets - 1 && n > P.bcap[lst]) ++lst;
-    }
-  }
-  // slot in the voxel's list: wavefront offsets within the workgroup through LDS,
-  // then one global atomic per workgroup and list
-  __shared__ uint32_t s_cnt[kLists], s_base[kLists];
-  const int lane = lane_id();
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  if (threadIdx.x < kLists) s_cnt[threadIdx.x] = 0u;
-  __syncthreads();
-  uint32_t woff = 0;
-  unsigned long long mymask = 0;
-#pragma unroll
-  for (int l = 0; l < kLists; ++l) {
-    const unsigned long long mk = __ballot(lst == l);
-    if (mk) {
-      const int leader = __ffsll((long long)mk) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&s_cnt[l], (uint32_t)__popcll(mk));
-      base = __shfl(base, leader, 64);
-      if (lst == l) {
-        woff = base;
-        mymask = mk;
-      }
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < kLists && s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&L.count[threadIdx.x], s_cnt[threadIdx.x]);
-  __syncthreads();
-  int slot = 0;
-  if (lst >= 0) slot = (int)(s_base[lst] + woff + __popcll(mymask & lt));
-  if (lst == kNanList) L.nan_list[slot] = (int32_t)v;
-  if (lst < 0 || lst == kNanList) return;
-
-  // stage the kept points and accumulate the covariance about the first point:
-  // S1 = sum d, S2 = sum d d^T with d = p - p0. Loads of four points are issued
-  // together so that a large voxel's thread keeps several gathers in flight.
-  const int* __restrict__ perm = io.perm;
-  const float* __restrict__ xyz = io.xyz;
-  const float* __restrict__ noise = io.noise;
-  float4* __restrict__ st = staged;
-  const int i0 = perm ? perm[off] : off;
-  const float x0 = xyz[3 * (size_t)i0], y0 = xyz[3 * (size_t)i0 + 1], z0 = xyz[3 * (size_t)i0 + 2];
-  st[off] = make_float4(x0, y0, z0, noise ? noise[i0] : P.noise);
-  const double p0x = x0, p0y = y0, p0z = z0;
-  double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
-  for (int i = 1; i < n; i += 4) {
-    float px[4], py[4], pz[4], pn[4];
-#pragma unroll
-    for (int u4 = 0; u4 < 4; ++u4) {
-      const int ii = i + u4 < n ? i + u4 : i;
-      const int idx = perm ? perm[off + ii] : off + ii;
-      px[u4] = xyz[3 * (size_t)idx];
-      py[u4] = xyz[3 * (size_t)idx + 1];
-      pz[u4] = xyz[3 * (size_t)idx + 2];
-      pn[u4] = noise ? noise[idx] : P.noise;
-    }
-#pragma unroll
-    for (int u4 = 0; u4 < 4; ++u4) {
-      if (i + u4 < n) {
-        st[off + i + u4] = make_float4(px[u4], py[u4], pz[u4], pn[u4]);
-        const double d0 = (double)px[u4] - p0x;
-        const double d1 = (double)py[u4] - p0y;
-        const double d2 = (double)pz[u4] - p0z;
-        s0 += d0; s1 += d1; s2 += d2;
-        a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
-        a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
-      }
-    }
-  }
+// The voxel's frame of Alg. 1 from the sums about its first point p0 (S1 = sum d,
+// S2 = sum d d^T, d = p - p0, in the order s0, s1, s2, a00, a01, a02, a11, a12, a22),
+// written as its slot record (and rotated frame).
+__device__ __forceinline__ void prep_frame(const FitParams& P, const FitArgs& io, const Lists& L, int64_t v, int lst,
+                                        int slot, int n, int c, int off, double p0x, double p0y, double p0z,
+                                        const double (&sums)[9]) {
+  const double s0 = sums[0], s1 = sums[1], s2 = sums[2], a00 = sums[3], a01 = sums[4], a02 = sums[5],
+               a11 = sums[6], a12 = sums[7], a22 = sums[8];
+  (void)off;
   const double inv_n = 1.0 / (double)n;
   const double m0 = s0 * inv_n, m1 = s1 * inv_n, m2 = s2 * inv_n;
   double A[3][3];
@@ -352,6 +278,146 @@ __global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, floa
     r.fr.anc_w = 0.0;
   }
   L.recs[lst * L.stride + slot] = r;
+}
+
+// ---------------------------------------------------------------------------
+// 1. prep: tau test, PCA frame, bucketing (one thread per voxel; one wavefront per
+//    voxel of more than kPrepCoop points)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) prep_kernel(FitParams P, FitArgs io, float4* __restrict__ staged,
+                                                   Lists L) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = v < io.n_vox;
+  int lst = -1, n = 0, c = 0, off = 0;
+  if (valid) {
+    c = io.counts[v];
+    off = io.offsets[v];
+    n = c < P.cap ? c : P.cap;
+    if (n < P.tau || off < 0 || (int64_t)off + n > io.n_pts) {
+      // below tau (type (a)); a voxel whose points lie outside [0, n_pts) is not solved either
+      const bool in_range = off >= 0 && (int64_t)off + n <= io.n_pts;
+      io.status[v] = in_range ? (uint8_t)(VGPR_ST_BELOW_TAU | (c > P.cap ? VGPR_ST_CAPPED : 0)) : (uint8_t)0;
+      io.axis[v] = -1;
+      lst = kNanList;
+    } else {
+      lst = 0;
+      while (lst < kNumBuckets - 1 && n > P.bcap[lst]) ++lst;
+    }
+  }
+  // slot in the voxel's list: wavefront offsets within the workgroup through LDS,
+  // then one global atomic per workgroup and list
+  __shared__ uint32_t s_cnt[kLists], s_base[kLists];
+  const int lane = lane_id();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  if (threadIdx.x < kLists) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t woff = 0;
+  unsigned long long mymask = 0;
+#pragma unroll
+  for (int l = 0; l < kLists; ++l) {
+    const unsigned long long mk = __ballot(lst == l);
+    if (mk) {
+      const int leader = __ffsll((long long)mk) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&s_cnt[l], (uint32_t)__popcll(mk));
+      base = __shfl(base, leader, 64);
+      if (lst == l) {
+        woff = base;
+        mymask = mk;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kLists && s_cnt[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&L.count[threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  int slot = 0;
+  if (lst >= 0) slot = (int)(s_base[lst] + woff + __popcll(mymask & lt));
+  if (lst == kNanList) L.nan_list[slot] = (int32_t)v;
+  if (lst < 0 || lst == kNanList) return;
+  if (n > kPrepCoop) {
+    // staged, summed and framed by prep_big_kernel, one wavefront per voxel
+    L.big[atomicAdd(L.big_count, 1u)] = make_int4((int)v, lst, slot, 0);
+    return;
+  }
+
+  // stage the kept points and accumulate the covariance about the first point:
+  // S1 = sum d, S2 = sum d d^T with d = p - p0. Loads of four points are issued
+  // together so that a thread keeps several gathers in flight.
+  const int* __restrict__ perm = io.perm;
+  const float* __restrict__ xyz = io.xyz;
+  const float* __restrict__ noise = io.noise;
+  float4* __restrict__ st = staged;
+  const int i0 = perm ? perm[off] : off;
+  const float x0 = xyz[3 * (size_t)i0], y0 = xyz[3 * (size_t)i0 + 1], z0 = xyz[3 * (size_t)i0 + 2];
+  st[off] = make_float4(x0, y0, z0, noise ? noise[i0] : P.noise);
+  const double p0x = x0, p0y = y0, p0z = z0;
+  double s0 = 0, s1 = 0, s2 = 0, a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+  for (int i = 1; i < n; i += 4) {
+    float px[4], py[4], pz[4], pn[4];
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      const int ii = i + u4 < n ? i + u4 : i;
+      const int idx = perm ? perm[off + ii] : off + ii;
+      px[u4] = xyz[3 * (size_t)idx];
+      py[u4] = xyz[3 * (size_t)idx + 1];
+      pz[u4] = xyz[3 * (size_t)idx + 2];
+      pn[u4] = noise ? noise[idx] : P.noise;
+    }
+#pragma unroll
+    for (int u4 = 0; u4 < 4; ++u4) {
+      if (i + u4 < n) {
+        st[off + i + u4] = make_float4(px[u4], py[u4], pz[u4], pn[u4]);
+        const double d0 = (double)px[u4] - p0x;
+        const double d1 = (double)py[u4] - p0y;
+        const double d2 = (double)pz[u4] - p0z;
+        s0 += d0; s1 += d1; s2 += d2;
+        a00 += d0 * d0; a01 += d0 * d1; a02 += d0 * d2;
+        a11 += d1 * d1; a12 += d1 * d2; a22 += d2 * d2;
+      }
+    }
+  }
+  const double sums[9] = {s0, s1, s2, a00, a01, a02, a11, a12, a22};
+  prep_frame(P, io, L, v, lst, slot, n, c, off, p0x, p0y, p0z, sums);
+}
+
+// prep for the voxels of more than kPrepCoop points: one wavefront per voxel stages its
+// points (lane l takes points l, l + 64, ...) and sums its share of S1 and S2; the shares
+// are added across the wavefront and lane 0 computes the frame. Grid-stride over the list.
+__global__ void __launch_bounds__(256) prep_big_kernel(FitParams P, FitArgs io, float4* __restrict__ staged,
+                                                       Lists L) {
+  const int lane = lane_id();
+  const int gw = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
+  const int count = (int)*L.big_count;
+  const int* __restrict__ perm = io.perm;
+  const float* __restrict__ xyz = io.xyz;
+  const float* __restrict__ noise = io.noise;
+  for (int it = gw; it < count; it += nw) {
+    const int4 e = L.big[it];
+    const int v = e.x;
+    const int c = io.counts[v];
+    const int off = io.offsets[v];
+    const int n = c < P.cap ? c : P.cap;
+    const int i0 = perm ? perm[off] : off;
+    const float x0 = xyz[3 * (size_t)i0], y0 = xyz[3 * (size_t)i0 + 1], z0 = xyz[3 * (size_t)i0 + 2];
+    const double p0x = x0, p0y = y0, p0z = z0;
+    double t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = lane; i < n; i += 64) {
+      const int idx = perm ? perm[off + i] : off + i;
+      const float px = xyz[3 * (size_t)idx], py = xyz[3 * (size_t)idx + 1], pz = xyz[3 * (size_t)idx + 2];
+      staged[off + i] = make_float4(px, py, pz, noise ? noise[idx] : P.noise);
+      const double d0 = (double)px - p0x, d1 = (double)py - p0y, d2 = (double)pz - p0z;
+      t[0] += d0; t[1] += d1; t[2] += d2;
+      t[3] += d0 * d0; t[4] += d0 * d1; t[5] += d0 * d2;
+      t[6] += d1 * d1; t[7] += d1 * d2; t[8] += d2 * d2;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) t[k] += __shfl_xor(t[k], d, 64);
+    }
+    if (lane == 0) prep_frame(P, io, L, v, e.y, e.z, n, c, off, p0x, p0y, p0z, t);
+  }
 }
 
 // Zero the list counters with a kernel (no memset node when a caller captures the call in a graph).
@@ -2045,7 +2111,8 @@ size_t fit_work_bytes(const vgpr_ctx* ctx, int64_t n_vox, int64_t n_pts, const v
     if (p->max_pts > kBucketCap[b - 1]) tiles += Carver::round(tile_bucket_bytes(ctx, b, mixed));
   const size_t rot_bytes = p->frame_mode == 1 ? Carver::round(sizeof(RotRec) * (size_t)n_vox * kNumBuckets) : 0;
   return rot_bytes + Carver::round(sizeof(SlotRec) * (size_t)n_vox * kNumBuckets) + Carver::round(sizeof(float4) * (size_t)n_pts) +
-         Carver::round(sizeof(int32_t) * (size_t)n_vox) + 2 * Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
+         Carver::round(sizeof(int32_t) * (size_t)n_vox) + Carver::round(sizeof(int4) * (size_t)n_vox) +
+         2 * Carver::round(sizeof(int32_t) * (size_t)n_vox * kNumBuckets) +
          Carver::round(sizeof(uint32_t) * 64) + tiles + 4096;
 }
 
@@ -2068,9 +2135,11 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   SlotRec* recs = cv.take<SlotRec>((size_t)a.n_vox * kNumBuckets);
   float4* staged = cv.take<float4>((size_t)a.n_pts);
   int32_t* nan_list = cv.take<int32_t>((size_t)a.n_vox);
+  int4* big_list = cv.take<int4>((size_t)a.n_vox);
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   int32_t* flists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
-  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch, [32,39) refinement counts, [40,47) fetch
+  // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch, [32,39) refinement counts, [40,47) fetch,
+  // 48 voxels of more than kPrepCoop points
   uint32_t* ctr = cv.take<uint32_t>(64);
   double* tile_scratch[kNumBuckets] = {};
   const bool mixed = p->precision == VGPR_PREC_MIXED;
@@ -2100,12 +2169,17 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   const bool fp32 = p->precision == VGPR_PREC_FP32 || p->precision == VGPR_PREC_MIXED;
   P.mode = 2;
 
-  Lists L{recs, nan_list, ctr, a.n_vox, rots};
+  Lists L{recs, nan_list, ctr, a.n_vox, rots, big_list, ctr + 48};
   {
     ProfScope ps(ctx, "classify");
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((a.n_vox + 255) / 256)), dim3(256), 0, ctx->stream, P, a,
                        staged, L);
     VGPR_HIP(ctx, hipGetLastError());
+    if (p->max_pts > kPrepCoop) {
+      hipLaunchKernelGGL(prep_big_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 2048)), dim3(256), 0,
+                         ctx->stream, P, a, staged, L);
+      VGPR_HIP(ctx, hipGetLastError());
+    }
     hipLaunchKernelGGL(nan_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 4096)), dim3(256), 0,
                        ctx->stream, P, a.out, L);
     VGPR_HIP(ctx, hipGetLastError());
