@@ -88,6 +88,16 @@ def voxel_bytes(n: np.ndarray, m: int) -> np.ndarray:
     return 12.0 * n + 16 + 16.0 * m + 2
 
 
+def family_buckets(fam: str, tuning: dict, max_pts: int) -> tuple:
+    """Size buckets whose voxels a solver family's launch takes: its own, and with
+    tiled_merge the 512-point launch also takes the 256-point bucket."""
+    b = BUCKETS.index(int(fam.rsplit("_n", 1)[1]))
+    if b == len(BUCKETS) - 1 and tuning.get("tiled_merge") and max_pts > BUCKETS[-2] \
+            and tuning["tile_first_bucket"] <= len(BUCKETS) - 2 and not fam.startswith("refine"):
+        return (b - 1, b)
+    return (b,)
+
+
 def bucket_of(n: np.ndarray) -> np.ndarray:
     b = np.zeros(len(n), dtype=np.int64)
     for i, c in enumerate(BUCKETS[:-1]):
@@ -358,12 +368,11 @@ def main():
         dom = max((f for f in fam_time if f.startswith(("fit", "refine"))), key=lambda f: fam_time[f][0],
                   default=None)
         if dom is not None:
-            cap = int(dom.rsplit("_n", 1)[1])
-            b = BUCKETS.index(cap)
+            fb = family_buckets(dom, ctx.tuning().as_dict(), w["max_pts"])
             if dom.startswith("refine"):
-                sel = solved & refined & (b_of == b)
+                sel = solved & refined & np.isin(b_of, fb)
             else:
-                sel = solved & (b_of == b)
+                sel = solved & np.isin(b_of, fb)
             flops = float(fl[sel].sum())
             ms, cnt = fam_time[dom]
             per_launch_s = ms / cnt / 1e3
@@ -373,6 +382,7 @@ def main():
             dt = "f64" if ("f64" in dom) else "f32"
             roof = {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
                     "frac": achieved / PEAK[dt], "traffic": None, "kernel": dom,
+                    "voxel_points": f"({([0] + list(BUCKETS))[fb[0]]}, {BUCKETS[fb[-1]]}]",
                     "voxels_per_launch": int(sel.sum() / launches_per_step),
                     "algorithmic_bytes_per_launch": float(by[sel].sum() / launches_per_step),
                     "hbm_frac": float(by[sel].sum() / launches_per_step) / per_launch_s / 1e9 / HBM_PEAK}
@@ -411,8 +421,8 @@ def main():
         for fam, (ms, cnt) in iso.items():
             if not cnt or not fam.startswith(("fit", "refine")):
                 continue
-            b = BUCKETS.index(int(fam.rsplit("_n", 1)[1]))
-            sel = solved & (b_of == b) & (refined if fam.startswith("refine") else True)
+            fb = family_buckets(fam, t_saved, w["max_pts"])
+            sel = solved & np.isin(b_of, fb) & (refined if fam.startswith("refine") else True)
             lps = cnt / args.isolated_steps
             sec = ms / cnt / 1e3
             tf = float(fl[sel].sum()) / lps / sec / 1e12
@@ -791,7 +801,7 @@ def serve_leg(args, vgpr) -> dict:
     return out
 
 
-FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify"] + \
+FAMILIES = ["voxelize_key", "voxelize_sort", "voxelize_segment", "classify", "nan_rows"] + \
     [f"fit_f32_n{c}" for c in BUCKETS] + [f"fit_f64_n{c}" for c in BUCKETS] + [f"refine_f64_n{c}" for c in BUCKETS] + \
     ["refine_f32_n16"] + \
     [f"fit_mix_n{c}" for c in BUCKETS] + ["gauss_init"]

@@ -434,6 +434,9 @@ typedef struct {
                                  another, largest first (default {0, 2, 2, 1, 1, 3, 3}: 16
                                  points on the context's stream, 96/128, 32/64 and 256/512
                                  points each on one side stream) */
+  int32_t tiled_merge;        /* 1: the 256- and 512-point buckets run as one longest-first
+                                 launch of the 512-point tiled solver (the smaller voxels fill
+                                 the CUs the larger ones leave idle); 0: one launch each */
 } vgpr_tuning;
 
 VGPR_API vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t);
@@ -446,7 +449,8 @@ VGPR_API vgpr_status vgpr_get_tuning(const vgpr_ctx* ctx, vgpr_tuning* t);
  * family `name`, the summed duration in milliseconds and the number of
  * launches since the last read of that family, then resets it. Families:
  * "voxelize_key", "voxelize_sort" (all radix passes of a call),
- * "voxelize_segment", "classify", "gauss_init", "structure_loss" (the ring-search
+ * "voxelize_segment", "classify" (tau test, frames and bucket slots), "nan_rows"
+ * (the rows of voxels below tau), "gauss_init", "structure_loss" (the ring-search
  * kernel of vgpr_structure_loss), "structure_loss_brute" (its brute-force pass
  * over points far from every Gaussian), "fit_mix_n<C>" (MIXED mode tiled
  * solver), "fit_f32_n<C>" / "fit_f64_n<C>" (the

@@ -107,6 +107,8 @@ def tune(ctx, xyz, vox, params, reps: int = 5, log=print) -> dict:
     # bucket -> stream maps (0: the context's stream, 1..3: side streams): the default, the
     # 256-point bucket ahead of the 96/128-point ones, the 96-point bucket with the 32/64-point ones
     space.append(("bucket_stream", [list(vgpr.DEFAULT_BUCKET_STREAM), [0, 2, 2, 1, 1, 1, 3], [0, 2, 2, 2, 1, 1, 3]]))
+    if params.max_pts > 256:
+        space.append(("tiled_merge", [0, 1]))
     caps = (0, 16, 32, 64, 96, 128, 256)  # lower bound of each bucket
     space += [(("grid_scale", b), [2, 4, 8, 16]) for b in range(7) if params.max_pts > caps[b]]
     t0 = time.perf_counter()

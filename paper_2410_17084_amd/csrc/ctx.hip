@@ -287,6 +287,7 @@ vgpr_status vgpr_set_tuning(vgpr_ctx* ctx, const vgpr_tuning* t) {
   for (int b = 0; b < kNumBuckets; ++b)
     if (t->bucket_stream[b] < 0 || t->bucket_stream[b] > vgpr_ctx::kAux)
       return fail(ctx, VGPR_E_INVALID, "bucket_stream entries must be in [0, 3]");
+  if (t->tiled_merge != 0 && t->tiled_merge != 1) return fail(ctx, VGPR_E_INVALID, "tiled_merge must be 0 or 1");
   ctx->tune = *t;
   return VGPR_OK;
 }

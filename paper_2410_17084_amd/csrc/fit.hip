@@ -431,26 +431,36 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, int n) {
 // largest solves start first and the last ones to start are the shortest (list
 // scheduling by longest processing time). Slots with equal counts may come in any order;
 // every voxel is solved the same way whatever its position.
+// With count2, the slots of a second list at recs + stride2 join the sort (their order
+// entries are stride2 + slot) and *total receives the combined count.
 constexpr int kOrderThreads = 1024;
 __global__ void __launch_bounds__(kOrderThreads) order_kernel(const SlotRec* __restrict__ recs,
                                                               const uint32_t* __restrict__ count,
-                                                              int32_t* __restrict__ order) {
+                                                              int32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ count2, int32_t stride2,
+                                                              uint32_t* __restrict__ total) {
   static_assert(kMaxPtsLimit < kOrderThreads, "one count per thread in the scan");
   __shared__ uint32_t start[kMaxPtsLimit + 1];
   __shared__ uint32_t part[kOrderThreads / 64 + 1];
-  const int items = (int)*count;
+  const int items1 = (int)*count;
+  const int items = items1 + (count2 ? (int)*count2 : 0);
+  auto slot_of = [&](int i) { return i < items1 ? i : stride2 + (i - items1); };
   for (int i = threadIdx.x; i <= kMaxPtsLimit; i += kOrderThreads) start[i] = 0u;
   __syncthreads();
-  for (int i = threadIdx.x; i < items; i += kOrderThreads) atomicAdd(&start[recs[i].fr.n], 1u);
+  for (int i = threadIdx.x; i < items; i += kOrderThreads) atomicAdd(&start[recs[slot_of(i)].fr.n], 1u);
   __syncthreads();
   // first slot of each count, largest count first: thread t scans the count n = limit - t
   const int k = kMaxPtsLimit - (int)threadIdx.x;
   const uint32_t h = k >= 0 ? start[k] : 0u;
-  uint32_t total;
-  const uint32_t first = block_exclusive_sum<kOrderThreads>(h, part, &total);
+  uint32_t all;
+  const uint32_t first = block_exclusive_sum<kOrderThreads>(h, part, &all);
   if (k >= 0) start[k] = first;
   __syncthreads();
-  for (int i = threadIdx.x; i < items; i += kOrderThreads) order[atomicAdd(&start[recs[i].fr.n], 1u)] = i;
+  for (int i = threadIdx.x; i < items; i += kOrderThreads) {
+    const int sl = slot_of(i);
+    order[atomicAdd(&start[recs[sl].fr.n], 1u)] = sl;
+  }
+  if (total && threadIdx.x == 0) *total = (uint32_t)items;
 }
 
 // ---------------------------------------------------------------------------
@@ -2139,7 +2149,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   int32_t* rlists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   int32_t* flists = cv.take<int32_t>((size_t)a.n_vox * kNumBuckets);
   // [0,8) list counts, [8,15) fetch, [16,23) re-solve counts, [24,31) fetch, [32,39) refinement counts, [40,47) fetch,
-  // 48 voxels of more than kPrepCoop points
+  // 48 voxels of more than kPrepCoop points, 49 the merged 256/512-point list
   uint32_t* ctr = cv.take<uint32_t>(64);
   double* tile_scratch[kNumBuckets] = {};
   const bool mixed = p->precision == VGPR_PREC_MIXED;
@@ -2180,9 +2190,6 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
                          ctx->stream, P, a, staged, L);
       VGPR_HIP(ctx, hipGetLastError());
     }
-    hipLaunchKernelGGL(nan_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 4096)), dim3(256), 0,
-                       ctx->stream, P, a.out, L);
-    VGPR_HIP(ctx, hipGetLastError());
   }
   // Buckets run concurrently on the caller's stream and the three side streams
   // (bucket_stream of the launch choices; by default the 96/128-point buckets on
@@ -2202,6 +2209,7 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     const int s = tu.bucket_stream[b];
     return s == 0 ? ctx->stream : ctx->aux[s - 1];
   };
+  bool merge_top = false;  // set below, once the launched buckets are known
   auto launch_b = [&](int b) -> vgpr_status {
     const bool tiled = b >= first_tile_bucket(ctx);
     const bool wave = wave_ok(b) && b <= tu.wave_last_bucket;
@@ -2215,7 +2223,18 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
       if (mixed) l.fam = kFamMixed[b];
       // largest voxels first: the bucket's (otherwise unused) re-solve list holds the order
       int32_t* order = rlists + (size_t)b * a.n_vox;
-      hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, l.count, order);
+      if (b == kNumBuckets - 1 && merge_top) {
+        // the 256- and 512-point buckets as one launch: slots of both lists relative to the
+        // 256-point bucket's records (the 512-point list follows it at a.n_vox)
+        l.recs = recs + (size_t)(b - 1) * a.n_vox;
+        l.rots = rots ? rots + (size_t)(b - 1) * a.n_vox : nullptr;
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, ctr + b - 1, order,
+                           ctr + b, (int32_t)a.n_vox, ctr + 49);
+        l.count = ctr + 49;
+      } else {
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, l.count, order, nullptr,
+                           0, nullptr);
+      }
       VGPR_HIP(ctx, hipGetLastError());
       l.slots = order;
       return launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
@@ -2244,14 +2263,26 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
     return launch_bucket<double>(ctx, b, wave, R, a, staged, lr);
   };
   auto launched = [&](int b) { return p->max_pts > (b ? P.bcap[b - 1] : 0); };
+  // 256- and 512-point buckets merged into the 512-point launch (the combined slots must fit int32)
+  merge_top = tu.tiled_merge != 0 && launched(kNumBuckets - 1) && first_tile_bucket(ctx) <= kNumBuckets - 2 &&
+              a.n_vox < (int64_t(1) << 30);
+  auto skipped = [&](int b) { return merge_top && b == kNumBuckets - 2; };
   if (tiles_first)
     for (int b = kNumBuckets - 1; b >= first_tile_bucket(ctx); --b)
-      if (launched(b) && (st = launch_b(b)) != VGPR_OK) return st;
+      if (launched(b) && !skipped(b) && (st = launch_b(b)) != VGPR_OK) return st;
   VGPR_HIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int i = 0; i < vgpr_ctx::kAux; ++i) VGPR_HIP(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
   for (int b = kNumBuckets - 1; b >= 0; --b) {
-    if (!launched(b) || (tiles_first && b >= first_tile_bucket(ctx))) continue;
+    if (!launched(b) || skipped(b) || (tiles_first && b >= first_tile_bucket(ctx))) continue;
     if ((st = launch_b(b)) != VGPR_OK) return st;
+  }
+  {
+    // NaN rows of the voxels below tau: HBM writes only, queued behind the caller's stream's
+    // buckets so that they overlap the long solves instead of delaying the fork
+    ProfScope ps(ctx, "nan_rows");
+    hipLaunchKernelGGL(nan_kernel, dim3((unsigned)std::min<int64_t>((a.n_vox + 3) / 4, 4096)), dim3(256), 0,
+                       ctx->stream, P, a.out, L);
+    VGPR_HIP(ctx, hipGetLastError());
   }
   for (int i = 0; i < vgpr_ctx::kAux; ++i) {
     VGPR_HIP(ctx, hipEventRecord(ctx->join_ev[i], ctx->aux[i]));

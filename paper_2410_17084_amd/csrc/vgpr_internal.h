@@ -64,7 +64,7 @@ struct vgpr_ctx {
   int cu_count = 0;
   int live_maps = 0;          // maps created on this context and not yet destroyed
   int live_graphs = 0;        // captured graphs created on this context and not yet destroyed
-  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}, 5, 0, {0, 2, 2, 1, 1, 3, 3}};
+  vgpr_tuning tune{0, 2, 3, {4, 4, 4, 4, 4, 4, 4}, 5, 0, {0, 2, 2, 1, 1, 3, 3}, 0};
   static constexpr int kAux = 3;
   hipStream_t aux[kAux] = {nullptr, nullptr, nullptr};  // side streams the solver buckets fork onto
   hipEvent_t fork_ev = nullptr;

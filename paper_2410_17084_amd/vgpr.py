@@ -54,13 +54,13 @@ DEFAULT_BUCKET_STREAM = (0, 2, 2, 1, 1, 3, 3)
 class Tuning(C.Structure):
     _fields_ = [("fp32_last_bucket", C.c_int32), ("wave_last_bucket", C.c_int32), ("streams", C.c_int32),
                 ("grid_scale", C.c_int32 * 7), ("tile_first_bucket", C.c_int32), ("tiled_first", C.c_int32),
-                ("bucket_stream", C.c_int32 * 7)]
+                ("bucket_stream", C.c_int32 * 7), ("tiled_merge", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {"fp32_last_bucket": self.fp32_last_bucket, "wave_last_bucket": self.wave_last_bucket,
                 "streams": self.streams, "grid_scale": list(self.grid_scale),
                 "tile_first_bucket": self.tile_first_bucket, "tiled_first": self.tiled_first,
-                "bucket_stream": list(self.bucket_stream)}
+                "bucket_stream": list(self.bucket_stream), "tiled_merge": self.tiled_merge}
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tuning":
@@ -77,6 +77,7 @@ class Tuning(C.Structure):
         bs = list(d.get("bucket_stream", DEFAULT_BUCKET_STREAM))
         for i in range(7):
             t.bucket_stream[i] = bs[i]
+        t.tiled_merge = d.get("tiled_merge", 0)
         return t
 
 

@@ -227,6 +227,37 @@ def test_fit_large_voxels(env, nq, ls_mode):
         print(stats)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fit_tiled_merge(env, prec):
+    """The 256- and 512-point buckets as one longest-first launch of the 512-point solver:
+    every voxel is solved the same way as in its own bucket's launch (bit-identical), and
+    matches the oracle."""
+    torch, vgpr, ctx = env
+    p_ = {"fp64": vgpr.PREC_FP64, "mixed": vgpr.PREC_MIXED}[prec]
+    sizes = LARGE_SIZES + [140, 250, 260, 380, 500] * 3
+    xyz = _ragged_voxels(77, sizes)
+    w = dict(configs.params_for("spin32"), max_pts=512, min_pts=3, grid_side=16, ls_mode=1)
+    default = ctx.tuning().as_dict()
+    outs = []
+    try:
+        for merge in (0, 1):
+            say("fit tiled merge", prec, merge, len(xyz))
+            t = dict(default)
+            t.update(tiled_merge=merge, tile_first_bucket=4)
+            ctx.set_tuning(vgpr.Tuning.from_dict(t))
+            gv, res = run_fit(env, xyz, w, precision=p_)
+            outs.append([r.cpu().numpy() for r in res])
+    finally:
+        ctx.set_tuning(vgpr.Tuning.from_dict(default))
+    for g, r in zip(outs[1], outs[0]):
+        assert np.array_equal(g, r, equal_nan=True)
+    ov = O.voxelize(xyz, w["voxel_size"])
+    out, axis, status = (torch.from_numpy(x) for x in outs[1])
+    stats = parity.compare_fit(xyz, ov, parity.oracle_params(w), out, axis, status)
+    assert stats["solved"] == len(sizes)
+    print(stats)
+
+
 @pytest.mark.parametrize("tile_first", [2, 5])
 def test_fit_mixed_precision(env, tile_first):
     """MIXED mode (FP32 tiles, the query rows as one FP32 product with the formed inverse,
@@ -761,7 +792,8 @@ def test_tuning_choices(env):
         for g, r in zip(outs[1], outs[0]):
             assert np.array_equal(g, r, equal_nan=True)
         for key, val in (("streams", 2), ("tile_first_bucket", 1), ("wave_last_bucket", 3), ("tiled_first", 2),
-                         ("bucket_stream", [0, 1, 2, 4, 1, 2, 3]), ("bucket_stream", [-1] + [0] * 6)):
+                         ("bucket_stream", [0, 1, 2, 4, 1, 2, 3]), ("bucket_stream", [-1] + [0] * 6),
+                         ("tiled_merge", 2)):
             with pytest.raises(vgpr.VgprError):
                 bad = dict(default)
                 bad[key] = val
