@@ -25,8 +25,8 @@ namespace vgpr {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                      // per lane
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 elements per block
+constexpr int kSortItems = 4;                       // per lane (4 x 256: several tiles per CU at 1M points)
+constexpr int kSortTile = kSortThreads * kSortItems;  // 1024 elements per block
 constexpr int kSortWaves = kSortThreads / 64;
 
 // Result words read back to the host after a voxelize call.
