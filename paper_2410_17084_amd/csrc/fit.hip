@@ -38,6 +38,7 @@
 // double; in FP64 mode every voxel runs in double.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 #include <cfloat>
 
 #include "scan.h"
@@ -1082,6 +1083,17 @@ constexpr size_t tile_scratch_doubles_mixed(int npad) {
   return ((size_t)(3 * ((npad / kTile) * (npad / kTile + 1) / 2) + npad / kTile) * kTileDoubles + 1) / 2;
 }
 
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{}): a loop whose
+// index is a compile-time constant in every iteration.
+template <typename F, int... T>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, T...>) {
+  (f(std::integral_constant<int, T>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 __device__ __forceinline__ double sum16(double v) {
 #pragma unroll
   for (int d = 8; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -1286,45 +1298,47 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
 #pragma unroll
           for (int c = 0; c < kTile; ++c) B[c] = lane < kTile ? rb[lane * LD + I * kTile + c] : 0.0;
           bool bad = false;
-          for (int j = 0; j < kTile; ++j) {
-            // column j of the remaining rows through LDS (one wavefront: no workgroup barrier)
-            const double cj = B[0];
-            sdc[lane] = cj;
-            if (lane == j) sdy = fy;
-            wave_sync();
-            // first half of the column before the reciprocal, so the LDS reads overlap it
-            constexpr int H = kTile / 2;
-            double colv[H];
+          // four groups of eight pivot steps: group g reads and updates the 31 - 8 g entries
+          // that can still be live in its steps (B[1 .. 31 - j] at step j), not all 31
+          static_for<kTile / 8>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            constexpr int R = kTile - 1 - 8 * g;  // entries right of the group's first pivot
+            constexpr int H = R / 2;              // read before the reciprocal, so the reads overlap it
+#pragma unroll 1
+            for (int j = 8 * g; j < 8 * g + 8; ++j) {
+              // column j of the remaining rows through LDS (one wavefront: no workgroup barrier)
+              const double cj = B[0];
+              sdc[lane] = cj;
+              if (lane == j) sdy = fy;
+              wave_sync();
+              double col[R];
 #pragma unroll
-            for (int k = 0; k < H; ++k) colv[k] = sdc[j + 1 + k];
-            const double d = sdc[j];
-            const double yj = sdy;
-            // 1/sqrt(d) from the hardware estimate and two Newton steps (each doubles the
-            // correct bits), then 1/d = rs^2 and sqrt(d) = d rs
-            double rs = __builtin_amdgcn_rsq(d);
-            rs = rs * (1.5 - 0.5 * d * rs * rs);
-            rs = rs * (1.5 - 0.5 * d * rs * rs);
-            const double inv = rs * rs;
-            const double t = cj * inv;
-            bad |= !(d > 0.0);
-            if (lane == j) {
-              rb[lane * LD + I * kTile + j] = d * rs;  // sqrt(d)
-              srd[j] = rs;
-              sy[I * kTile + j] = yj * rs;
-            } else if (lane > j && lane < kTile) {
-              rb[lane * LD + I * kTile + j] = cj * rs;
+              for (int k = 0; k < H; ++k) col[k] = sdc[j + 1 + k];
+              const double d = sdc[j];
+              const double yj = sdy;
+              // 1/sqrt(d) from the hardware estimate and two Newton steps (each doubles the
+              // correct bits), then 1/d = rs^2 and sqrt(d) = d rs
+              double rs = __builtin_amdgcn_rsq(d);
+              rs = rs * (1.5 - 0.5 * d * rs * rs);
+              rs = rs * (1.5 - 0.5 * d * rs * rs);
+              const double inv = rs * rs;
+              const double t = cj * inv;
+              bad |= !(d > 0.0);
+              if (lane == j) {
+                rb[lane * LD + I * kTile + j] = d * rs;  // sqrt(d)
+                srd[j] = rs;
+                sy[I * kTile + j] = yj * rs;
+              } else if (lane > j && lane < kTile) {
+                rb[lane * LD + I * kTile + j] = cj * rs;
+              }
+              fy -= t * yj;
+#pragma unroll
+              for (int k = H; k < R; ++k) col[k] = sdc[j + 1 + k];
+#pragma unroll
+              for (int k = 0; k < R; ++k) B[k] = B[k + 1] - t * col[k];
+              wave_sync();  // every lane has read column j before it is overwritten
             }
-            fy -= t * yj;
-            double colw[kTile - 1 - H];
-#pragma unroll
-            for (int k = 0; k < kTile - 1 - H; ++k) colw[k] = sdc[j + 1 + H + k];
-#pragma unroll
-            for (int k = 0; k < H; ++k) B[k] = B[k + 1] - t * colv[k];
-#pragma unroll
-            for (int k = 0; k < kTile - 1 - H; ++k) B[H + k] = B[H + k + 1] - t * colw[k];
-            B[kTile - 1] = 0.0;
-            wave_sync();  // every lane has read column j before it is overwritten
-          }
+          });
           if (bad && lane == 0) s_fail = 1;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
