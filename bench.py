@@ -356,7 +356,7 @@ def main():
     value = n_solved * args.steps / elapsed
     dense = value * m
 
-    # roofline of the dominant kernel family (largest summed duration)
+    # roofline of the dominant kernel family
     roof = None
     kernels = {}
     if fam_time:
@@ -365,8 +365,17 @@ def main():
         by = voxel_bytes(n_kept, m)
         for fam, (ms, cnt) in fam_time.items():
             kernels[fam] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
-        dom = max((f for f in fam_time if f.startswith(("fit", "refine"))), key=lambda f: fam_time[f][0],
-                  default=None)
+        # dominant kernel: the solver family that carries the most algorithmic FLOPs of the step
+        # (a launch's duration in the concurrent step includes waiting for CUs, so the longest
+        # launch can be a small one); its roofline uses its duration in the timed region
+        tun = ctx.tuning().as_dict()
+
+        def fam_flops(f):
+            fb_ = family_buckets(f, tun, w["max_pts"])
+            sel_ = solved & np.isin(b_of, fb_) & (refined if f.startswith("refine") else True)
+            return float(fl[sel_].sum())
+        dom = max((f for f in fam_time if f.startswith(("fit", "refine"))),
+                  key=lambda f: (fam_flops(f), fam_time[f][0]), default=None)
         if dom is not None:
             fb = family_buckets(dom, ctx.tuning().as_dict(), w["max_pts"])
             if dom.startswith("refine"):
