@@ -427,23 +427,37 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// Longest-first order of one tiled bucket's slots: a counting sort by kept point count,
-// descending, in one workgroup. The tiled solvers hand out voxels in this order, so the
-// largest solves start first and the last ones to start are the shortest (list
+// Longest-first order of the tiled buckets' slots: a counting sort by kept point count,
+// descending, one workgroup per bucket. The tiled solvers hand out voxels in this order, so
+// the largest solves start first and the last ones to start are the shortest (list
 // scheduling by longest processing time). Slots with equal counts may come in any order;
-// every voxel is solved the same way whatever its position.
+// every voxel is solved the same way whatever its position. One launch on the caller's
+// stream before the buckets fork: a lone 1024-thread workgroup queued on a side stream
+// could wait a millisecond for a CU while the solvers hold them.
 // With count2, the slots of a second list at recs + stride2 join the sort (their order
 // entries are stride2 + slot) and *total receives the combined count.
+struct OrderJob {
+  const SlotRec* recs;
+  const uint32_t* count;
+  int32_t* order;
+  const uint32_t* count2;
+  int32_t stride2;
+  uint32_t* total;
+};
+struct OrderJobs {
+  OrderJob job[kNumBuckets];
+};
 constexpr int kOrderThreads = 1024;
-__global__ void __launch_bounds__(kOrderThreads) order_kernel(const SlotRec* __restrict__ recs,
-                                                              const uint32_t* __restrict__ count,
-                                                              int32_t* __restrict__ order,
-                                                              const uint32_t* __restrict__ count2, int32_t stride2,
-                                                              uint32_t* __restrict__ total) {
+__global__ void __launch_bounds__(kOrderThreads) order_kernel(OrderJobs jobs) {
   static_assert(kMaxPtsLimit < kOrderThreads, "one count per thread in the scan");
   __shared__ uint32_t start[kMaxPtsLimit + 1];
   __shared__ uint32_t part[kOrderThreads / 64 + 1];
-  const int items1 = (int)*count;
+  const OrderJob& jb = jobs.job[blockIdx.x];
+  const SlotRec* __restrict__ recs = jb.recs;
+  const uint32_t* count2 = jb.count2;
+  const int32_t stride2 = jb.stride2;
+  int32_t* __restrict__ order = jb.order;
+  const int items1 = (int)*jb.count;
   const int items = items1 + (count2 ? (int)*count2 : 0);
   auto slot_of = [&](int i) { return i < items1 ? i : stride2 + (i - items1); };
   for (int i = threadIdx.x; i <= kMaxPtsLimit; i += kOrderThreads) start[i] = 0u;
@@ -461,7 +475,7 @@ __global__ void __launch_bounds__(kOrderThreads) order_kernel(const SlotRec* __r
     const int sl = slot_of(i);
     order[atomicAdd(&start[recs[sl].fr.n], 1u)] = sl;
   }
-  if (total && threadIdx.x == 0) *total = (uint32_t)items;
+  if (jb.total && threadIdx.x == 0) *jb.total = (uint32_t)items;
 }
 
 // ---------------------------------------------------------------------------
@@ -2235,22 +2249,16 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
              rlists + (size_t)b * a.n_vox, ctr + 16 + b, a.n_vox, kFam[in_fp32 ? 0 : 2][b]};
     if (tiled) {
       if (mixed) l.fam = kFamMixed[b];
-      // largest voxels first: the bucket's (otherwise unused) re-solve list holds the order
-      int32_t* order = rlists + (size_t)b * a.n_vox;
+      // largest voxels first: the bucket's (otherwise unused) re-solve list holds the order,
+      // sorted before the fork
       if (b == kNumBuckets - 1 && merge_top) {
         // the 256- and 512-point buckets as one launch: slots of both lists relative to the
         // 256-point bucket's records (the 512-point list follows it at a.n_vox)
         l.recs = recs + (size_t)(b - 1) * a.n_vox;
         l.rots = rots ? rots + (size_t)(b - 1) * a.n_vox : nullptr;
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, ctr + b - 1, order,
-                           ctr + b, (int32_t)a.n_vox, ctr + 49);
         l.count = ctr + 49;
-      } else {
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, l.stream, l.recs, l.count, order, nullptr,
-                           0, nullptr);
       }
-      VGPR_HIP(ctx, hipGetLastError());
-      l.slots = order;
+      l.slots = rlists + (size_t)b * a.n_vox;
       return launch_tile(ctx, b, mixed, Pb, a, staged, l, tile_scratch[b]);
     }
     const bool refine_pass = in_fp32 && wave && b == 0;  // the wave shape that hands voxels to the refinement pass
@@ -2281,6 +2289,26 @@ vgpr_status fit_predict_impl(vgpr_ctx* ctx, const FitArgs& a, const vgpr_params*
   merge_top = tu.tiled_merge != 0 && launched(kNumBuckets - 1) && first_tile_bucket(ctx) <= kNumBuckets - 2 &&
               a.n_vox < (int64_t(1) << 30);
   auto skipped = [&](int b) { return merge_top && b == kNumBuckets - 2; };
+  {
+    // longest-first orders of the tiled buckets, one workgroup each
+    OrderJobs oj{};
+    int nj = 0;
+    for (int b = first_tile_bucket(ctx); b < kNumBuckets; ++b) {
+      if (!launched(b) || skipped(b)) continue;
+      const bool merged = b == kNumBuckets - 1 && merge_top;
+      OrderJob& j = oj.job[nj++];
+      j.recs = recs + (size_t)(merged ? b - 1 : b) * a.n_vox;
+      j.count = ctr + (merged ? b - 1 : b);
+      j.order = rlists + (size_t)b * a.n_vox;
+      j.count2 = merged ? ctr + b : nullptr;
+      j.stride2 = merged ? (int32_t)a.n_vox : 0;
+      j.total = merged ? ctr + 49 : nullptr;
+    }
+    if (nj > 0) {
+      hipLaunchKernelGGL(order_kernel, dim3((unsigned)nj), dim3(kOrderThreads), 0, ctx->stream, oj);
+      VGPR_HIP(ctx, hipGetLastError());
+    }
+  }
   if (tiles_first)
     for (int b = kNumBuckets - 1; b >= first_tile_bucket(ctx); --b)
       if (launched(b) && !skipped(b) && (st = launch_b(b)) != VGPR_OK) return st;
