@@ -1259,15 +1259,19 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
             if (data) Lij[frag_pos(row, col)] = acc[k];
           }
         }
-        // right-looking update of the block's later tiles: A(I,J') -= X L(J',J)^T,
-        // one 16 x 16 quarter per unit; the next unit's operand is fetched while
-        // the current one runs
+        // right-looking update of the block's later tiles: A(I,J') -= X L(J',J)^T. With the
+        // tiles in scratch a unit is a 32 x 16 column half (both row halves share the operand
+        // fragment of L(J',J), fetched once); with the tiles in LDS, a 16 x 16 quarter (twice
+        // the units to spread over the wavefronts). The next unit's operand is fetched while
+        // the current one runs.
+        constexpr int kHalves = kLdsTiles ? 1 : 2;  // row halves per unit
+        constexpr int kUnitsPerTile = 4 / kHalves;
         const int jlast = data ? I : nbd - 1;
-        const int units = (jlast - J) * 4;
+        const int units = (jlast - J) * kUnitsPerTile;
         int un = wid;
         double bf[8], bn[8];
         auto fetch = [&](int uu, double* dst) {
-          const int Jp = J + 1 + (uu >> 2), b2 = uu & 1;
+          const int Jp = J + 1 + uu / kUnitsPerTile, b2 = uu & 1;
           if (data && Jp == I) {  // L(I,J) itself: the tile buffer
 #pragma unroll
             for (int s = 0; s < 8; ++s) dst[s] = xb[(b2 * 16 + l16) * kXS + 4 * s + l4];
@@ -1280,15 +1284,25 @@ __global__ void __launch_bounds__(kTileThreads) fit_tile_kernel(FitParams P, Fit
         if (un < units) fetch(un, bf);
         for (; un < units; un += kTileWaves) {
           if (un + kTileWaves < units) fetch(un + kTileWaves, bn);
-          const int Jp = J + 1 + (un >> 2), a2 = (un >> 1) & 1, b2 = un & 1;
+          const int Jp = J + 1 + un / kUnitsPerTile, b2 = un & 1;
+          const int a0 = kHalves == 2 ? 0 : (un >> 1) & 1;  // first row half of the unit
           double* __restrict__ cp = rb + Jp * kTile + b2 * 16 + l16;
-          dbl4 c4;
+          dbl4 c[kHalves];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) c4[k] = cp[(a2 * 16 + l4 + 4 * k) * LD];
+          for (int h = 0; h < kHalves; ++h) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) c4 = mfma_f64(-xb[(a2 * 16 + l16) * kXS + 4 * s + l4], bf[s], c4);
+            for (int k = 0; k < 4; ++k) c[h][k] = cp[((a0 + h) * 16 + l4 + 4 * k) * LD];
+          }
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cp[(a2 * 16 + l4 + 4 * k) * LD] = c4[k];
+          for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int h = 0; h < kHalves; ++h) c[h] = mfma_f64(-xb[((a0 + h) * 16 + l16) * kXS + 4 * s + l4], bf[s], c[h]);
+          }
+#pragma unroll
+          for (int h = 0; h < kHalves; ++h) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cp[((a0 + h) * 16 + l4 + 4 * k) * LD] = c[h][k];
+          }
 #pragma unroll
           for (int s = 0; s < 8; ++s) bf[s] = bn[s];
         }
