@@ -3,10 +3,11 @@
 A step is one pass of the whole path over one batch of synthetic scans that
 are already resident in HBM: vgpr_voxelize over the batch (frames voxelized
 independently) followed by vgpr_fit_predict over every voxel of the batch.
-By default the batch is 64 seeded 32-beam x 1800-azimuth spinning scans of the
-box scene (voxel 0.5 m, cap 128, tau 3, 8x8 query grid); `--workload batched`
-and `--workload aggregated` run the 1 m / cap 256 and 0.1 m / cap 512 / 16x16
-workloads instead.
+By default the batch is one aggregated map-update frame: 10 seeded 128-beam x
+1024-azimuth scans of the box scene 0.05 m apart with pose noise (about 1M
+points; voxel 0.1 m, cap 512, tau 3, 16x16 query grid, length scale from PCA);
+`--workload spin32` and `--workload batched` run 64 spinning scans (0.5 m, cap
+128, 8x8) and the 16-frame spinning + rosette batch (1 m, cap 256, 8x8) instead.
 
 Prints one JSON line: solved voxels per second (plus dense points per second),
 the per-kernel roofline of the dominant kernel from HIP events on the
