@@ -5,7 +5,8 @@
 // frame's finite points.
 //
 // Exact search on a uniform grid of cell size h. The Gaussian centres are
-// sorted into cells with the voxelizer (Alg. S1's keys), each cell's range
+// sorted into cells with the voxelizer (Alg. S1's keys, cells in Morton order
+// so that consecutive Gaussians stay close in space), each cell's range
 // goes into an open-addressing table, and each point visits the cells of
 // growing cubes around its own cell (rings r = 0, 1, ..., eight lanes per
 // point sharing out each ring's cells). Every Gaussian
@@ -13,10 +14,10 @@
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
 // win. Points still open after kRingMax rings (far from the map) are resolved
-// by a tiled brute-force pass: each workgroup stages a chunk of Gaussians in
-// LDS and evaluates it against every open point that cannot rule the chunk out
-// by its bounding box, and the chunks' minima merge through a 64-bit atomic
-// minimum of (ordered value bits, index), seeded with what the rings found. Both passes
+// by an exhaustive pass over chunks of consecutive Gaussians: one wavefront per
+// point visits the chunks nearest box first, starting from what the rings
+// found, and skips every chunk whose bounding box rules it out against the
+// best so far (the minimum of (ordered value bits, index)). Both passes
 // take the minimum of the same float values with the same tie rule (lowest
 // value, then lowest index), so the result does not depend on h, which only
 // sets the speed.
@@ -32,7 +33,7 @@ namespace {
 
 constexpr int kRingMax = 3;
 constexpr int kReduceTile = 1024;
-constexpr int kBruteChunk = 2048;  // Gaussians a brute-force workgroup stages in LDS (40 KB)
+constexpr int kBruteChunk = 2048;  // consecutive Gaussians (cell order) under one bounding box
 
 __device__ __forceinline__ uint32_t float_order(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -247,15 +248,14 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
   }
 }
 
-// Bounding box and extreme mean scales of each brute-force chunk (the Gaussians
-// are in cell order, so a chunk covers a compact region): (min x, y, z, max S),
-// (max x, y, z, min S).
+// Bounding box and largest mean scale of each brute-force chunk (the Gaussians
+// are in Morton cell order, so a chunk covers a compact region):
+// (min x, y, z, max S), (max x, y, z, 0).
 __global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict__ G, int64_t nvalid,
                                                         float4* __restrict__ box) {
   const int64_t g0 = (int64_t)blockIdx.x * kBruteChunk;
   const int cnt = (int)min((int64_t)kBruteChunk, nvalid - g0);
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, sm = -INFINITY,
-        sn = INFINITY;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, sm = -INFINITY;
   for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
     const float4 q = G[g0 + t];
     lo[0] = fminf(lo[0], q.x);
@@ -265,7 +265,6 @@ __global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict
     hi[1] = fmaxf(hi[1], q.y);
     hi[2] = fmaxf(hi[2], q.z);
     sm = fmaxf(sm, q.w);
-    sn = fminf(sn, q.w);
   }
   for (int o = 32; o > 0; o >>= 1) {
     for (int a = 0; a < 3; ++a) {
@@ -273,13 +272,12 @@ __global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict
       hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
     }
     sm = fmaxf(sm, __shfl_xor(sm, o, 64));
-    sn = fminf(sn, __shfl_xor(sn, o, 64));
   }
-  __shared__ float red[4][8];
+  __shared__ float red[4][7];
   const int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
     red[w][0] = lo[0], red[w][1] = lo[1], red[w][2] = lo[2];
-    red[w][3] = hi[0], red[w][4] = hi[1], red[w][5] = hi[2], red[w][6] = sm, red[w][7] = sn;
+    red[w][3] = hi[0], red[w][4] = hi[1], red[w][5] = hi[2], red[w][6] = sm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -289,87 +287,80 @@ __global__ void __launch_bounds__(256) chunk_box_kernel(const float4* __restrict
         red[0][3 + a] = fmaxf(red[0][3 + a], red[k][3 + a]);
       }
       red[0][6] = fmaxf(red[0][6], red[k][6]);
-      red[0][7] = fminf(red[0][7], red[k][7]);
     }
     box[2 * blockIdx.x] = make_float4(red[0][0], red[0][1], red[0][2], red[0][6]);
-    box[2 * blockIdx.x + 1] = make_float4(red[0][3], red[0][4], red[0][5], red[0][7]);
+    box[2 * blockIdx.x + 1] = make_float4(red[0][3], red[0][4], red[0][5], 0.0f);
   }
 }
 
-// Upper bound of each open point's best value before any chunk is evaluated:
-// every Gaussian of a chunk lies within the distance to the box's farthest
-// corner, so the chunk's minimum is at most that distance minus its smallest
-// mean scale (rounded up by the margin).
-__global__ void __launch_bounds__(256) bound_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
-                                                    uint32_t n_open, const float4* __restrict__ box, int nchunk,
-                                                    float* __restrict__ ub) {
-  // one wavefront per open point, its lanes sharing out the chunk boxes
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+    const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// Nearest-first brute force for the points the rings left open, one wavefront
+// per point, its lanes sharing out first the chunk boxes and then one chunk's
+// Gaussians. Each round takes, among the chunks that the point cannot rule out
+// (box distance minus the chunk's largest mean scale above its best so far by
+// more than the rounding margin), the one with the nearest box that no earlier
+// round took (ordered by that bound, then by chunk number), evaluates all of
+// its Gaussians and tightens the best, kept as the minimum of (ordered value
+// bits, index) over the rings' seed and every chunk taken. Rounds end when
+// every chunk has been taken or ruled out. The best only falls, so a chunk
+// ruled out once stays ruled out, and one is ruled out only when none of its
+// values can reach the best: the result is that of evaluating every Gaussian.
+// The nearest chunks usually hold the answer, so a point takes a few rounds.
+__global__ void __launch_bounds__(256) nearest_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
+                                                      uint32_t n_open, const float4* __restrict__ G,
+                                                      const int32_t* __restrict__ gi, int64_t nvalid,
+                                                      const float4* __restrict__ box, int nchunk,
+                                                      const unsigned long long* __restrict__ seed,
+                                                      float* __restrict__ val, int32_t* __restrict__ arg) {
   const uint32_t o = (uint32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (o >= n_open) return;  // whole wavefronts: o is uniform in a wavefront
   const int lane = lane_id();
   const int i = fb[o];
-  const double x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
-  double u = INFINITY;
-  for (int c = lane; c < nchunk; c += 64) {
-    const float4 lo = box[2 * c], hi = box[2 * c + 1];
-    const double fx = fmax(fabs(x - lo.x), fabs(x - hi.x)), fy = fmax(fabs(y - lo.y), fabs(y - hi.y)),
-                 fz = fmax(fabs(z - lo.z), fabs(z - hi.z));
-    const double d = sqrt(fx * fx + fy * fy + fz * fz) - (double)hi.w;
-    u = fmin(u, d + 1e-5 * (fabs(d) + fabs((double)hi.w)) + 1e-7);
-  }
-  for (int off = 32; off > 0; off >>= 1) u = fmin(u, __shfl_xor(u, off, 64));
-  if (lane == 0) ub[o] = (float)u + 1e-6f * fabsf((float)u);  // rounded up past the float conversion
-}
-
-// Tiled brute force for the open points: workgroup (bx, by) stages Gaussians
-// [bx * kBruteChunk, ...) in LDS and takes the open points by = by, by + gy,
-// ... in strides of 256; each point's minimum over the chunk merges into
-// best[o] as (ordered value bits << 32 | index), so atomicMin keeps the lowest
-// value and, among equal values, the lowest index. A point skips a chunk whose
-// box distance minus its largest mean scale exceeds the point's current best
-// by more than the rounding margin (no value in the chunk can reach it).
-__global__ void __launch_bounds__(256) brute_kernel(const float* __restrict__ pts, const int32_t* __restrict__ fb,
-                                                    uint32_t n_open, const float4* __restrict__ G,
-                                                    const int32_t* __restrict__ gi, int64_t nvalid,
-                                                    const float4* __restrict__ box, const float* __restrict__ ub,
-                                                    unsigned long long* __restrict__ best) {
-  __shared__ float4 sg[kBruteChunk];
-  __shared__ int32_t sk[kBruteChunk];
-  const int64_t g0 = (int64_t)blockIdx.x * kBruteChunk;
-  const int cnt = (int)min((int64_t)kBruteChunk, nvalid - g0);
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    sg[t] = G[g0 + t];
-    sk[t] = gi[g0 + t];
-  }
-  __syncthreads();
-  const float4 blo = box[2 * blockIdx.x], bhi = box[2 * blockIdx.x + 1];
-  for (uint32_t o = blockIdx.y * blockDim.x + threadIdx.x; o < n_open; o += gridDim.y * blockDim.x) {
-    const int i = fb[o];
-    const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
-    const unsigned long long cur = __hip_atomic_load(&best[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double cv = (double)ub[o];
-    if (cur != ~0ull) cv = fmin(cv, (double)float_unorder((uint32_t)(cur >> 32)));
-    const double ex = fmax(fmax((double)blo.x - x, (double)x - bhi.x), 0.0);
-    const double ey = fmax(fmax((double)blo.y - y, (double)y - bhi.y), 0.0);
-    const double ez = fmax(fmax((double)blo.z - z, (double)z - bhi.z), 0.0);
-    const double lb = sqrt(ex * ex + ey * ey + ez * ez) - (double)blo.w;
-    if (lb > cv + 1e-5 * (fabs(lb) + fabs(cv) + fabs((double)blo.w)) + 1e-7) continue;
+  const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+  unsigned long long cur = seed[o];
+  unsigned long long next = 0;  // smallest (bound, chunk) key a round may still take
+  for (;;) {
+    const double cv = cur == ~0ull ? (double)INFINITY : (double)float_unorder((uint32_t)(cur >> 32));
+    unsigned long long pick = ~0ull;
+    for (int c = lane; c < nchunk; c += 64) {
+      const float4 lo = box[2 * c], hi = box[2 * c + 1];
+      const double ex = fmax(fmax((double)lo.x - x, (double)x - hi.x), 0.0);
+      const double ey = fmax(fmax((double)lo.y - y, (double)y - hi.y), 0.0);
+      const double ez = fmax(fmax((double)lo.z - z, (double)z - hi.z), 0.0);
+      const double lb = sqrt(ex * ex + ey * ey + ez * ez) - (double)lo.w;
+      if (lb > cv + 1e-5 * (fabs(lb) + fabs(cv) + fabs((double)lo.w)) + 1e-7) continue;
+      const unsigned long long key = ((unsigned long long)float_order((float)lb) << 32) | (uint32_t)c;
+      if (key >= next && key < pick) pick = key;
+    }
+    pick = wave_min_u64(pick);
+    if (pick == ~0ull) break;
+    next = pick + 1;
+    const int64_t g0 = (int64_t)(uint32_t)pick * kBruteChunk;
+    const int cnt = (int)min((int64_t)kBruteChunk, nvalid - g0);
     float b = INFINITY;
     int bk = INT_MAX;
-    for (int t = 0; t < cnt; ++t) take_min(gauss_value(x, y, z, sg[t]), sk[t], &b, &bk);
-    if (bk != INT_MAX) atomicMin(&best[o], pack_best(b, bk));
+#pragma unroll 4
+    for (int t = lane; t < cnt; t += 64) take_min(gauss_value(x, y, z, G[g0 + t]), gi[g0 + t], &b, &bk);
+    if (bk != INT_MAX) {
+      const unsigned long long pb = pack_best(b, bk);
+      cur = pb < cur ? pb : cur;
+    }
+    cur = wave_min_u64(cur);
   }
-}
-
-__global__ void __launch_bounds__(256) brute_finish(const int32_t* __restrict__ fb, uint32_t n_open,
-                                                    const unsigned long long* __restrict__ best,
-                                                    float* __restrict__ val, int32_t* __restrict__ arg) {
-  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_open) return;
-  const unsigned long long b = best[o];
-  const int i = fb[o];
-  val[i] = float_unorder((uint32_t)(b >> 32));
-  arg[i] = (int32_t)(uint32_t)(b & 0xffffffffull);
+  if (lane == 0) {
+    val[i] = cur == ~0ull ? INFINITY : float_unorder((uint32_t)(cur >> 32));
+    arg[i] = cur == ~0ull ? -1 : (int32_t)(uint32_t)(cur & 0xffffffffull);
+  }
 }
 
 // Deterministic sum of the finite points' values: fixed per-tile order, then
@@ -469,7 +460,7 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
                o_co = sub(4 * (size_t)ng + 16), o_cc = sub(4 * (size_t)ng + 16), o_pm = sub(4 * (size_t)ng + 16),
                o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
                o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
-               o_box = sub(32 * (size_t)((ng + kBruteChunk - 1) / kBruteChunk) + 32), o_ub = sub(4 * (size_t)n),
+               o_box = sub(32 * (size_t)((ng + kBruteChunk - 1) / kBruteChunk) + 32),
                o_bmax = sub(4 * (size_t)((ng + 255) / 256) + 16),
                o_val = sub(d_value ? 0 : 4 * (size_t)n),
                o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
@@ -493,7 +484,6 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   int32_t* fb = reinterpret_cast<int32_t*>(w + o_fb);
   unsigned long long* bbest = reinterpret_cast<unsigned long long*>(w + o_bb);
   float4* cbox = reinterpret_cast<float4*>(w + o_box);
-  float* ubound = reinterpret_cast<float*>(w + o_ub);
   uint32_t* bmax = reinterpret_cast<uint32_t*>(w + o_bmax);
   float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
   int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
@@ -510,7 +500,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
                        reinterpret_cast<const float4*>(d_gauss), ng, scale_mode, cen, sb, bmax);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, ctx->stream, bmax, nb, misc);
     VGPR_HIP(ctx, hipGetLastError());
-    st = voxelize_impl(ctx, cen, ng, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, ng, &nc, nullptr, &n_bad, head);
+    st = voxelize_impl(ctx, cen, ng, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, ng, &nc, nullptr, &n_bad, head,
+                       true);
     if (st != VGPR_OK) return st;
     if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during the loss");
   }
@@ -541,13 +532,8 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
     ProfScope ps(ctx, "structure_loss_brute");
     const unsigned gx = (unsigned)((nvalid + kBruteChunk - 1) / kBruteChunk);
     hipLaunchKernelGGL(chunk_box_kernel, dim3(gx), dim3(256), 0, ctx->stream, G, nvalid, cbox);
-    hipLaunchKernelGGL(bound_kernel, dim3((unsigned)(((int64_t)n_open * 64 + 255) / 256)), dim3(256), 0,
-                       ctx->stream, d_pts, fb, n_open, cbox, (int)gx, ubound);
-    const unsigned gy = (unsigned)std::min<int64_t>((n_open + 255) / 256, 16);
-    hipLaunchKernelGGL(brute_kernel, dim3(gx, gy), dim3(256), 0, ctx->stream, d_pts, fb, n_open, G, gi, nvalid,
-                       cbox, ubound, bbest);
-    hipLaunchKernelGGL(brute_finish, dim3((n_open + 255) / 256), dim3(256), 0, ctx->stream, fb, n_open, bbest, val,
-                       arg);
+    hipLaunchKernelGGL(nearest_kernel, dim3((unsigned)(((int64_t)n_open * 64 + 255) / 256)), dim3(256), 0,
+                       ctx->stream, d_pts, fb, n_open, G, gi, nvalid, cbox, (int)gx, bbest, val, arg);
     VGPR_HIP(ctx, hipGetLastError());
   }
   hipLaunchKernelGGL(sum_tiles, dim3((unsigned)nt), dim3(256), 0, ctx->stream, val, d_pts, n, tsum, tcnt);

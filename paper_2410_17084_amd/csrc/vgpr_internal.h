@@ -133,13 +133,15 @@ vgpr_status ensure_aux(vgpr_ctx* ctx);
 
 vgpr_status check_params(vgpr_ctx* ctx, const vgpr_params* p);
 
-// Voxelize into caller buffers; also used by the map. On success *n_vox holds
-// the voxel count (host) and, when d_sorted_keys is given, the sorted point
-// keys are left there (device, n_pts entries).
+// Voxelize into caller buffers; also used by the map and the structure loss.
+// On success *n_vox holds the voxel count (host). Voxels come out in x-major
+// order of their indices, or with `morton` in Morton order (index bits
+// interleaved), where each run of consecutive voxels covers a compact region.
 vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, const int64_t* h_frame_offsets,
                           int32_t n_frames, float voxel_size, uint64_t* d_keys, int32_t* d_offsets,
                           int32_t* d_counts, int32_t* d_perm, int64_t cap_vox, int64_t* h_n_vox,
-                          int64_t* h_frame_vox, int64_t* h_n_invalid, size_t work_offset);
+                          int64_t* h_frame_vox, int64_t* h_n_invalid, size_t work_offset,
+                          bool morton = false);
 
 // Solve the voxels of a list. `d_list` (nullable) maps output slot -> voxel
 // index into keys/offsets/counts; with NULL the slots are 0..n_vox-1.

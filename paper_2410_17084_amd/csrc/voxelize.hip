@@ -34,12 +34,45 @@ enum { R_NVOX = 0, R_INVALID = 1, R_RANGE = 2, R_NVALID = 3, R_MIN = 4, R_MAX = 
 
 // Compacted sort key: fields (k - kmin) in bx / by / bz bits (x highest), the
 // invalid flag at bit B = bx + by + bz, the frame index above it if embedded.
+// In Morton form the B field bits are interleaved instead (see interleave3), so
+// that runs of consecutive voxels cover compact 3-D regions.
 struct KeyForm {
   int bx, by, bz, B;
   int embed;           // frame index in bits [B + 1, ...)
   int key_passes;      // radix passes over the packed key
+  int morton;          // field bits interleaved (1) or concatenated (0)
   int64_t mn[3];       // per-axis minimum voxel index
 };
+
+// Morton interleave of fields of unequal widths: bit l of z, then of y, then
+// of x, for l = 0, 1, ...; an axis drops out once l reaches its width, so the
+// code takes exactly B bits and is a bijection of the three fields.
+__device__ __forceinline__ uint64_t interleave3(uint64_t ux, uint64_t uy, uint64_t uz, const KeyForm& kf) {
+  uint64_t tk = 0;
+  int o = 0;
+  const int top = max(kf.bx, max(kf.by, kf.bz));
+  for (int l = 0; l < top; ++l) {
+    if (l < kf.bz) tk |= ((uz >> l) & 1ull) << o++;
+    if (l < kf.by) tk |= ((uy >> l) & 1ull) << o++;
+    if (l < kf.bx) tk |= ((ux >> l) & 1ull) << o++;
+  }
+  return tk;
+}
+
+__device__ __forceinline__ void deinterleave3(uint64_t tk, const KeyForm& kf, uint64_t* ux, uint64_t* uy,
+                                              uint64_t* uz) {
+  uint64_t x = 0, y = 0, z = 0;
+  int o = 0;
+  const int top = max(kf.bx, max(kf.by, kf.bz));
+  for (int l = 0; l < top; ++l) {
+    if (l < kf.bz) z |= ((tk >> o++) & 1ull) << l;
+    if (l < kf.by) y |= ((tk >> o++) & 1ull) << l;
+    if (l < kf.bx) x |= ((tk >> o++) & 1ull) << l;
+  }
+  *ux = x;
+  *uy = y;
+  *uz = z;
+}
 
 __device__ __forceinline__ int frame_of(uint32_t idx, const int64_t* fo, int nf) {
   // largest f with fo[f] <= idx, for nf frames (fo has nf + 1 entries)
@@ -173,7 +206,7 @@ __global__ void __launch_bounds__(256) compose_kernel(uint64_t* __restrict__ key
     const uint64_t ux = (uint64_t)((int64_t)((key >> (2 * kKeyFieldBits)) & mask) - kKeyBias - kf.mn[0]);
     const uint64_t uy = (uint64_t)((int64_t)((key >> kKeyFieldBits) & mask) - kKeyBias - kf.mn[1]);
     const uint64_t uz = (uint64_t)((int64_t)(key & mask) - kKeyBias - kf.mn[2]);
-    tk = (ux << (kf.by + kf.bz)) | (uy << kf.bz) | uz;
+    tk = kf.morton ? interleave3(ux, uy, uz, kf) : (ux << (kf.by + kf.bz)) | (uy << kf.bz) | uz;
   }
   if (kf.embed && nf > 1) tk |= (uint64_t)frame_of((uint32_t)i, fo, nf) << (kf.B + 1);
   keys[i] = tk;
@@ -181,6 +214,12 @@ __global__ void __launch_bounds__(256) compose_kernel(uint64_t* __restrict__ key
 
 // Compacted sort key -> packed voxel key.
 __device__ __forceinline__ uint64_t unpack_sort_key(uint64_t tk, const KeyForm& kf) {
+  if (kf.morton) {
+    uint64_t ux, uy, uz;
+    deinterleave3(tk, kf, &ux, &uy, &uz);
+    return ((uint64_t)((int64_t)ux + kf.mn[0] + kKeyBias) << (2 * kKeyFieldBits)) |
+           ((uint64_t)((int64_t)uy + kf.mn[1] + kKeyBias) << kKeyFieldBits) | (uint64_t)((int64_t)uz + kf.mn[2] + kKeyBias);
+  }
   const uint64_t mz = (kf.bz ? (1ull << kf.bz) : 1ull) - 1ull, my = (kf.by ? (1ull << kf.by) : 1ull) - 1ull,
                  mx = (kf.bx ? (1ull << kf.bx) : 1ull) - 1ull;
   const int64_t kz = (int64_t)(tk & mz) + kf.mn[2];
@@ -405,7 +444,7 @@ __global__ void __launch_bounds__(256) seg_finish(const int32_t* __restrict__ ou
 vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, const int64_t* h_frame_offsets,
                           int32_t n_frames, float voxel_size, uint64_t* d_keys, int32_t* d_offsets,
                           int32_t* d_counts, int32_t* d_perm, int64_t cap_vox, int64_t* h_n_vox,
-                          int64_t* h_frame_vox, int64_t* h_n_invalid, size_t work_offset) {
+                          int64_t* h_frame_vox, int64_t* h_n_invalid, size_t work_offset, bool morton) {
   if (n_pts < 0 || n_pts >= (int64_t(1) << 31)) return fail(ctx, VGPR_E_INVALID, "n_pts out of range");
   if (cap_vox < 0) return fail(ctx, VGPR_E_INVALID, "cap_vox < 0");
   if (!h_n_vox) return fail(ctx, VGPR_E_INVALID, "h_n_vox is NULL");
@@ -457,6 +496,7 @@ vgpr_status voxelize_impl(vgpr_ctx* ctx, const float* d_xyz, int64_t n_pts, cons
   uint32_t* perm = reinterpret_cast<uint32_t*>(d_perm);
   KeyForm kf{};
   kf.B = 0;
+  kf.morton = morton ? 1 : 0;
   if (n > 0) {
     const double inv_s = 1.0 / (double)voxel_size;
     // keys and the batch's index ranges; the ranges decide the sort key's width

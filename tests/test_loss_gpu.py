@@ -156,6 +156,39 @@ def test_loss_edge_cases(env):
     assert np.isnan(loss) and nv == 0
 
 
+def test_loss_open_points_ties_across_chunks(env):
+    """Every point is farther from the map than the rings reach, so the exhaustive
+    chunk pass decides all of them. Six Gaussians lie at exactly the same value
+    from the origin, each in front of a cluster of its own (so they sit in
+    different chunks of 2048), and two pairs of them tie for the points
+    (1, 1, 0) and (-1, -1, 0): the lowest index must win whichever chunk is
+    visited first."""
+    torch, vgpr, ctx = env
+    r = rng(60)
+    dirs = np.array([[5, 0, 0], [-5, 0, 0], [0, 5, 0], [0, -5, 0], [0, 0, 5], [0, 0, -5]], np.float32)
+    clusters = []
+    for d in dirs:
+        u = r.normal(0, 1, (3000, 3))
+        u *= (r.random((3000, 1)) ** (1 / 3)) / np.linalg.norm(u, axis=1, keepdims=True)
+        clusters.append(d * 1.4 + u)             # a unit ball 7 m out: at least 6 m from the origin
+    C = np.concatenate(clusters).astype(np.float32)
+    G = np.zeros((len(C) + 6, 8), np.float32)
+    tie_at = np.array([9000, 15000, 3, 12000, 600, 17000])
+    rest = np.setdiff1d(np.arange(len(G)), tie_at)
+    G[rest, :3] = C
+    G[rest, 4:7] = r.uniform(0, 0.01, (len(rest), 3))
+    G[tie_at, :3] = dirs
+    G[tie_at, 4:7] = 0.004                       # equal mean scales: equal values at equal distances
+    P = np.concatenate([[[0, 0, 0], [1, 1, 0], [-1, -1, 0], [0, 0, 1]],
+                        r.uniform(-2, 2, (600, 3))]).astype(np.float32)
+    want = [tie_at.min(), min(tie_at[0], tie_at[2]), min(tie_at[1], tie_at[3]), tie_at[4]]
+    for cell in (0.05, 1.0):
+        say("loss open points, ties across chunks, cell", cell)
+        loss, nv, value, arg = ctx.structure_loss(dev(torch, P), dev(torch, G), cell_size=cell, scale_mode=0)
+        print(check(P, G, 0, value, arg, loss, nv))
+        assert arg.cpu().numpy()[:4].tolist() == want
+
+
 def test_loss_argument_errors(env):
     torch, vgpr, ctx = env
     P = dev(torch, np.zeros((4, 3)))
