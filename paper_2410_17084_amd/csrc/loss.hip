@@ -63,97 +63,166 @@ __device__ __forceinline__ void take_min(float v, int k, float* best, int* bk) {
   }
 }
 
-// Centres (NaN for a Gaussian that is not a candidate, so the voxelizer drops
-// it), mean scales, and the largest mean scale among candidates.
+// Mean scale of a Gaussian row pair and whether it is a candidate (finite
+// centre and scale); the counting and the compacting kernel both call it.
+__device__ __forceinline__ bool row_scale(float4 a, float4 b, int scale_mode, float* s) {
+  if (scale_mode == 1)
+    *s = __fdiv_rn(__fadd_rn(__fadd_rn(__fsqrt_rn(b.x), __fsqrt_rn(b.y)), __fsqrt_rn(b.z)), 3.0f);
+  else
+    *s = __fdiv_rn(__fadd_rn(__fadd_rn(b.x, b.y), b.z), 3.0f);
+  return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(*s);
+}
+
+// Per-workgroup candidate count and largest mean scale (ordered bits).
 __global__ void __launch_bounds__(256) prepare_kernel(const float4* __restrict__ rows, int64_t ng, int scale_mode,
-                                                      float* __restrict__ cen, float* __restrict__ sb,
-                                                      uint32_t* __restrict__ bmax) {
+                                                      uint32_t* __restrict__ bcnt, uint32_t* __restrict__ bmax) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t m = 0u;
+  uint32_t m = 0u, c = 0u;
   if (k < ng) {
-    const float4 a = rows[2 * k], b = rows[2 * k + 1];
     float s;
-    if (scale_mode == 1)
-      s = __fdiv_rn(__fadd_rn(__fadd_rn(__fsqrt_rn(b.x), __fsqrt_rn(b.y)), __fsqrt_rn(b.z)), 3.0f);
-    else
-      s = __fdiv_rn(__fadd_rn(__fadd_rn(b.x, b.y), b.z), 3.0f);
-    const bool ok = isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(s);
-    cen[3 * k + 0] = ok ? a.x : __int_as_float(0x7fc00000);
-    cen[3 * k + 1] = a.y;
-    cen[3 * k + 2] = a.z;
-    sb[k] = s;
-    if (ok) m = float_order(s);
+    if (row_scale(rows[2 * k], rows[2 * k + 1], scale_mode, &s)) {
+      m = float_order(s);
+      c = 1u;
+    }
   }
-  // workgroup max into bmax[block] (a device-wide atomic per wavefront on one address serialised)
-  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-  __shared__ uint32_t wm[4];
-  if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
+  // workgroup max and count (a device-wide atomic per wavefront on one address serialised)
+  for (int o = 32; o > 0; o >>= 1) {
+    m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    c += (uint32_t)__shfl_xor((int)c, o, 64);
+  }
+  __shared__ uint32_t wm[4], wc[4];
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = m, wc[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+  if (threadIdx.x == 0) {
+    bmax[blockIdx.x] = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+    bcnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+  }
 }
 
-// The largest mean scale (ordered bits) over the workgroup maxima.
-__global__ void __launch_bounds__(256) max_kernel(const uint32_t* __restrict__ bmax, int64_t nb,
-                                                  uint32_t* __restrict__ smax) {
-  uint32_t m = 0u;
-  for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) m = max(m, bmax[i]);
+// One workgroup: the largest mean scale over the workgroup maxima into smax[0],
+// the exclusive scan of the workgroup counts into boff and the candidate count
+// into smax[2].
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(const uint32_t* __restrict__ bmax,
+                                                            const uint32_t* __restrict__ bcnt, int64_t nb,
+                                                            uint32_t* __restrict__ boff,
+                                                            uint32_t* __restrict__ smax) {
+  __shared__ uint32_t sm[kScanThreads / 64 + 1];
+  uint32_t m = 0u, run = 0u;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t c = b < nb ? bcnt[b] : 0u;
+    if (b < nb) m = max(m, bmax[b]);
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_sum<kScanThreads>(c, sm, &tot);
+    if (b < nb) boff[b] = run + ex;
+    run += tot;
+  }
   for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-  __shared__ uint32_t wm[4];
+  __shared__ uint32_t wm[kScanThreads / 64];
   if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) *smax = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kScanThreads / 64; ++w) m = max(m, wm[w]);
+    smax[0] = m;
+    smax[2] = run;
+  }
 }
 
-// Gaussians in cell order as (x, y, z, S) with their original index, and the
-// cell table (key -> cell).
+// The candidates' centres and mean scales, compacted in row order, with their
+// row indices (the voxelizer then sorts only candidates).
+__global__ void __launch_bounds__(256) compact_kernel(const float4* __restrict__ rows, int64_t ng, int scale_mode,
+                                                      const uint32_t* __restrict__ boff, float* __restrict__ cen,
+                                                      float* __restrict__ sb, int32_t* __restrict__ orig) {
+  __shared__ uint32_t sm[256 / 64 + 1];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  float s = 0.f;
+  bool ok = false;
+  if (k < ng) {
+    a = rows[2 * k];
+    ok = row_scale(a, rows[2 * k + 1], scale_mode, &s);
+  }
+  uint32_t tot;
+  const uint32_t pos = boff[blockIdx.x] + block_exclusive_sum<256>(ok ? 1u : 0u, sm, &tot);
+  if (ok) {
+    cen[3 * (size_t)pos + 0] = a.x;
+    cen[3 * (size_t)pos + 1] = a.y;
+    cen[3 * (size_t)pos + 2] = a.z;
+    sb[pos] = s;
+    orig[pos] = (int32_t)k;
+  }
+}
+
+// Gaussians in cell order as (x, y, z, S) with their row index, and the cell
+// table (cell key -> (key, first Gaussian, count) in one 16-byte slot, so that
+// a lookup touches one cache line) behind an occupancy filter: one bit per
+// hash value, set for every occupied cell, at least 64 bits per cell, so that
+// most empty cells of a ring are rejected by one load from a small array.
 __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ cen, const float* __restrict__ sb,
+                                                     const int32_t* __restrict__ orig,
                                                      const int32_t* __restrict__ perm, int64_t nvalid,
                                                      float4* __restrict__ G, int32_t* __restrict__ gi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvalid) return;
   const int k = perm[i];
   G[i] = make_float4(cen[3 * (size_t)k], cen[3 * (size_t)k + 1], cen[3 * (size_t)k + 2], sb[k]);
-  gi[i] = k;
+  gi[i] = orig[k];
 }
 
-__global__ void __launch_bounds__(256) table_kernel(const uint64_t* __restrict__ ckeys, int64_t nc,
-                                                    uint64_t* __restrict__ tkey, int32_t* __restrict__ tcell,
-                                                    int64_t nslots) {
+struct alignas(16) Slot {
+  uint64_t key;  // cell key, or the sentinel for an empty slot
+  int32_t off;   // first Gaussian of the cell (cell order)
+  int32_t cnt;   // Gaussians in the cell
+};
+
+__global__ void __launch_bounds__(256) table_kernel(const uint64_t* __restrict__ ckeys, const int32_t* __restrict__ coff,
+                                                    const int32_t* __restrict__ ccnt, int64_t nc,
+                                                    Slot* __restrict__ table, int64_t nslots,
+                                                    uint32_t* __restrict__ filter, int fshift) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const uint64_t key = ckeys[c];
-  int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
+  const uint64_t hk = mix64(key);
+  const uint64_t fi = hk >> fshift;  // top bits: independent of the slot's low bits
+  atomicOr(&filter[fi >> 5], 1u << (fi & 31));
+  int64_t s = (int64_t)(hk & (uint64_t)(nslots - 1));
   for (int64_t probe = 0; probe < nslots; ++probe) {
-    const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tkey[s]),
+    const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&table[s].key),
                                               (unsigned long long)kKeySentinel, (unsigned long long)key);
     if (prev == kKeySentinel) {  // cell keys are unique: no two threads insert the same key
-      tcell[s] = (int32_t)c;
+      table[s].off = coff[c];
+      table[s].cnt = ccnt[c];
       return;
     }
     s = (s + 1) & (nslots - 1);
   }
 }
 
-__device__ __forceinline__ int lookup(const uint64_t* __restrict__ tkey, const int32_t* __restrict__ tcell,
-                                      int64_t nslots, uint64_t key) {
-  int64_t s = (int64_t)(mix64(key) & (uint64_t)(nslots - 1));
+// The Gaussians of cell `key` (hash hk), or false if the cell holds none.
+__device__ __forceinline__ bool lookup(const Slot* __restrict__ table, int64_t nslots, uint64_t key, uint64_t hk,
+                                       int* off, int* cnt) {
+  int64_t s = (int64_t)(hk & (uint64_t)(nslots - 1));
   for (int64_t probe = 0; probe < nslots; ++probe) {
-    const uint64_t k = tkey[s];
-    if (k == key) return tcell[s];
-    if (k == kKeySentinel) return -1;
+    const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(&table[s]);
+    if (q.x == key) {
+      *off = (int)(uint32_t)q.y;
+      *cnt = (int)(uint32_t)(q.y >> 32);
+      return true;
+    }
+    if (q.x == kKeySentinel) return false;
     s = (s + 1) & (nslots - 1);
   }
-  return -1;
+  return false;
 }
 
 struct Grid {
   const float4* G;
   const int32_t* gi;
-  const uint64_t* tkey;
-  const int32_t* tcell;
+  const Slot* table;
   int64_t nslots;
-  const int32_t* coff;
-  const int32_t* ccnt;
+  const uint32_t* filter;
+  int fshift;
   double inv_h, h;
   const uint32_t* smax;
 };
@@ -207,10 +276,12 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
         const uint64_t key = ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
                              ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) |
                              (uint64_t)((int64_t)cz + kKeyBias);
-        const int c = lookup(g.tkey, g.tcell, g.nslots, key);
-        if (c < 0) continue;
-        const int e = g.coff[c] + g.ccnt[c];
-        for (int j = g.coff[c]; j < e; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
+        const uint64_t hk = mix64(key);
+        const uint64_t fi = hk >> g.fshift;
+        if (!((g.filter[fi >> 5] >> (fi & 31)) & 1u)) continue;
+        int off, cnt;
+        if (!lookup(g.table, g.nslots, key, hk, &off, &cnt)) continue;
+        for (int j = off; j < off + cnt; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
       }
     }
 #pragma unroll
@@ -458,10 +529,11 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   };
   const size_t o_cen = sub(12 * (size_t)ng + 16), o_sb = sub(4 * (size_t)ng + 16), o_ck = sub(8 * (size_t)ng + 16),
                o_co = sub(4 * (size_t)ng + 16), o_cc = sub(4 * (size_t)ng + 16), o_pm = sub(4 * (size_t)ng + 16),
-               o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_tk = sub(8 * (size_t)ns),
-               o_tc = sub(4 * (size_t)ns), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
+               o_G = sub(16 * (size_t)ng + 16), o_gi = sub(4 * (size_t)ng + 16), o_or = sub(4 * (size_t)ng + 16),
+               o_tb = sub(sizeof(Slot) * (size_t)ns), o_fl = sub(16 * (size_t)ng + 64), o_fb = sub(4 * (size_t)n), o_bb = sub(8 * (size_t)n),
                o_box = sub(32 * (size_t)((ng + kBruteChunk - 1) / kBruteChunk) + 32),
-               o_bmax = sub(4 * (size_t)((ng + 255) / 256) + 16),
+               o_bmax = sub(4 * (size_t)((ng + 255) / 256) + 16), o_bc = sub(4 * (size_t)((ng + 255) / 256) + 16),
+               o_bo = sub(4 * (size_t)((ng + 255) / 256) + 16),
                o_val = sub(d_value ? 0 : 4 * (size_t)n),
                o_arg = sub(d_arg ? 0 : 4 * (size_t)n), o_ts = sub(8 * (size_t)nt), o_tn = sub(4 * (size_t)nt),
                o_misc = sub(64);
@@ -479,44 +551,65 @@ extern "C" vgpr_status vgpr_structure_loss(vgpr_ctx* ctx, const float* d_pts, in
   int32_t* perm = reinterpret_cast<int32_t*>(w + o_pm);
   float4* G = reinterpret_cast<float4*>(w + o_G);
   int32_t* gi = reinterpret_cast<int32_t*>(w + o_gi);
-  uint64_t* tkey = reinterpret_cast<uint64_t*>(w + o_tk);
-  int32_t* tcell = reinterpret_cast<int32_t*>(w + o_tc);
+  int32_t* orig = reinterpret_cast<int32_t*>(w + o_or);
+  Slot* table = reinterpret_cast<Slot*>(w + o_tb);
+  uint32_t* filter = reinterpret_cast<uint32_t*>(w + o_fl);
   int32_t* fb = reinterpret_cast<int32_t*>(w + o_fb);
   unsigned long long* bbest = reinterpret_cast<unsigned long long*>(w + o_bb);
   float4* cbox = reinterpret_cast<float4*>(w + o_box);
   uint32_t* bmax = reinterpret_cast<uint32_t*>(w + o_bmax);
+  uint32_t* bcnt = reinterpret_cast<uint32_t*>(w + o_bc);
+  uint32_t* boff = reinterpret_cast<uint32_t*>(w + o_bo);
   float* val = d_value ? d_value : reinterpret_cast<float*>(w + o_val);
   int32_t* arg = d_arg ? d_arg : reinterpret_cast<int32_t*>(w + o_arg);
   double* tsum = reinterpret_cast<double*>(w + o_ts);
   uint32_t* tcnt = reinterpret_cast<uint32_t*>(w + o_tn);
-  uint32_t* misc = reinterpret_cast<uint32_t*>(w + o_misc);  // [0] max mean scale (ordered bits), [1] open points
+  // [0] largest mean scale (ordered bits), [1] open points, [2] candidates
+  uint32_t* misc = reinterpret_cast<uint32_t*>(w + o_misc);
   double* dsum = reinterpret_cast<double*>(w + o_misc + 16);
 
   VGPR_HIP(ctx, hipMemsetAsync(misc, 0, 64, ctx->stream));
-  int64_t nc = 0, n_bad = 0;
+  int64_t nc = 0, n_bad = 0, n_cand = 0;
   if (ng > 0) {
+    // candidates only (rows of unsolved voxels are NaN) go to the voxelizer
     const int64_t nb = (ng + 255) / 256;
-    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, ctx->stream,
-                       reinterpret_cast<const float4*>(d_gauss), ng, scale_mode, cen, sb, bmax);
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, ctx->stream, bmax, nb, misc);
+    const float4* rows = reinterpret_cast<const float4*>(d_gauss);
+    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, ctx->stream, rows, ng, scale_mode, bcnt,
+                       bmax);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, ctx->stream, bmax, bcnt, nb, boff, misc);
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)nb), dim3(256), 0, ctx->stream, rows, ng, scale_mode, boff,
+                       cen, sb, orig);
     VGPR_HIP(ctx, hipGetLastError());
-    st = voxelize_impl(ctx, cen, ng, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, ng, &nc, nullptr, &n_bad, head,
-                       true);
-    if (st != VGPR_OK) return st;
-    if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during the loss");
+    void* hp0 = ctx->pinned;
+    VGPR_HIP(ctx, hipMemcpyAsync(hp0, misc + 2, 4, hipMemcpyDeviceToHost, ctx->stream));
+    VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    n_cand = static_cast<const uint32_t*>(hp0)[0];
+    if (n_cand > 0) {
+      st = voxelize_impl(ctx, cen, n_cand, nullptr, 1, cell_size, ckeys, coff, ccnt, perm, n_cand, &nc, nullptr,
+                         &n_bad, head, true);
+      if (st != VGPR_OK) return st;
+      if (ctx->work.ptr != static_cast<void*>(w)) return fail(ctx, VGPR_E_DEVICE, "workspace moved during the loss");
+    }
   }
-  const int64_t nvalid = ng - n_bad;
+  const int64_t nvalid = n_cand - n_bad;
   const bool has_cand = nvalid > 0;
+  // table of at least twice the cell count (at most ns, since nc <= ng); filter
+  // of at least 64 bits per cell (at most 16 ng bytes)
+  int64_t nsl = 2;
+  while (nsl < 2 * nc) nsl <<= 1;
+  int lf = 6;
+  while ((int64_t(1) << lf) < 64 * nc) ++lf;
   if (has_cand) {
-    VGPR_HIP(ctx, hipMemsetAsync(tkey, 0xFF, 8 * (size_t)ns, ctx->stream));
+    VGPR_HIP(ctx, hipMemsetAsync(table, 0xFF, sizeof(Slot) * (size_t)nsl, ctx->stream));
+    VGPR_HIP(ctx, hipMemsetAsync(filter, 0, (size_t(1) << lf) / 8, ctx->stream));
     hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nvalid + 255) / 256)), dim3(256), 0, ctx->stream, cen, sb,
-                       perm, nvalid, G, gi);
-    hipLaunchKernelGGL(table_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, ctx->stream, ckeys, nc, tkey,
-                       tcell, ns);
+                       orig, perm, nvalid, G, gi);
+    hipLaunchKernelGGL(table_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, ctx->stream, ckeys, coff, ccnt,
+                       nc, table, nsl, filter, 64 - lf);
     VGPR_HIP(ctx, hipGetLastError());
   }
   const double inv_h = 1.0 / (double)cell_size;
-  Grid grid{G, gi, tkey, tcell, ns, coff, ccnt, inv_h, (double)cell_size, misc};
+  Grid grid{G, gi, table, nsl, filter, 64 - lf, inv_h, (double)cell_size, misc};
   {
     ProfScope ps(ctx, "structure_loss");
     hipLaunchKernelGGL(query_kernel, dim3((unsigned)((n * kGroup + 255) / 256)), dim3(256), 0, ctx->stream, d_pts, n, grid,
