@@ -45,7 +45,7 @@ struct vgpr_map {
   int mode = 0;              // 0: re-solve on the stored points; 1: covariance feedback
   float4* pred = nullptr;    // mode 1: m predicted rows (x, y, z, var) per voxel
   uint8_t* vpred = nullptr;  // mode 1: the voxel holds a prediction (it is in the map)
-  void* stage = nullptr;     // mode 1: stacked points, noise, per-update records, fit scratch
+  void* stage = nullptr;     // the solve's inputs (mode 0: pooled points; mode 1: stacked points, noise) and scratch
   size_t stage_bytes = 0;
   int64_t host_voxels = 0;   // voxels held, as read back after the last update (host copy)
 };
@@ -169,46 +169,72 @@ __global__ void __launch_bounds__(256) insert_kernel(vgpr_map M, const float* __
 
 constexpr int kCompactTile = 1024;
 
-__global__ void __launch_bounds__(1024) compact_reduce(const uint32_t* __restrict__ flag, int64_t n,
-                                                       uint32_t* __restrict__ block_sums) {
+// The update list: flagged frame voxels in frame order. Besides each entry's
+// slot, the scan gives each entry's first point in a back-to-back staging of
+// the voxels' pooled points (update mode 0 solves from that staging).
+__device__ __forceinline__ uint32_t pooled_of(const vgpr_map& M, const int32_t* ids, const uint32_t* flag,
+                                              int64_t i, int64_t n) {
+  return (i < n && flag[i]) ? (uint32_t)M.vstored[ids[i]] : 0u;
+}
+
+__global__ void __launch_bounds__(1024) compact_reduce(vgpr_map M, const uint32_t* __restrict__ flag,
+                                                       const int32_t* __restrict__ ids, int64_t n,
+                                                       uint32_t* __restrict__ block_sums,
+                                                       uint32_t* __restrict__ block_pts) {
   const int64_t i = (int64_t)blockIdx.x * kCompactTile + threadIdx.x;
-  uint32_t c = wave_sum(i < n ? flag[i] : 0u);
-  __shared__ uint32_t s[16];
-  if (lane_id() == 0) s[threadIdx.x >> 6] = c;
+  const uint32_t c = wave_sum(i < n ? flag[i] : 0u);
+  const uint32_t q = wave_sum(pooled_of(M, ids, flag, i, n));
+  __shared__ uint32_t s[16], sq[16];
+  if (lane_id() == 0) s[threadIdx.x >> 6] = c, sq[threadIdx.x >> 6] = q;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < 16; ++w) t += s[w];
+    uint32_t t = 0, tq = 0;
+    for (int w = 0; w < 16; ++w) t += s[w], tq += sq[w];
     block_sums[blockIdx.x] = t;
+    block_pts[blockIdx.x] = tq;
   }
 }
 
-__global__ void __launch_bounds__(1024) compact_scan(uint32_t* __restrict__ block_sums, int nblocks,
+// One workgroup: exclusive scans of both per-block sums; total[0] = entries,
+// total[1] = their pooled points.
+__global__ void __launch_bounds__(1024) compact_scan(uint32_t* __restrict__ block_sums,
+                                                     uint32_t* __restrict__ block_pts, int nblocks,
                                                      unsigned long long* __restrict__ total) {
   __shared__ uint32_t smem[17];
-  uint32_t carry = 0;
+  uint32_t carry = 0, carry_q = 0;
   for (int s = 0; s < nblocks; s += 1024) {
     const int i = s + threadIdx.x;
     const uint32_t v = i < nblocks ? block_sums[i] : 0u;
-    uint32_t tot;
+    const uint32_t q = i < nblocks ? block_pts[i] : 0u;
+    uint32_t tot, tot_q;
     const uint32_t ex = block_exclusive_sum<1024>(v, smem, &tot);
-    if (i < nblocks) block_sums[i] = carry + ex;
+    const uint32_t ex_q = block_exclusive_sum<1024>(q, smem, &tot_q);
+    if (i < nblocks) {
+      block_sums[i] = carry + ex;
+      block_pts[i] = carry_q + ex_q;
+    }
     carry += tot;
+    carry_q += tot_q;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    total[0] = carry;
+    total[1] = carry_q;
+  }
 }
 
 __global__ void __launch_bounds__(1024) compact_scatter(vgpr_map M, const uint32_t* __restrict__ flag,
                                                         const int32_t* __restrict__ ids, int64_t n,
                                                         const uint32_t* __restrict__ block_base,
+                                                        const uint32_t* __restrict__ block_pts,
                                                         uint64_t* __restrict__ ukey, int32_t* __restrict__ uoff,
                                                         int32_t* __restrict__ ucnt, int32_t* __restrict__ uid,
-                                                        int32_t* __restrict__ ufv) {
+                                                        int32_t* __restrict__ ufv, int32_t* __restrict__ upts) {
   __shared__ uint32_t smem[17];
   const int64_t i = (int64_t)blockIdx.x * kCompactTile + threadIdx.x;
   const uint32_t f = i < n ? flag[i] : 0u;
   uint32_t tot;
   const uint32_t ex = block_exclusive_sum<1024>(f, smem, &tot);
+  const uint32_t ex_q = block_exclusive_sum<1024>(pooled_of(M, ids, flag, i, n), smem, &tot);
   if (f) {
     const uint32_t slot = block_base[blockIdx.x] + ex;
     const int id = ids[i];
@@ -217,7 +243,25 @@ __global__ void __launch_bounds__(1024) compact_scatter(vgpr_map M, const uint32
     ucnt[slot] = M.vtotal[id];
     uid[slot] = id;
     ufv[slot] = (int32_t)i;
+    upts[slot] = (int32_t)(block_pts[blockIdx.x] + ex_q);
   }
+}
+
+// Update mode 0: one wavefront per re-solved voxel u copies its pooled points
+// to [upts[u], upts[u] + stored) of the staging area, back to back, so that the
+// solve's point scratch scales with the update, not with the map's capacity.
+__global__ void __launch_bounds__(256) gather_pool_kernel(vgpr_map M, const int32_t* __restrict__ uid,
+                                                          const int32_t* __restrict__ upts, int64_t nu,
+                                                          float* __restrict__ sxyz, int32_t* __restrict__ soff) {
+  const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (u >= nu) return;
+  const int lane = lane_id();
+  const int id = uid[u];
+  const int k = M.vstored[id];
+  const int64_t o = upts[u];
+  const float* src = M.pool + (size_t)id * M.params.max_pts * 3;
+  for (int t = lane; t < 3 * k; t += 64) sxyz[3 * o + t] = src[t];
+  if (lane == 0) soff[u] = (int32_t)o;
 }
 
 __global__ void __launch_bounds__(256) state_kernel(vgpr_map M, const int32_t* __restrict__ uid,
@@ -498,12 +542,12 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
     return r;
   };
   const size_t o_k = sub(8 * n), o_o = sub(4 * n), o_c = sub(4 * n), o_p = sub(4 * n), o_f = sub(4 * n),
-               o_id = sub(4 * n), o_bs = sub(4 * nblk + 64), o_uk = sub(8 * n), o_uo = sub(4 * n), o_uc = sub(4 * n),
-               o_ui = sub(4 * n), o_fv = sub(4 * n), o_tot = sub(64);
+               o_id = sub(4 * n), o_bs = sub(4 * nblk + 64), o_bq = sub(4 * nblk + 64), o_uk = sub(8 * n),
+               o_uo = sub(4 * n), o_uc = sub(4 * n), o_ui = sub(4 * n), o_fv = sub(4 * n), o_up = sub(4 * n),
+               o_tot = sub(64);
   head = (head + 255) & ~size_t(255);
-  // update mode 1 solves from the map's own staging area (sized once the update count is known)
-  const size_t fit_bytes = M->mode == 1 ? 0 : fit_work_bytes(ctx, n, M->max_voxels * (int64_t)p.max_pts, &p);
-  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + fit_bytes + (1 << 20));
+  // the solve runs from the map's own staging area, sized once the update is known
+  vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + (1 << 20));
   if (st != VGPR_OK) return st;
   char* w = static_cast<char*>(ctx->work.ptr);
   uint64_t* fkeys = reinterpret_cast<uint64_t*>(w + o_k);
@@ -513,11 +557,13 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   uint32_t* flag = reinterpret_cast<uint32_t*>(w + o_f);
   int32_t* ids = reinterpret_cast<int32_t*>(w + o_id);
   uint32_t* bsum = reinterpret_cast<uint32_t*>(w + o_bs);
+  uint32_t* bpts = reinterpret_cast<uint32_t*>(w + o_bq);
   uint64_t* ukey = reinterpret_cast<uint64_t*>(w + o_uk);
   int32_t* uoff = reinterpret_cast<int32_t*>(w + o_uo);
   int32_t* ucnt = reinterpret_cast<int32_t*>(w + o_uc);
   int32_t* uid = reinterpret_cast<int32_t*>(w + o_ui);
   int32_t* ufv = reinterpret_cast<int32_t*>(w + o_fv);
+  int32_t* upts = reinterpret_cast<int32_t*>(w + o_up);
   unsigned long long* dtot = reinterpret_cast<unsigned long long*>(w + o_tot);
 
   int64_t nv = 0;
@@ -547,19 +593,33 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   const int64_t nvb = (nv + kCompactTile - 1) / kCompactTile;
   hipLaunchKernelGGL(insert_kernel, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, ctx->stream, *M, d_xyz, fkeys,
                      foff, fcnt, fperm, nv, p.max_pts, p.min_pts, flag, ids);
-  hipLaunchKernelGGL(compact_reduce, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, flag, nv, bsum);
-  hipLaunchKernelGGL(compact_scan, dim3(1), dim3(1024), 0, ctx->stream, bsum, (int)nvb, dtot);
-  hipLaunchKernelGGL(compact_scatter, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, *M, flag, ids, nv, bsum, ukey,
-                     uoff, ucnt, uid, ufv);
+  hipLaunchKernelGGL(compact_reduce, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, *M, flag, ids, nv, bsum, bpts);
+  hipLaunchKernelGGL(compact_scan, dim3(1), dim3(1024), 0, ctx->stream, bsum, bpts, (int)nvb, dtot);
+  hipLaunchKernelGGL(compact_scatter, dim3((unsigned)nvb), dim3(1024), 0, ctx->stream, *M, flag, ids, nv, bsum, bpts,
+                     ukey, uoff, ucnt, uid, ufv, upts);
   VGPR_HIP(ctx, hipGetLastError());
-  VGPR_HIP(ctx, hipMemcpyAsync(hc, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
-  VGPR_HIP(ctx, hipMemcpyAsync(hc + 1, M->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipMemcpyAsync(hc, dtot, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  VGPR_HIP(ctx, hipMemcpyAsync(hc + 2, M->counters, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  M->host_voxels = (int64_t)hc[1];
+  M->host_voxels = (int64_t)hc[2];
   const int64_t nu = (int64_t)hc[0];
+  const int64_t pooled = (int64_t)hc[1];  // pooled points of all nu entries (an upper bound for the first nout)
   *h_n_upd = nu;
   if (nu == 0) return VGPR_OK;
   const int64_t nout = nu < cap_upd ? nu : cap_upd;
+  // the map's staging area holds the solve's inputs and scratch; it grows to the
+  // largest update seen and is reused after that
+  auto stage_for = [&](size_t need) -> vgpr_status {
+    if (need <= M->stage_bytes) return VGPR_OK;
+    VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the previous frame's solve may still read it
+    if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
+    M->stage = nullptr;
+    M->stage_bytes = 0;
+    vgpr_status s2 = alloc_owned(ctx, &M->stage, need + need / 4);
+    if (s2 != VGPR_OK) return s2;
+    M->stage_bytes = need + need / 4;
+    return VGPR_OK;
+  };
   if (nout > 0 && M->mode == 1) {
     VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
     const int m = p.grid_side * p.grid_side;
@@ -577,16 +637,8 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
     };
     const size_t s_xyz = take(12 * (size_t)npts), s_nz = take(4 * (size_t)npts), s_off = take(4 * (size_t)nout),
                  s_cnt = take(4 * (size_t)nout), s_cap = take((size_t)nout), s_fit = take(fit_work_bytes(ctx, nout, npts, &pf));
-    const size_t need = (so + 255) & ~size_t(255);
-    if (need > M->stage_bytes) {
-      VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the previous frame's solve may still read it
-      if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
-      M->stage = nullptr;
-      M->stage_bytes = 0;
-      st = alloc_owned(ctx, &M->stage, need + need / 4);
-      if (st != VGPR_OK) return st;
-      M->stage_bytes = need + need / 4;
-    }
+    st = stage_for((so + 255) & ~size_t(255));
+    if (st != VGPR_OK) return st;
     char* sb = static_cast<char*>(M->stage);
     float* sxyz = reinterpret_cast<float*>(sb + s_xyz);
     float* snz = reinterpret_cast<float*>(sb + s_nz);
@@ -604,9 +656,27 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
     VGPR_HIP(ctx, hipGetLastError());
   } else if (nout > 0) {
     VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
-    FitArgs a{M->pool, M->max_voxels * (int64_t)p.max_pts, ukey, uoff, ucnt, nullptr, nullptr, nout, d_out, d_axis,
-              d_status};
-    st = fit_predict_impl(ctx, a, &p, head);
+    // the re-solved voxels' pooled points back to back (counts stay the totals, for CAPPED)
+    const int64_t npts = pooled > 0 ? pooled : 1;
+    size_t so = 0;
+    auto take = [&](size_t bytes) {
+      so = (so + 255) & ~size_t(255);
+      size_t r = so;
+      so += bytes;
+      return r;
+    };
+    const size_t s_xyz = take(12 * (size_t)npts), s_off = take(4 * (size_t)nout),
+                 s_fit = take(fit_work_bytes(ctx, nout, npts, &p));
+    st = stage_for((so + 255) & ~size_t(255));
+    if (st != VGPR_OK) return st;
+    char* sb = static_cast<char*>(M->stage);
+    float* sxyz = reinterpret_cast<float*>(sb + s_xyz);
+    int32_t* soff = reinterpret_cast<int32_t*>(sb + s_off);
+    hipLaunchKernelGGL(gather_pool_kernel, dim3((unsigned)((nout + 3) / 4)), dim3(256), 0, ctx->stream, *M, uid, upts,
+                       nout, sxyz, soff);
+    VGPR_HIP(ctx, hipGetLastError());
+    FitArgs a{sxyz, npts, ukey, soff, ucnt, nullptr, nullptr, nout, d_out, d_axis, d_status};
+    st = fit_predict_impl(ctx, a, &p, 0, sb + s_fit);
     if (st != VGPR_OK) return st;
     hipLaunchKernelGGL(state_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, ctx->stream, *M, uid,
                        d_status, nout);

@@ -736,6 +736,36 @@ def test_map_capacity_rejects_frame(env):
     assert gm.stats()["voxels"] == 0
 
 
+def test_map_update_scratch_scales_with_the_update(env):
+    """A 2M-voxel map (48 points a voxel: about 1.25 GB of pool and table) updated
+    with a small frame under a 2 GB context budget: the solve stages only the
+    re-solved voxels' points, so the update fits (a point scratch sized by the
+    map's capacity, 16 B x 96M slots, would exceed the budget), and its output
+    agrees with the oracle's map on two frames."""
+    torch, vgpr, _ = env
+    w = dict(configs.params_for("paper_stream"), max_pts=48)
+    prm = parity.oracle_params(w)
+    p = parity.gpu_params(vgpr, w)
+    big = vgpr.Context(0, hbm_budget=2 << 30)
+    gm = vgpr.Map(big, p, max_voxels=2_000_000)
+    held_map = big.workspace_bytes()  # device bytes the context holds: the map's own so far
+    om = O.VoxelMap(prm)
+    n_solved = 0
+    for k in range(2):
+        xyz = synth.spin_scan(synth.frame_seed(7, 3 + k), n_beams=32, n_az=1024, position=(0.2 * k, 0.0))
+        say("map update scratch, frame", k, len(xyz))
+        keys, out, axis, status = gm.update(dev(torch, xyz))
+        ref = om.update(xyz)
+        _, _, n_cmp = _compare_map_frame(ref, keys, out, axis, status, prm.signal_var, prm.converge_var)
+        solved = int(((ref["status"] & O.ST_SOLVED) != 0).sum())
+        assert n_cmp >= 0.9 * solved
+        n_solved += solved
+    assert n_solved > 0
+    assert big.workspace_bytes() - held_map < (256 << 20)  # the updates' scratch and staging
+    gm.close()
+    big.close()
+
+
 def test_budget_exhaustion(env):
     torch, vgpr, _ = env
     small = vgpr.Context(0, hbm_budget=1 << 16)
