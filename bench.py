@@ -770,6 +770,9 @@ def serve_leg(args, vgpr) -> dict:
                      m=p.grid_side ** 2)
     out = st.summary()
     out["arrivals"] = "sensors phase-shifted by 1/80 s"
+    # held for good by the eight contexts (scratch, map staging, maps), beside the
+    # per-frame admission estimate of the frames in flight (max_inflight_bytes)
+    out["device_bytes_held"] = be.device_bytes()
     be.close()
     # the same streams with every sensor ticking at the same instant (synchronised sensors):
     # eight frames arrive together each 100 ms, so admission and device overlap are exercised

@@ -150,8 +150,8 @@ VGPR_API vgpr_status vgpr_set_stream(vgpr_ctx* ctx, void* hip_stream);
 /* Message of the last failed call on this context (static until the next call);
  * with ctx = NULL, why the calling thread's last vgpr_create failed. */
 VGPR_API const char* vgpr_last_error(const vgpr_ctx* ctx);
-/* Device bytes the context currently holds: its scratch plus the maps created
- * on it (with their staging areas). */
+/* Device bytes the context currently holds: its scratch, the staging area of
+ * its maps' updates, and the maps created on it. */
 VGPR_API size_t vgpr_workspace_bytes(const vgpr_ctx* ctx);
 
 /*
@@ -250,12 +250,13 @@ VGPR_API vgpr_status vgpr_fit_predict_noalloc(vgpr_ctx* ctx, const float* d_xyz,
  * params.max_pts points stored in arrival order; later points of a full voxel
  * are dropped. The map owns its device memory (about
  * max_voxels * (32 + 12 * max_pts) bytes plus a hash table of
- * 2 * max_voxels 8-byte slots), counted against the context's budget, and
- * a staging area for its updates' solves that grows to the largest update
- * so far: the re-solved voxels' stored points back to back (28 bytes per
- * point with the solver's copy), about 530 bytes per re-solved voxel, and
- * the tiled solvers' fixed scratch when max_pts > 64. An update's scratch
- * therefore scales with the voxels it re-solves, not with max_voxels.
+ * 2 * max_voxels 8-byte slots), counted against the context's budget. Its
+ * updates' solves run from a staging area that the context holds and its
+ * maps share, grown to the largest update so far: the re-solved voxels'
+ * stored points back to back (28 bytes per point with the solver's copy),
+ * about 530 bytes per re-solved voxel, and the tiled solvers' fixed scratch
+ * when max_pts > 64. An update's scratch therefore scales with the voxels it
+ * re-solves, not with max_voxels.
  */
 VGPR_API vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels,
                             vgpr_map** out);
@@ -274,8 +275,8 @@ VGPR_API vgpr_status vgpr_map_create(vgpr_ctx* ctx, const vgpr_params* params, i
  * their max variance <= converge_var. CAPPED then reports that the frame
  * brought more than max_pts points to the voxel. Needs grid_side^2 + max_pts
  * <= 512 and max_voxels * grid_side^2 < 2^31; the map owns an extra
- * max_voxels * (16 m + 1) bytes and a staging area of about
- * 48 (m + max_pts) bytes per re-solved voxel of the largest frame so far.
+ * max_voxels * (16 m + 1) bytes, and its updates take about
+ * 48 (m + max_pts) bytes per re-solved voxel of the context's staging area.
  * Errors: E_INVALID for another update_mode or those limits.
  */
 VGPR_API vgpr_status vgpr_map_create_ex(vgpr_ctx* ctx, const vgpr_params* params, int64_t max_voxels,

@@ -47,27 +47,35 @@ vgpr_status hip_fail(vgpr_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, e == hipErrorOutOfMemory ? VGPR_E_NOMEM : VGPR_E_DEVICE, m);
 }
 
-vgpr_status reserve_work(vgpr_ctx* ctx, size_t bytes) {
-  if (bytes <= ctx->work.bytes) return VGPR_OK;
+namespace {
+vgpr_status reserve_buffer(vgpr_ctx* ctx, DeviceBuffer& buf, size_t bytes, const char* what) {
+  if (bytes <= buf.bytes) return VGPR_OK;
   size_t want = bytes + bytes / 4;
-  size_t others = ctx->held - ctx->work.bytes;
+  size_t others = ctx->held - buf.bytes;
   if (ctx->budget && others + want > ctx->budget) {
     want = bytes;
     if (others + want > ctx->budget)
       return fail(ctx, VGPR_E_BUDGET,
-                  "scratch of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+                  std::string(what) + " of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
   }
   VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->work.ptr) VGPR_HIP(ctx, hipFree(ctx->work.ptr));
-  ctx->held -= ctx->work.bytes;
-  ctx->work = DeviceBuffer{};
+  if (buf.ptr) VGPR_HIP(ctx, hipFree(buf.ptr));
+  ctx->held -= buf.bytes;
+  buf = DeviceBuffer{};
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
-  ctx->work.ptr = p;
-  ctx->work.bytes = want;
+  if (e != hipSuccess) return hip_fail(ctx, e, &buf == &ctx->stage ? "hipMalloc(map staging)" : "hipMalloc(workspace)");
+  buf.ptr = p;
+  buf.bytes = want;
   ctx->held += want;
   return VGPR_OK;
+}
+}  // namespace
+
+vgpr_status reserve_work(vgpr_ctx* ctx, size_t bytes) { return reserve_buffer(ctx, ctx->work, bytes, "scratch"); }
+
+vgpr_status reserve_stage(vgpr_ctx* ctx, size_t bytes) {
+  return reserve_buffer(ctx, ctx->stage, bytes, "map staging");
 }
 
 vgpr_status reserve_pinned(vgpr_ctx* ctx, size_t bytes) {
@@ -243,6 +251,7 @@ vgpr_status vgpr_destroy(vgpr_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);
+  if (ctx->stage.ptr) (void)hipFree(ctx->stage.ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (auto& kv : ctx->prof)
     for (auto& pr : kv.second.pending) {

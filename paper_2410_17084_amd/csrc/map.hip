@@ -45,8 +45,6 @@ struct vgpr_map {
   int mode = 0;              // 0: re-solve on the stored points; 1: covariance feedback
   float4* pred = nullptr;    // mode 1: m predicted rows (x, y, z, var) per voxel
   uint8_t* vpred = nullptr;  // mode 1: the voxel holds a prediction (it is in the map)
-  void* stage = nullptr;     // the solve's inputs (mode 0: pooled points; mode 1: stacked points, noise) and scratch
-  size_t stage_bytes = 0;
   int64_t host_voxels = 0;   // voxels held, as read back after the last update (host copy)
 };
 
@@ -511,7 +509,6 @@ vgpr_status vgpr_map_destroy(vgpr_map* M) {
   vgpr_ctx* ctx = M->ctx;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
   free_owned(ctx, M->block, M->bytes);
   ctx->live_maps -= 1;
   delete M;
@@ -546,7 +543,7 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
                o_uo = sub(4 * n), o_uc = sub(4 * n), o_ui = sub(4 * n), o_fv = sub(4 * n), o_up = sub(4 * n),
                o_tot = sub(64);
   head = (head + 255) & ~size_t(255);
-  // the solve runs from the map's own staging area, sized once the update is known
+  // the solve runs from the context's staging area, sized once the update is known
   vgpr_status st = reserve_work(ctx, head + 24 * (size_t)n + 4096 * 16 + (1 << 20));
   if (st != VGPR_OK) return st;
   char* w = static_cast<char*>(ctx->work.ptr);
@@ -607,19 +604,6 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
   *h_n_upd = nu;
   if (nu == 0) return VGPR_OK;
   const int64_t nout = nu < cap_upd ? nu : cap_upd;
-  // the map's staging area holds the solve's inputs and scratch; it grows to the
-  // largest update seen and is reused after that
-  auto stage_for = [&](size_t need) -> vgpr_status {
-    if (need <= M->stage_bytes) return VGPR_OK;
-    VGPR_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the previous frame's solve may still read it
-    if (M->stage) free_owned(ctx, M->stage, M->stage_bytes);
-    M->stage = nullptr;
-    M->stage_bytes = 0;
-    vgpr_status s2 = alloc_owned(ctx, &M->stage, need + need / 4);
-    if (s2 != VGPR_OK) return s2;
-    M->stage_bytes = need + need / 4;
-    return VGPR_OK;
-  };
   if (nout > 0 && M->mode == 1) {
     VGPR_HIP(ctx, hipMemcpyAsync(d_upd_keys, ukey, sizeof(uint64_t) * nout, hipMemcpyDeviceToDevice, ctx->stream));
     const int m = p.grid_side * p.grid_side;
@@ -637,9 +621,9 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
     };
     const size_t s_xyz = take(12 * (size_t)npts), s_nz = take(4 * (size_t)npts), s_off = take(4 * (size_t)nout),
                  s_cnt = take(4 * (size_t)nout), s_cap = take((size_t)nout), s_fit = take(fit_work_bytes(ctx, nout, npts, &pf));
-    st = stage_for((so + 255) & ~size_t(255));
+    st = reserve_stage(ctx, (so + 255) & ~size_t(255));
     if (st != VGPR_OK) return st;
-    char* sb = static_cast<char*>(M->stage);
+    char* sb = static_cast<char*>(ctx->stage.ptr);
     float* sxyz = reinterpret_cast<float*>(sb + s_xyz);
     float* snz = reinterpret_cast<float*>(sb + s_nz);
     int32_t* soff = reinterpret_cast<int32_t*>(sb + s_off);
@@ -667,9 +651,9 @@ vgpr_status vgpr_map_update(vgpr_map* M, const float* d_xyz, int64_t n_pts, uint
     };
     const size_t s_xyz = take(12 * (size_t)npts), s_off = take(4 * (size_t)nout),
                  s_fit = take(fit_work_bytes(ctx, nout, npts, &p));
-    st = stage_for((so + 255) & ~size_t(255));
+    st = reserve_stage(ctx, (so + 255) & ~size_t(255));
     if (st != VGPR_OK) return st;
-    char* sb = static_cast<char*>(M->stage);
+    char* sb = static_cast<char*>(ctx->stage.ptr);
     float* sxyz = reinterpret_cast<float*>(sb + s_xyz);
     int32_t* soff = reinterpret_cast<int32_t*>(sb + s_off);
     hipLaunchKernelGGL(gather_pool_kernel, dim3((unsigned)((nout + 3) / 4)), dim3(256), 0, ctx->stream, *M, uid, upts,

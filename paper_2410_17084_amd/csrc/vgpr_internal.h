@@ -56,8 +56,10 @@ struct vgpr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t budget = 0;          // 0 = unlimited
-  size_t held = 0;            // workspace + maps
+  size_t held = 0;            // workspace + staging + maps
   vgpr::DeviceBuffer work;    // per-call scratch, grown on demand
+  vgpr::DeviceBuffer stage;   // map updates' solve inputs and scratch, grown on demand (shared by the
+                              // context's maps: their updates are ordered on `stream`)
   void* pinned = nullptr;     // small pinned host staging area
   size_t pinned_bytes = 0;
   std::string last_error;
@@ -89,6 +91,8 @@ vgpr_status hip_fail(vgpr_ctx* ctx, hipError_t e, const char* what);
 
 // Make sure ctx->work holds at least `bytes`; may synchronise the stream.
 vgpr_status reserve_work(vgpr_ctx* ctx, size_t bytes);
+// Make sure ctx->stage holds at least `bytes`; may synchronise the stream.
+vgpr_status reserve_stage(vgpr_ctx* ctx, size_t bytes);
 // Pinned host staging of at least `bytes`.
 vgpr_status reserve_pinned(vgpr_ctx* ctx, size_t bytes);
 // Device memory owned by something other than the workspace (maps).

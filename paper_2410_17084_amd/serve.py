@@ -71,7 +71,10 @@ def working_set_bytes(n_pts: int, m: int) -> int:
     """Upper estimate of the device bytes one frame update touches besides the map.
 
     Voxelize scratch (~21 B/point), solver scratch (~84 B/voxel) and the output
-    rows (16 m B/voxel) with at most one voxel per point.
+    rows (16 m B/voxel) with at most one voxel per point. What each stream's
+    context holds for good (its scratch and map staging, grown to its largest
+    update, and its map) is not part of this per-frame estimate;
+    `GpuBackend.device_bytes` reports it.
     """
     return int(n_pts * (21 + 84 + 16 * m + 24))
 
@@ -140,6 +143,10 @@ class GpuBackend(Backend):
                 scratch_map.update(f, out=self.outs[s])
             self.streams[s].synchronize()
             scratch_map.close()
+
+    def device_bytes(self) -> int:
+        """Device bytes the streams' contexts hold: scratch, map staging and maps."""
+        return sum(c.workspace_bytes() for c in self.ctxs)
 
     def update(self, stream: int, frame_index: int):
         frames = self.frames[stream]
