@@ -233,6 +233,8 @@ struct Grid {
 // what). A group stops once its bound clears; the wavefront runs until every
 // group has stopped, so every lane takes part in the shuffles.
 constexpr int kGroup = 8;
+static_assert(((2 * kRingMax + 1) * (2 * kRingMax + 1) * (2 * kRingMax + 1) + kGroup - 1) / kGroup <= 64,
+              "a lane's cells of one ring must fit the 64-bit hit mask");
 
 __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pts, int64_t n, Grid g, int has_cand,
                                                     float* __restrict__ val, int32_t* __restrict__ arg,
@@ -266,21 +268,35 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
   bool done = !live;
   for (int r = 0; r <= kRingMax; ++r) {
     if (!done) {
-      // the shell of radius r: cells of the (2r+1)^3 cube with Chebyshev distance r
-      const int side = 2 * r + 1;
-      for (int t = gl; t < side * side * side; t += kGroup) {
+      // the shell of radius r: cells of the (2r+1)^3 cube with Chebyshev distance r. The
+      // lane's cells t = gl + kGroup i go in two passes: first every filter load (independent,
+      // so they overlap) into a mask of possibly occupied cells, then the table and the
+      // Gaussians of those cells only.
+      const int side = 2 * r + 1, nt = side * side * side;
+      auto cell_key = [&](int t, bool* ok) {
         const int dz = t % side - r, dy = (t / side) % side - r, dx = t / (side * side) - r;
-        if (max(max(abs(dx), abs(dy)), abs(dz)) != r) continue;
         const double cx = kx + dx, cy = ky + dy, cz = kz + dz;
-        if (fabs(cx) > lim || fabs(cy) > lim || fabs(cz) > lim) continue;
-        const uint64_t key = ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
-                             ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) |
-                             (uint64_t)((int64_t)cz + kKeyBias);
-        const uint64_t hk = mix64(key);
-        const uint64_t fi = hk >> g.fshift;
-        if (!((g.filter[fi >> 5] >> (fi & 31)) & 1u)) continue;
+        *ok = max(max(abs(dx), abs(dy)), abs(dz)) == r && fabs(cx) <= lim && fabs(cy) <= lim && fabs(cz) <= lim;
+        return *ok ? ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
+                         ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) | (uint64_t)((int64_t)cz + kKeyBias)
+                   : 0ull;
+      };
+      uint64_t hits = 0;  // bit i: cell gl + kGroup i passed the filter (at most 43 cells a lane for r <= 3)
+#pragma unroll 4
+      for (int i = 0; gl + kGroup * i < nt; ++i) {
+        bool ok;
+        const uint64_t key = cell_key(gl + kGroup * i, &ok);
+        const uint64_t fi = mix64(key) >> g.fshift;  // in range for any key
+        const uint32_t word = g.filter[fi >> 5];
+        if (ok && ((word >> (fi & 31)) & 1u)) hits |= 1ull << i;
+      }
+      while (hits) {
+        const int i = __builtin_ctzll(hits);
+        hits &= hits - 1;
+        bool ok;
+        const uint64_t key = cell_key(gl + kGroup * i, &ok);
         int off, cnt;
-        if (!lookup(g.table, g.nslots, key, hk, &off, &cnt)) continue;
+        if (!lookup(g.table, g.nslots, key, mix64(key), &off, &cnt)) continue;
         for (int j = off; j < off + cnt; ++j) take_min(gauss_value(x, y, z, g.G[j]), g.gi[j], &best, &bk);
       }
     }
@@ -401,16 +417,18 @@ __global__ void __launch_bounds__(256) nearest_kernel(const float* __restrict__ 
   unsigned long long cur = seed[o];
   unsigned long long next = 0;  // smallest (bound, chunk) key a round may still take
   for (;;) {
-    const double cv = cur == ~0ull ? (double)INFINITY : (double)float_unorder((uint32_t)(cur >> 32));
+    // box bounds in float: their rounding (a few ulps of the distance) is far inside the margin,
+    // which exceeds 1e-5 (|lb| + |S|) >= 1e-5 x the distance
+    const float cv = cur == ~0ull ? INFINITY : float_unorder((uint32_t)(cur >> 32));
     unsigned long long pick = ~0ull;
     for (int c = lane; c < nchunk; c += 64) {
       const float4 lo = box[2 * c], hi = box[2 * c + 1];
-      const double ex = fmax(fmax((double)lo.x - x, (double)x - hi.x), 0.0);
-      const double ey = fmax(fmax((double)lo.y - y, (double)y - hi.y), 0.0);
-      const double ez = fmax(fmax((double)lo.z - z, (double)z - hi.z), 0.0);
-      const double lb = sqrt(ex * ex + ey * ey + ez * ez) - (double)lo.w;
-      if (lb > cv + 1e-5 * (fabs(lb) + fabs(cv) + fabs((double)lo.w)) + 1e-7) continue;
-      const unsigned long long key = ((unsigned long long)float_order((float)lb) << 32) | (uint32_t)c;
+      const float ex = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.0f);
+      const float ey = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.0f);
+      const float ez = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.0f);
+      const float lb = __fsqrt_rn(ex * ex + ey * ey + ez * ez) - lo.w;
+      if (lb > cv + 1e-5f * (fabsf(lb) + fabsf(cv) + fabsf(lo.w)) + 1e-7f) continue;
+      const unsigned long long key = ((unsigned long long)float_order(lb) << 32) | (uint32_t)c;
       if (key >= next && key < pick) pick = key;
     }
     pick = wave_min_u64(pick);
