@@ -4,12 +4,13 @@
 // attains it (the lowest k among equal values); L_p is their mean over the
 // frame's finite points.
 //
-// Exact search on a uniform grid of cell size h. The Gaussian centres are
-// sorted into cells with the voxelizer (Alg. S1's keys, cells in Morton order
-// so that consecutive Gaussians stay close in space), each cell's range
-// goes into an open-addressing table, and each point visits the cells of
-// growing cubes around its own cell (rings r = 0, 1, ..., eight lanes per
-// point sharing out each ring's cells). Every Gaussian
+// Exact search on a uniform grid of cell size h. The candidates' centres
+// (compacted: rows of unsolved voxels are NaN) are sorted into cells with the
+// voxelizer (Alg. S1's keys, cells in Morton order so that consecutive
+// Gaussians stay close in space), each cell's range goes into an
+// open-addressing table behind an occupancy filter, and each point visits the
+// cells of growing cubes around its own cell (rings r = 0, 1, ..., eight lanes
+// per point sharing out each ring's cells). Every Gaussian
 // outside the cube of radius r lies at least lb_r (the distance from P_j to the
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
