@@ -34,7 +34,7 @@ namespace {
 
 constexpr int kRingMax = 3;
 constexpr int kReduceTile = 1024;
-constexpr int kBruteChunk = 2048;  // consecutive Gaussians (cell order) under one bounding box
+constexpr int kBruteChunk = 1024;  // consecutive Gaussians (cell order) under one bounding box
 
 __device__ __forceinline__ uint32_t float_order(float f) {
   const uint32_t u = __float_as_uint(f);

@@ -160,7 +160,7 @@ def test_loss_open_points_ties_across_chunks(env):
     """Every point is farther from the map than the rings reach, so the exhaustive
     chunk pass decides all of them. Six Gaussians lie at exactly the same value
     from the origin, each in front of a cluster of its own (so they sit in
-    different chunks of 2048), and two pairs of them tie for the points
+    different chunks of 1024), and two pairs of them tie for the points
     (1, 1, 0) and (-1, -1, 0): the lowest index must win whichever chunk is
     visited first."""
     torch, vgpr, ctx = env
