@@ -9,8 +9,8 @@
 // voxelizer (Alg. S1's keys, cells in Morton order so that consecutive
 // Gaussians stay close in space), each cell's range goes into an
 // open-addressing table behind an occupancy filter, and each point visits the
-// cells of growing cubes around its own cell (rings r = 0, 1, ..., eight lanes
-// per point sharing out each ring's cells). Every Gaussian
+// cells of growing cubes around its own cell (the cube of radius 1, then the
+// shells r = 2, 3, eight lanes per point sharing out each pass's cells). Every Gaussian
 // outside the cube of radius r lies at least lb_r (the distance from P_j to the
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
@@ -267,9 +267,12 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
   float best = INFINITY;
   int bk = INT_MAX;
   bool done = !live;
-  for (int r = 0; r <= kRingMax; ++r) {
+  // the first pass takes the whole cube of radius 1 (rings 0 and 1 together: a point's own
+  // cell alone almost never settles it), later passes one shell each
+  for (int r = 1; r <= kRingMax; ++r) {
     if (!done) {
-      // the shell of radius r: cells of the (2r+1)^3 cube with Chebyshev distance r. The
+      // the shell of radius r: cells of the (2r+1)^3 cube with Chebyshev distance r (all 27
+      // cells for r = 1). The
       // lane's cells t = gl + kGroup i go in two passes: first every filter load (independent,
       // so they overlap) into a mask of possibly occupied cells, then the table and the
       // Gaussians of those cells only.
@@ -277,7 +280,8 @@ __global__ void __launch_bounds__(256) query_kernel(const float* __restrict__ pt
       auto cell_key = [&](int t, bool* ok) {
         const int dz = t % side - r, dy = (t / side) % side - r, dx = t / (side * side) - r;
         const double cx = kx + dx, cy = ky + dy, cz = kz + dz;
-        *ok = max(max(abs(dx), abs(dy)), abs(dz)) == r && fabs(cx) <= lim && fabs(cy) <= lim && fabs(cz) <= lim;
+        const int cheb = max(max(abs(dx), abs(dy)), abs(dz));
+        *ok = (cheb == r || r == 1) && fabs(cx) <= lim && fabs(cy) <= lim && fabs(cz) <= lim;
         return *ok ? ((uint64_t)((int64_t)cx + kKeyBias) << (2 * kKeyFieldBits)) |
                          ((uint64_t)((int64_t)cy + kKeyBias) << kKeyFieldBits) | (uint64_t)((int64_t)cz + kKeyBias)
                    : 0ull;
