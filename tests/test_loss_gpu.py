@@ -189,6 +189,32 @@ def test_loss_open_points_ties_across_chunks(env):
         assert arg.cpu().numpy()[:4].tolist() == want
 
 
+def test_loss_degenerate_grid_extents(env):
+    """Gaussian centres whose cell indices span no bits on some axes: all on one
+    horizontal plane (z one cell), all on one line along x (y and z one cell),
+    all in a single cell (no index bits at all), at two cell sizes each; points
+    around them, some far enough to reach the exhaustive pass. The cell keys are
+    then built from fields of unequal width, down to none."""
+    torch, vgpr, ctx = env
+    r = rng(70)
+    n = 3000
+    cases = {
+        "plane": np.c_[r.uniform(-4, 4, (n, 2)), np.full(n, 0.3)],
+        "line": np.c_[r.uniform(-4, 4, n), np.full(n, -1.1), np.full(n, 0.7)],
+        "one cell": r.uniform(0.01, 0.09, (n, 3)),
+    }
+    for name, C in cases.items():
+        G = np.zeros((n, 8), np.float32)
+        G[:, :3] = C
+        G[:, 4:7] = r.uniform(0, 0.004, (n, 3))
+        P = np.concatenate([C[:200] + r.normal(0, 0.05, (200, 3)), r.uniform(-6, 6, (400, 3)),
+                            r.uniform(40, 60, (20, 3))]).astype(np.float32)
+        for cell in (0.1, 0.5):
+            say("loss degenerate extents", name, "cell", cell)
+            loss, nv, value, arg = ctx.structure_loss(dev(torch, P), dev(torch, G), cell_size=cell, scale_mode=0)
+            print(check(P, G, 0, value, arg, loss, nv))
+
+
 def test_loss_argument_errors(env):
     torch, vgpr, ctx = env
     P = dev(torch, np.zeros((4, 3)))
