@@ -488,8 +488,8 @@ def main():
         gctx.close()
         log(f"graph: {graph}")
 
-    # initial 3D Gaussians (Sec. 3.2) from the batch's grids: 8x8 grid as 4x4
-    # subgrids of 2x2 points; HBM-bound (rows read once, 32 B per Gaussian written)
+    # initial 3D Gaussians (Sec. 3.2) from the batch's grids: HBM-bound (the rows of
+    # solved voxels read once, one status byte per voxel, 32 B per Gaussian written)
     gauss = None
     if args.gauss_launches > 0:
         nr = max(1, w["grid_side"] // 4)
@@ -504,7 +504,7 @@ def main():
         gms, gcnt = ctx.profile_read("gauss_init")
         ctx.profile(False)
         per = gms / gcnt / 1e3
-        gbytes = V * m * 16 + V + n_solved * ns * ns * 32 + (V - n_solved) * ns * ns * 32
+        gbytes = n_solved * m * 16 + V + V * ns * ns * 32
         gauss = {"ms_per_launch": per * 1e3, "gaussians_per_launch": int(V * ns * ns), "n_r": nr,
                  "bytes_per_launch": gbytes, "achieved_GBps": gbytes / per / 1e9,
                  "hbm_frac": gbytes / per / 1e9 / HBM_PEAK, "bound": "hbm"}

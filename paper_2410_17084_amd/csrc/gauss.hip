@@ -7,13 +7,19 @@
 // sum, its scale the covariance diagonal, its rotation the identity (not
 // stored). One thread per Gaussian: two passes over the subgrid's rows
 // (mean, then scatter) with double accumulation, so the result does not
-// depend on cancellation in a one-pass formula. The kernel streams the
-// output rows once and writes 32 bytes per Gaussian: it is bound by HBM.
+// depend on cancellation in a one-pass formula. The kernel reads the rows of
+// solved voxels once and the status byte of every voxel, and writes 32 bytes
+// per Gaussian (NaN for voxels that were not solved): it is bound by HBM.
 #include "vgpr_internal.h"
 
 namespace vgpr {
 namespace {
 
+// One thread per Gaussian. NR > 0: subgrids of NR x NR rows, all loaded before
+// any arithmetic and kept in registers (with their weights) for both passes;
+// NR = 0: any n_r, rows loaded as the passes go. The sums run in the same order
+// either way, so both give the same bits.
+template <int NR>
 __global__ void __launch_bounds__(256) gauss_kernel(const float4* __restrict__ rows, const uint8_t* __restrict__ status,
                                                     int64_t n_gauss, int gs, int nr, int ns, float var_floor,
                                                     float4* __restrict__ gauss) {
@@ -32,27 +38,51 @@ __global__ void __launch_bounds__(256) gauss_kernel(const float4* __restrict__ r
   }
   const float4* __restrict__ g = rows + v * gs * gs + (int64_t)(bi * nr) * gs + bj * nr;
   const double fl = (double)var_floor;
-  double sw = 0, sx = 0, sy = 0, sz = 0;
-  for (int i = 0; i < nr; ++i) {
-    for (int j = 0; j < nr; ++j) {
-      const float4 r = g[i * gs + j];
-      const double w = 1.0 / fmax((double)r.w, fl);
-      sw += w;
-      sx += w * (double)r.x;
-      sy += w * (double)r.y;
-      sz += w * (double)r.z;
+  double sw = 0, sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0, px, py, pz;
+  if constexpr (NR > 0) {
+    float4 r[NR * NR];
+    double w[NR * NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+      for (int j = 0; j < NR; ++j) r[i * NR + j] = g[i * gs + j];
+#pragma unroll
+    for (int k = 0; k < NR * NR; ++k) {
+      w[k] = 1.0 / fmax((double)r[k].w, fl);
+      sw += w[k];
+      sx += w[k] * (double)r[k].x;
+      sy += w[k] * (double)r[k].y;
+      sz += w[k] * (double)r[k].z;
     }
-  }
-  const double px = sx / sw, py = sy / sw, pz = sz / sw;
-  double cx = 0, cy = 0, cz = 0;
-  for (int i = 0; i < nr; ++i) {
-    for (int j = 0; j < nr; ++j) {
-      const float4 r = g[i * gs + j];
-      const double w = 1.0 / fmax((double)r.w, fl);
-      const double dx = (double)r.x - px, dy = (double)r.y - py, dz = (double)r.z - pz;
-      cx += w * dx * dx;
-      cy += w * dy * dy;
-      cz += w * dz * dz;
+    px = sx / sw, py = sy / sw, pz = sz / sw;
+#pragma unroll
+    for (int k = 0; k < NR * NR; ++k) {
+      const double dx = (double)r[k].x - px, dy = (double)r[k].y - py, dz = (double)r[k].z - pz;
+      cx += w[k] * dx * dx;
+      cy += w[k] * dy * dy;
+      cz += w[k] * dz * dz;
+    }
+  } else {
+    for (int i = 0; i < nr; ++i) {
+      for (int j = 0; j < nr; ++j) {
+        const float4 r = g[i * gs + j];
+        const double w = 1.0 / fmax((double)r.w, fl);
+        sw += w;
+        sx += w * (double)r.x;
+        sy += w * (double)r.y;
+        sz += w * (double)r.z;
+      }
+    }
+    px = sx / sw, py = sy / sw, pz = sz / sw;
+    for (int i = 0; i < nr; ++i) {
+      for (int j = 0; j < nr; ++j) {
+        const float4 r = g[i * gs + j];
+        const double w = 1.0 / fmax((double)r.w, fl);
+        const double dx = (double)r.x - px, dy = (double)r.y - py, dz = (double)r.z - pz;
+        cx += w * dx * dx;
+        cy += w * dy * dy;
+        cz += w * dz * dz;
+      }
     }
   }
   o[0] = make_float4((float)px, (float)py, (float)pz, (float)sw);
@@ -78,7 +108,12 @@ extern "C" vgpr_status vgpr_gauss_init(vgpr_ctx* ctx, const float* d_out, const 
   const int ns = grid_side / n_r;
   const int64_t n_gauss = n_vox * ns * ns;
   ProfScope ps(ctx, "gauss_init");
-  hipLaunchKernelGGL(gauss_kernel, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, ctx->stream,
+  auto kernel = n_r == 1 ? gauss_kernel<1>
+              : n_r == 2 ? gauss_kernel<2>
+              : n_r == 3 ? gauss_kernel<3>
+              : n_r == 4 ? gauss_kernel<4>
+                         : gauss_kernel<0>;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, ctx->stream,
                      reinterpret_cast<const float4*>(d_out), d_status, n_gauss, grid_side, n_r, ns, var_floor,
                      reinterpret_cast<float4*>(d_gauss));
   VGPR_HIP(ctx, hipGetLastError());
