@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) prepare_kernel(const float4* __restrict__
       c = 1u;
     }
   }
-  // workgroup max and count (a device-wide atomic per wavefront on one address serialised)
+  // per-workgroup slots rather than device-wide atomics (one address per wavefront serialised)
   for (int o = 32; o > 0; o >>= 1) {
     m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
     c += (uint32_t)__shfl_xor((int)c, o, 64);
