@@ -10,7 +10,7 @@
 // Gaussians stay close in space), each cell's range goes into an
 // open-addressing table behind an occupancy filter, and each point visits the
 // cells of growing cubes around its own cell (the cube of radius 1, then the
-// shells r = 2, 3, eight lanes per point sharing out each pass's cells). Every Gaussian
+// shells r = 2, 3, sixteen lanes per point sharing out each pass's cells). Every Gaussian
 // outside the cube of radius r lies at least lb_r (the distance from P_j to the
 // cube's faces) away, so its value is at least lb_r - max_k S_k; once that
 // bound exceeds the best value by a rounding margin no unvisited Gaussian can
@@ -233,7 +233,7 @@ struct Grid {
 // (value, index) order is total, so the result does not depend on who visited
 // what). A group stops once its bound clears; the wavefront runs until every
 // group has stopped, so every lane takes part in the shuffles.
-constexpr int kGroup = 8;
+constexpr int kGroup = 16;
 static_assert(((2 * kRingMax + 1) * (2 * kRingMax + 1) * (2 * kRingMax + 1) + kGroup - 1) / kGroup <= 64,
               "a lane's cells of one ring must fit the 64-bit hit mask");
 
