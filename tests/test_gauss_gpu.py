@@ -1,9 +1,13 @@
 """GPU parity of vgpr_gauss_init (initial 3D Gaussians, Sec. 3.2) against the oracle.
 
 Two comparisons:
-- same inputs: the oracle's gauss_init evaluated on the GPU's own predicted
-  rows; both sides accumulate in double from the same float32 rows, so the
-  float32 outputs agree to a few ulps (rtol 4e-7, atol 1e-12);
+- same inputs: seeded synthetic predicted grids (tilted planes with noise,
+  variances from 1e-9 to 1e-2 so that some fall below the floor, a third of
+  the voxels unsolved with NaN rows) go to both sides; both accumulate in
+  double from the same float32 rows, so the float32 outputs agree to a few
+  ulps (rtol 4e-7, atol 1e-12). Subgrid sizes 1 to 4 take the kernel's
+  register path, 5, 8 and 16 its generic loop; the bench's shape (161,604
+  voxels of 16 x 16, n_r 4) is checked on sampled voxels;
 - end to end (FP64 mode): the oracle's full fit_predict + gauss_init against
   the GPU's. The GPU's FP64 rows differ from the oracle's by at most ~1e-6 m
   in the mean and ~3e-8 in the variance, which moves a weighted position by
@@ -43,27 +47,65 @@ def _fit(env, xyz, w, prec):
     return gv, out, axis, status
 
 
-def _same_inputs(ctx, out, status, gs, nr, floor):
-    g = ctx.gauss_init(out, status, gs, nr, floor).cpu().numpy().astype(np.float64)
-    ref = O.gauss_init(out.cpu().numpy().astype(np.float64), status.cpu().numpy(), gs, nr,
-                       float(np.float32(floor)))
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def synthetic_rows(seed, n_vox, gs, solved_frac=0.67):
+    """Seeded stand-in for predicted grids: per voxel a tilted plane sampled on
+    the gs x gs interval centres of a random square, with noise, and variances
+    spread over seven decades; unsolved voxels get NaN rows."""
+    r = rng(seed)
+    m = gs * gs
+    i, j = np.divmod(np.arange(m), gs)
+    corner = r.uniform(-50, 50, (n_vox, 3))
+    size = r.uniform(0.1, 1.0, (n_vox, 1))
+    u = (i[None] + 0.5) / gs * size
+    w = (j[None] + 0.5) / gs * size
+    slope = r.normal(0, 0.3, (n_vox, 2))
+    out = np.empty((n_vox, m, 4), np.float32)
+    out[:, :, 0] = corner[:, :1] + u
+    out[:, :, 1] = corner[:, 1:2] + w
+    out[:, :, 2] = corner[:, 2:3] + slope[:, :1] * u + slope[:, 1:] * w + r.normal(0, 0.005, (n_vox, m))
+    out[:, :, 3] = 10.0 ** r.uniform(-9, -2, (n_vox, m))
+    status = np.where(r.random(n_vox) < solved_frac, O.ST_SOLVED, O.ST_BELOW_TAU).astype(np.uint8)
+    out[status != O.ST_SOLVED] = np.nan
+    return out, status
+
+
+def _compare(g, ref):
     nan = np.isnan(ref)
     assert np.array_equal(np.isnan(g), nan)
     assert np.allclose(g[~nan], ref[~nan], rtol=4e-7, atol=1e-12)
-    return g, ref
 
 
-@pytest.mark.parametrize("nr", [1, 2, 4, 8])
-def test_gauss_same_inputs_spin32(env, nr):
+@pytest.mark.parametrize("gs,nr", [(8, 1), (8, 2), (9, 3), (16, 4), (10, 5), (8, 8), (16, 16)])
+def test_gauss_same_inputs(env, gs, nr):
     torch, vgpr, ctx = env
-    xyz = synth.spin_scan(synth.frame_seed(2, 6), n_beams=32, n_az=1024)
-    w = configs.params_for("spin32")
-    say("gauss same inputs spin32", nr, len(xyz))
-    gv, out, axis, status = _fit(env, xyz, w, vgpr.PREC_FP32)
-    g, ref = _same_inputs(ctx, out, status, 8, nr, 1e-8)
-    assert g.shape == (gv.n_vox, (8 // nr) ** 2, 8)
-    solved = (status.cpu().numpy() & vgpr.ST_SOLVED) != 0
+    out, status = synthetic_rows(100 + 10 * gs + nr, 3000, gs)
+    say("gauss same inputs", gs, nr)
+    g = ctx.gauss_init(torch.from_numpy(out).cuda(), torch.from_numpy(status).cuda(), gs, nr,
+                       1e-8).cpu().numpy().astype(np.float64)
+    ref = O.gauss_init(out.astype(np.float64), status, gs, nr, float(np.float32(1e-8)))
+    assert g.shape == (3000, (gs // nr) ** 2, 8)
+    _compare(g, ref)
+    solved = status == O.ST_SOLVED
     assert np.isnan(g[~solved]).all() and np.isfinite(g[solved]).all()
+
+
+def test_gauss_full_size_sampled(env):
+    """The bench's shape: 161,604 voxels of 16 x 16 rows, n_r 4 (2.59M Gaussians);
+    2,000 sampled voxels against the oracle, NaN exactly on the unsolved ones."""
+    torch, vgpr, ctx = env
+    out, status = synthetic_rows(200, 161_604, 16, solved_frac=0.46)
+    say("gauss full size", out.shape)
+    g = ctx.gauss_init(torch.from_numpy(out).cuda(), torch.from_numpy(status).cuda(), 16, 4, 1e-8).cpu().numpy()
+    assert g.shape == (161_604, 16, 8)
+    solved = status == O.ST_SOLVED
+    assert np.isnan(g[~solved]).all() and np.isfinite(g[solved]).all()
+    sample = np.sort(rng(201).choice(161_604, 2000, replace=False))
+    ref = O.gauss_init(out[sample].astype(np.float64), status[sample], 16, 4, float(np.float32(1e-8)))
+    _compare(g[sample].astype(np.float64), ref)
 
 
 def test_gauss_paper_grid_end_to_end(env):
@@ -73,7 +115,7 @@ def test_gauss_paper_grid_end_to_end(env):
     w = configs.params_for("paper_stream")
     say("gauss end to end, 9x9 grid, n_r 3", len(xyz))
     gv, out, axis, status = _fit(env, xyz, w, vgpr.PREC_FP64)
-    g, _ = _same_inputs(ctx, out, status, 9, 3, 1e-8)
+    g = ctx.gauss_init(out, status, 9, 3, 1e-8).cpu().numpy().astype(np.float64)
     ov = O.voxelize(xyz, w["voxel_size"])
     prm = parity.oracle_params(w)
     of = O.fit_predict(xyz, ov, prm)
