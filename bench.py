@@ -222,6 +222,34 @@ def cpu_pool(xyz_np: np.ndarray, fo, w: dict, workers: int, timeout_s: float = 2
                       "per worker"}
 
 
+def precision_accuracy(forms: dict, samples: dict) -> None:
+    """CPU-baseline leg, for the precision forms: the oracle's voxelization and FP64
+    fit of each form's sampled voxels, compared with the GPU outputs the precision
+    leg kept; fills in the forms' error fields."""
+    import torch
+
+    from oracle import vgpr_oracle as O
+    from tests import parity
+    xyz_np, fo = samples["xyz"], samples["fo"]
+    for s in (0.2, 0.5, 1.0):
+        w = configs.params_for("batched", voxel_size=s, length_scale=s / 2)
+        ov = O.voxelize(xyz_np, w["voxel_size"], fo)
+        for prec_name in ("fp32", "fp64", "mixed"):
+            V, m, pick, rows, ax, st = samples[(s, prec_name)]
+            out = np.full((V, m, 4), np.nan, np.float32)
+            axis = np.full(V, -1, np.int8)
+            status = np.zeros(V, np.uint8)
+            out[pick], axis[pick], status[pick] = rows, ax, st
+            stats = parity.compare_fit(xyz_np, ov, parity.oracle_params(w), torch.from_numpy(out),
+                                       torch.from_numpy(axis), torch.from_numpy(status), voxels=pick, strict=False)
+            forms[f"s={s:g}"][prec_name].update({
+                "max_mean_err_m": stats["max_mean_err"], "max_var_err_prior": stats["max_var_err"],
+                "max_var_rel_own": stats["max_var_rel_own"],
+                "sample_voxels_outside_tolerance": stats["outside_tolerance"],
+                "within_tolerance": stats["outside_tolerance"] == 0})
+            log(f"precision form s={s} {prec_name} accuracy: {forms[f's={s:g}'][prec_name]}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -593,7 +621,12 @@ def main():
             if name != args.workload:
                 extra[name] = extra_leg(args, vgpr, name)
                 log(f"{name}: {extra[name]}")
-    forms = precision_leg(args, vgpr) if args.precision_forms else None
+    forms = None
+    if args.precision_forms:
+        forms, fsamples = precision_leg(args, vgpr)
+        if not args.no_cpu_baseline:
+            precision_accuracy(forms, fsamples)
+        del fsamples
     rec = {
         "metric": "voxel GPR solves/s (dense pts/s, p50/p99 frame latency) at fixed accuracy",
         "value": value, "unit": "voxel solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -679,17 +712,16 @@ def extra_leg(args, vgpr, name: str) -> dict:
             "arithmetic": sp["label"], "workload": WORKLOAD_DESC[name]}
 
 
-def precision_leg(args, vgpr) -> dict:
+def precision_leg(args, vgpr) -> tuple:
     """The three arithmetic forms on the batched workload (128-beam and rosette scans, cap 256,
     8x8 grid) at voxel sizes 0.2, 0.5 and 1.0 m (length scale half a voxel): solves/s of
-    voxelize + fit_predict per step under each form's cached launch choices, and the largest
-    error of each output against the FP64 oracle on a seeded sample of voxels (every voxel
-    above 128 points, every refined voxel up to 100, and 150 others)."""
+    voxelize + fit_predict per step under each form's cached launch choices. Returns the
+    forms and the GPU outputs of a seeded sample of voxels (every voxel above 128 points,
+    every refined voxel up to 100, and 150 others), whose largest errors against the FP64
+    oracle the CPU-baseline leg fills in (`precision_accuracy`)."""
     import torch
 
-    from oracle import vgpr_oracle as O
     from paper_2410_17084_amd import autotune
-    from tests import parity
     frames = 16
     xyz_np, fo = workload_frames("batched", frames)
     xyz = torch.from_numpy(xyz_np).cuda()
@@ -699,10 +731,10 @@ def precision_leg(args, vgpr) -> dict:
                    "grid, l = s/2; errors: max |mean - oracle| (m), max |var - oracle| / s_f^2, max "
                    "|var - oracle| / oracle, on a seeded sample"}
     rng = np.random.Generator(np.random.PCG64(2024))
+    samples = {"xyz": xyz_np, "fo": fo}
     for s in (0.2, 0.5, 1.0):
         w = configs.params_for("batched", voxel_size=s, length_scale=s / 2)
         m = w["grid_side"] ** 2
-        ov = O.voxelize(xyz_np, w["voxel_size"], fo)
         row = {}
         for prec_name, prec in (("fp32", vgpr.PREC_FP32), ("fp64", vgpr.PREC_FP64), ("mixed", vgpr.PREC_MIXED)):
             p = vgpr.default_params(**{k: v for k, v in w.items() if k in {f for f, _ in vgpr.Params._fields_}})
@@ -733,20 +765,21 @@ def precision_leg(args, vgpr) -> dict:
             refd = np.flatnonzero(solved & ((st & vgpr.ST_REFINED) != 0))[:100]
             rest = np.flatnonzero(solved)
             pick = np.union1d(np.union1d(big, refd), rng.choice(rest, size=min(150, len(rest)), replace=False))
-            stats = parity.compare_fit(xyz_np, ov, parity.oracle_params(w), *res, voxels=pick, strict=False)
+            # the sampled voxels' outputs, checked against the oracle by the CPU-baseline leg
+            samples[(s, prec_name)] = (V, m, pick, res[0][torch.from_numpy(pick).cuda()].cpu().numpy(),
+                                       res[1].cpu().numpy()[pick], st[pick])
             ns = int(solved.sum())
             row[prec_name] = {"solves_per_s": ns / el, "ms_per_step": el * 1e3, "solved_per_step": ns,
                               "refined_per_step": int(((st & vgpr.ST_REFINED) != 0).sum()),
                               "arithmetic": precision_split(np.minimum(cnt, w["max_pts"]), solved, m,
                                                             ctx.tuning().as_dict(), prec_name)["label"],
-                              "sample_voxels": int(len(pick)), "max_mean_err_m": stats["max_mean_err"],
-                              "max_var_err_prior": stats["max_var_err"], "max_var_rel_own": stats["max_var_rel_own"],
-                              "sample_voxels_outside_tolerance": stats["outside_tolerance"],
-                              "within_tolerance": stats["outside_tolerance"] == 0}
+                              "sample_voxels": int(len(pick)), "max_mean_err_m": None, "max_var_err_prior": None,
+                              "max_var_rel_own": None, "sample_voxels_outside_tolerance": None,
+                              "within_tolerance": None}
             ctx.close()
             log(f"precision form s={s} {prec_name}: {row[prec_name]}")
         out[f"s={s:g}"] = row
-    return out
+    return out, samples
 
 
 def serve_leg(args, vgpr) -> dict:
