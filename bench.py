@@ -253,7 +253,7 @@ def precision_accuracy(forms: dict, samples: dict) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["spin32", "batched", "aggregated"], default="aggregated",
                     help="aggregated: 10-scan 128-beam map updates at 0.1 m voxels, cap 512, 16x16 (the default "
