@@ -19,8 +19,10 @@ namespace {
 // any arithmetic and kept in registers (with their weights) for both passes;
 // NR = 0: any n_r, rows loaded as the passes go. The sums run in the same order
 // either way, so both give the same bits.
+constexpr int kGaussThreads = 64;  // one wavefront a workgroup: measured faster than 128 or 256
+
 template <int NR>
-__global__ void __launch_bounds__(256) gauss_kernel(const float4* __restrict__ rows, const uint8_t* __restrict__ status,
+__global__ void __launch_bounds__(kGaussThreads) gauss_kernel(const float4* __restrict__ rows, const uint8_t* __restrict__ status,
                                                     int64_t n_gauss, int gs, int nr, int ns, float var_floor,
                                                     float4* __restrict__ gauss) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,13 +109,15 @@ extern "C" vgpr_status vgpr_gauss_init(vgpr_ctx* ctx, const float* d_out, const 
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VGPR_E_DEVICE, "hipSetDevice");
   const int ns = grid_side / n_r;
   const int64_t n_gauss = n_vox * ns * ns;
+  const int64_t blocks = (n_gauss + kGaussThreads - 1) / kGaussThreads;
+  if (blocks > INT32_MAX) return fail(ctx, VGPR_E_INVALID, "n_vox * (grid_side / n_r)^2 too large for one launch");
   ProfScope ps(ctx, "gauss_init");
   auto kernel = n_r == 1 ? gauss_kernel<1>
               : n_r == 2 ? gauss_kernel<2>
               : n_r == 3 ? gauss_kernel<3>
               : n_r == 4 ? gauss_kernel<4>
                          : gauss_kernel<0>;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kGaussThreads), 0, ctx->stream,
                      reinterpret_cast<const float4*>(d_out), d_status, n_gauss, grid_side, n_r, ns, var_floor,
                      reinterpret_cast<float4*>(d_gauss));
   VGPR_HIP(ctx, hipGetLastError());
